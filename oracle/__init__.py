@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the Brand-update K-factor path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library, its Python
+binding, the serving loop) imports, links or runs anything in this package;
+only the tests, the smoke check and the benchmark's CPU-baseline leg do.  The
+oracle shares no code with the HIP path: the only common module is the seeded
+input generator, which holds none of the method's arithmetic.
+
+Modules
+-------
+bprocess  Oracle-D: the dense definition.  Keeps the d x d B-process iterate
+          (Section 3.2, the B-process equation) and the true exponentially
+          averaged K-factor (Section 2.1 / the EA K-factor process), with a
+          full symmetric eigendecomposition per step.
+brand     Oracle-B: the structured FP64 algorithm the paper states
+          (Algorithm 3, Symmetric Brand, driven as in Algorithm 4, B-KFAC),
+          with a Householder thin QR and a dense eigh of the small core.
+precond   The regularised inverse applied on both sides of a layer gradient:
+          dense Cholesky solves (definition), the low-rank spectral form of
+          Algorithm 1 (its inverse-application lines), the factored form of
+          Algorithm 8, and spectrum continuation (Section 3.5).
+metrics   Basis-invariant comparisons (reconstruction, eigenvalues,
+          orthonormality, preconditioned-gradient error).
+"""
+from .bprocess import DenseFactor, truncate_rank, sorted_eigh  # noqa: F401
+from .brand import BrandFactor, symmetric_brand  # noqa: F401
+from .precond import (precondition_dense, lowrank_inverse_apply, precondition_lowrank,  # noqa: F401
+                      precondition_factored, spectrum_continuation)
+from .metrics import e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S  # noqa: F401

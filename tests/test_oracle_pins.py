@@ -1,0 +1,323 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix (CPU only).
+
+Each test ties the oracle to something other than itself: closed forms of the
+EA recursion, library SVDs / Cholesky solves, eigenvalue interlacing, the
+error recursion and positivity statements of Proposition 3.2, the bounds of
+Propositions 3.1 and 4.2, and brute force on tiny inputs.
+"""
+import numpy as np
+import pytest
+from scipy.linalg import cho_factor, cho_solve
+
+from oracle import (DenseFactor, BrandFactor, symmetric_brand, truncate_rank,
+                    precondition_dense, lowrank_inverse_apply, precondition_lowrank,
+                    precondition_factored, spectrum_continuation,
+                    e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S)
+from paper_2210_08494_amd import synth
+
+
+def _batches(d, n, steps, seed=0, decay=1.0):
+    rng = np.random.default_rng(seed)
+    k = np.arange(1, d + 1, dtype=np.float64)
+    return [rng.standard_normal((d, n)) * (k ** -decay)[:, None] for _ in range(steps)]
+
+
+def _proj(U):
+    return U @ U.T
+
+
+# ----------------------------------------------------------------------------
+# Whole B-update: untruncated exactness against the summed closed form
+# (Section 3.2: E_k = sum_i kappa(i) rho^(k-i) M_i M_i^T, here with the 1/n weight)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("d,n,r,steps", [(64, 8, 56, 8), (16, 2, 14, 8)])
+def test_untruncated_matches_closed_form(d, n, r, steps):
+    rho = 0.9
+    Ms = _batches(d, n, steps, seed=1)
+    dense = DenseFactor(d, r, rho)
+    brand = BrandFactor(d, r, rho)
+    for k, M in enumerate(Ms):
+        dense.update(M)
+        brand.update(M)
+        # closed form, summed directly (not via the recursion)
+        E = np.zeros((d, d))
+        for i in range(k + 1):
+            kappa = 1.0 if i == 0 else (1.0 - rho)
+            E += kappa * rho ** (k - i) * (Ms[i] @ Ms[i].T) / n
+        assert np.linalg.norm(dense.X - E) / np.linalg.norm(E) < 1e-12
+        assert e_rec_dense(brand.U, brand.D, E) < 1e-11
+        assert brand.U.shape[1] == min(k + 1, (d // n)) * n
+        # single-pass projection (as Algorithm 3 writes it) loses ~u*cond(Z_perp)
+        # orthogonality once r + n reaches d
+        assert e_orth(brand.U) < 1e-10
+
+
+def test_first_step_is_svd_of_batch():
+    d, n, r = 40, 6, 4
+    M = _batches(d, n, 1, seed=2)[0]
+    brand = BrandFactor(d, r, 0.95)
+    brand.update(M)
+    Ul, s, _ = np.linalg.svd(M, full_matrices=False)
+    assert np.allclose(brand.D, s ** 2 / n, rtol=1e-12, atol=1e-14 * s[0] ** 2)
+    assert np.allclose(_proj(brand.U), _proj(Ul), atol=1e-12)
+    dense = DenseFactor(d, r, 0.95)
+    dense.update(M)
+    V, lam = dense.modes()
+    assert np.allclose(lam, s ** 2 / n, rtol=1e-10, atol=1e-13 * s[0] ** 2)
+
+
+def test_rho_zero_forgets_history():
+    d, n, r = 30, 5, 3
+    Ms = _batches(d, n, 4, seed=3)
+    brand = BrandFactor(d, r, 0.0)
+    dense = DenseFactor(d, r, 0.0)
+    for M in Ms:
+        brand.update(M)
+        dense.update(M)
+    s = np.linalg.svd(Ms[-1], compute_uv=False)
+    top = np.sort(brand.D)[::-1][:n]
+    assert np.allclose(top, s ** 2 / n, rtol=1e-10, atol=1e-13)
+    assert np.allclose(dense.X, Ms[-1] @ Ms[-1].T / n, atol=1e-14)
+
+
+def test_interlacing_rank_one_update():
+    # n = 1: eigenvalues of rho*B + w m m^T interlace with those of rho*B (Weyl / Cauchy)
+    d, r, rho = 20, 5, 0.9
+    Ms = _batches(d, 1, 12, seed=4)
+    f = BrandFactor(d, r, rho)
+    for k, M in enumerate(Ms):
+        before = np.zeros(d)
+        if k > 0:
+            keep = min(r, f.D.size)
+            before[:keep] = rho * f.D[:keep]
+        f.update(M)
+        after = np.zeros(d)
+        after[:f.D.size] = f.D
+        tol = 1e-12 * max(after[0], 1e-30)
+        assert np.all(after >= before - tol)
+        assert np.all(after[1:] <= before[:-1] + tol)
+
+
+def test_update_inside_span_reduces_core():
+    # Z_perp = 0: the new eigenvalues are those of rho*D + w P P^T (r x r), the rest vanish
+    d, r, n = 50, 6, 3
+    rng = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rng.standard_normal((d, r)))
+    D = np.sort(rng.uniform(1, 5, r))[::-1]
+    C = rng.standard_normal((r, n))
+    A = U @ C
+    U2, D2 = symmetric_brand(U, D, A)
+    small = np.sort(np.linalg.eigvalsh(np.diag(D) + C @ C.T))[::-1]
+    assert np.allclose(D2[:r], small, rtol=1e-12)
+    assert np.all(np.abs(D2[r:]) < 1e-12 * small[0])
+
+
+def test_trace_invariant():
+    d, r, n, rho = 60, 8, 4, 0.95
+    Ms = _batches(d, n, 6, seed=6)
+    f = BrandFactor(d, r, rho)
+    for k, M in enumerate(Ms):
+        if k == 0:
+            expect = np.sum(M * M) / n
+        else:
+            keep = min(r, f.D.size)
+            expect = rho * np.sum(f.D[:keep]) + (1 - rho) / n * np.sum(M * M)
+        f.update(M)
+        assert abs(np.sum(f.D) - expect) < 1e-12 * expect
+
+
+# ----------------------------------------------------------------------------
+# Oracle-B against Oracle-D with truncation biting
+# ----------------------------------------------------------------------------
+def test_structured_matches_dense_with_truncation():
+    d, r, n, rho = 96, 16, 8, 0.95
+    Ms = _batches(d, n, 12, seed=7)
+    dense = DenseFactor(d, r, rho)
+    brand = BrandFactor(d, r, rho)
+    for M in Ms:
+        dense.update(M)
+        brand.update(M)
+        V, lam = dense.modes()
+        assert brand.U.shape[1] == V.shape[1] == dense.kept
+        assert e_rec_dense(brand.U, brand.D, dense.X) < 1e-12
+        assert e_D(brand.D, lam) < 1e-12
+        assert e_rec_lowrank(brand.U, brand.D, V, lam) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Proposition 3.2 (error recursion, positivity), 3.1 (optimality), 4.2 (bound)
+# ----------------------------------------------------------------------------
+def _run_dense(d, r, n, rho, steps, seed):
+    Ms = _batches(d, n, steps, seed=seed, decay=0.5)
+    f = DenseFactor(d, r, rho)
+    hist = []
+    for M in Ms:
+        prevE = None if f.E is None else f.E.copy()
+        f.update(M)
+        hist.append(dict(M=M, E=f.E.copy(), X=f.X.copy(), Bprev=f.B_prev, prevE=prevE,
+                         w=(1.0 / n if len(hist) == 0 else (1 - rho) / n)))
+    return f, hist
+
+
+def test_error_recursion_prop_3_2():
+    # E_k - X_k = rho (E_{k-1} - B_{k-1})  (proof of Proposition 3.2)
+    d, r, n, rho = 40, 5, 4, 0.9
+    f, hist = _run_dense(d, r, n, rho, 10, seed=8)
+    for h in hist[1:]:
+        lhs = h["E"] - h["X"]
+        rhs = rho * (h["prevE"] - h["Bprev"])
+        assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(h["E"])
+
+
+def test_psd_statements_prop_3_2():
+    d, r, n, rho = 40, 5, 4, 0.9
+    f, hist = _run_dense(d, r, n, rho, 10, seed=9)
+    for h in hist:
+        scale = np.linalg.norm(h["E"], 2)
+        assert np.linalg.eigvalsh(h["E"] - h["X"]).min() >= -1e-12 * scale
+        B = truncate_rank(h["X"], r)
+        assert np.linalg.eigvalsh(h["X"] - B).min() >= -1e-12 * scale
+        assert np.linalg.eigvalsh(h["E"] - B).min() >= -1e-12 * scale
+
+
+def _svd_truncate(X, r):
+    U, s, Vt = np.linalg.svd(X)
+    return (U[:, :r] * s[:r]) @ Vt[:r]
+
+
+def test_optimality_prop_3_1():
+    d, r, n, rho = 40, 5, 4, 0.9
+    f, hist = _run_dense(d, r, n, rho, 10, seed=10)
+    for h in hist:
+        E, X = h["E"], h["X"]
+        B = truncate_rank(X, r)
+        for ord_ in ("fro", 2):
+            assert np.linalg.norm(E - B, ord_) >= np.linalg.norm(E - _svd_truncate(E, r), ord_) - 1e-12
+            assert np.linalg.norm(E - X, ord_) >= np.linalg.norm(E - _svd_truncate(E, r + n), ord_) - 1e-12
+
+
+def test_truncation_error_bound_prop_4_2():
+    # || X_k - B_k ||_F <= || w M_k M_k^T ||_F for k >= 1
+    d, r, n, rho = 40, 5, 4, 0.9
+    f, hist = _run_dense(d, r, n, rho, 10, seed=11)
+    for h in hist[1:]:
+        B = truncate_rank(h["X"], r)
+        assert np.linalg.norm(h["X"] - B) <= np.linalg.norm(h["w"] * h["M"] @ h["M"].T) * (1 + 1e-12)
+
+
+def test_truncation_is_optimal_bruteforce():
+    # Eckart-Young by brute force on a tiny matrix: no sampled rank-r PSD matrix beats it,
+    # and the error equals the discarded singular values (library SVD).
+    rng = np.random.default_rng(12)
+    d, r = 6, 2
+    A = rng.standard_normal((d, d))
+    X = A @ A.T
+    B = truncate_rank(X, r)
+    err = np.linalg.norm(X - B)
+    s = np.linalg.svd(X, compute_uv=False)
+    assert abs(err - np.sqrt(np.sum(s[r:] ** 2))) < 1e-12 * s[0]
+    for _ in range(3000):
+        Y = rng.standard_normal((d, r)) * rng.uniform(0.1, 3)
+        Y = Y @ Y.T
+        assert np.linalg.norm(X - Y) >= err - 1e-12
+    lam, V = np.linalg.eigh(X)
+    Bworst = (V[:, :r] * lam[:r]) @ V[:, :r].T   # smallest modes: must be worse
+    assert np.linalg.norm(X - Bworst) > err
+
+
+# ----------------------------------------------------------------------------
+# Low-rank inverse application (Algorithm 1 inverse lines, Algorithm 8)
+# ----------------------------------------------------------------------------
+def _lowrank(d, N, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((d, N)))
+    D = np.sort(rng.uniform(0.01, 3.0, N))[::-1]
+    return U, D
+
+
+def test_lowrank_inverse_vs_cholesky():
+    d, N, lam = 50, 7, 0.3
+    U, D = _lowrank(d, N, 13)
+    Y = np.random.default_rng(14).standard_normal((d, 5))
+    X = (U * D) @ U.T
+    ref = cho_solve(cho_factor(X + lam * np.eye(d)), Y)
+    assert np.linalg.norm(lowrank_inverse_apply(U, D, lam, Y) - ref) < 1e-12 * np.linalg.norm(ref)
+    # eigen-checks: u_i -> u_i / (D_i + lam); x_perp -> x_perp / lam
+    out = lowrank_inverse_apply(U, D, lam, U)
+    assert np.allclose(out, U / (D + lam)[None, :], atol=1e-13)
+    xp = Y[:, 0] - U @ (U.T @ Y[:, 0])
+    assert np.allclose(lowrank_inverse_apply(U, D, lam, xp[:, None])[:, 0], xp / lam, atol=1e-12)
+
+
+def test_two_sided_lowrank_vs_dense():
+    dG, dA, NG, NA = 30, 40, 6, 9
+    UG, DG = _lowrank(dG, NG, 15)
+    UA, DA = _lowrank(dA, NA, 16)
+    J = np.random.default_rng(17).standard_normal((dG, dA))
+    XG, XA = (UG * DG) @ UG.T, (UA * DA) @ UA.T
+    S_ref = precondition_dense(XG, XA, J, 0.1, 0.2)
+    # independent check of the dense definition: explicit inverses
+    S_inv = np.linalg.inv(XG + 0.1 * np.eye(dG)) @ J @ np.linalg.inv(XA + 0.2 * np.eye(dA))
+    assert e_S(S_ref, S_inv) < 1e-12
+    assert e_S(precondition_lowrank(UG, DG, UA, DA, J, 0.1, 0.2), S_ref) < 1e-12
+
+
+def test_factored_apply_identity():
+    # Algorithm 8 on (G_k, A_k) equals the two-sided apply of J = G_k A_k^T
+    dG, dA, N, n = 30, 40, 6, 5
+    UG, DG = _lowrank(dG, N, 18)
+    UA, DA = _lowrank(dA, N, 19)
+    rng = np.random.default_rng(20)
+    Gk, Ak = rng.standard_normal((dG, n)), rng.standard_normal((dA, n))
+    S1 = precondition_factored(UG, DG, UA, DA, Gk, Ak, 0.05, 0.07)
+    S2 = precondition_lowrank(UG, DG, UA, DA, Gk @ Ak.T, 0.05, 0.07)
+    assert e_S(S1, S2) < 1e-12
+
+
+def test_spectrum_continuation():
+    d, N, lam = 25, 5, 0.1
+    U, D = _lowrank(d, N, 21)
+    D2, lam2 = spectrum_continuation(D, lam)
+    m = D.min()
+    assert lam2 == pytest.approx(lam + m) and D2.min() == 0.0
+    # the continued operator has eigenvalue D_i + lam on U and (m + lam) on the complement
+    Xc = (U * D2) @ U.T + lam2 * np.eye(d)
+    ev = np.sort(np.linalg.eigvalsh(Xc))
+    expect = np.sort(np.concatenate([D + lam, np.full(d - N, m + lam)]))
+    assert np.allclose(ev, expect, atol=1e-12)
+    Y = np.random.default_rng(22).standard_normal((d, 3))
+    assert np.allclose(lowrank_inverse_apply(U, D2, lam2, Y), np.linalg.solve(Xc, Y), atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Metrics and generator
+# ----------------------------------------------------------------------------
+def test_lowrank_metric_equals_dense_metric():
+    d = 40
+    U1, D1 = _lowrank(d, 6, 23)
+    rng = np.random.default_rng(24)
+    U2, _ = np.linalg.qr(U1 + 0.01 * rng.standard_normal(U1.shape))
+    D2 = D1 * (1 + 0.001 * rng.standard_normal(6))
+    X2 = (U2 * D2) @ U2.T
+    assert abs(e_rec_lowrank(U1, D1, U2, D2) - e_rec_dense(U1, D1, X2)) < 1e-12
+    # sign flips / rotations inside the basis do not change it
+    assert e_rec_lowrank(-U1, D1, U1, D1) < 1e-14
+
+
+def test_generator_recipe():
+    a = synth.batch_for(1, 0, "A", 32, 257, bias=True)
+    b = synth.batch_for(1, 0, "A", 32, 257, bias=True)
+    assert a.shape == (32, 257) and np.array_equal(a, b)
+    assert np.all(a[:, -1] == 1.0) and np.all(a >= 0)
+    g = synth.batch_for(1, 0, "G", 32, 256)
+    assert g.shape == (32, 256) and (g < 0).any()
+    # column scale decays like k^-0.7
+    big = synth.output_grads(synth.rng_for(9, 0, 1), 4000, 64)
+    s = big.std(axis=0)
+    k = np.arange(1, 65)
+    assert np.allclose(s * k ** 0.7, 1.0, atol=0.06)
+    G = synth.grad_for(1, 3, 8, 9)
+    assert G.shape == (8, 9)
+    x = np.array([1.0, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, -3.14159])
+    y = synth.to_bf16_values(x)
+    assert y[0] == 1.0 and y[1] == 1.0 and y[2] == 1.0 + 2 ** -7 and abs(y[3] + 3.140625) < 1e-12
