@@ -1,0 +1,161 @@
+/*
+ * kfb — Brand-update K-factor library for MI355X (gfx950).
+ *
+ * One K-factor (the input-side A or output-side Gamma factor of one
+ * fully-connected layer) is held as a low-rank eigen-representation
+ * U diag(D) U^T of its exponentially averaged value (Section 2.1, the EA
+ * K-factor).  kfb_brand_update performs one B-KFAC step on it (Algorithm 4:
+ * truncate to rank r, then the Symmetric Brand update of Algorithm 3 with the
+ * batch scaled by sqrt(w)); kfb_precondition applies the regularised inverses
+ * of the two factors of a layer on both sides of that layer's gradient
+ * (Algorithm 1, its inverse-application lines; Algorithm 8 for the cost).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix arguments are DEVICE pointers unless stated otherwise.
+ *  - Column-major: a d x n batch M has element (i, j) at M[i + j*ldm].  A
+ *    row-major PyTorch tensor of shape [n, d] is exactly this with ldm = d.
+ *  - Row-major: the layer gradient G and the step S are d_out x d_in with
+ *    element (i, j) at G[i*ldg + j] (the PyTorch weight-gradient layout).
+ *  - Memory is owned by the caller.  The library never allocates or frees
+ *    device memory; it records pointers.  kfb_state_bytes / *_workspace_bytes
+ *    give the sizes to allocate (256-byte aligned pointers required).
+ *  - Work is enqueued on the given HIP stream and is asynchronous; inputs must
+ *    stay valid until it completes (the same contract as a PyTorch kernel).
+ *  - A handle is not thread-safe; different handles may be driven from
+ *    different host threads and streams.
+ *  - Return codes are synchronous argument/launch checks.  Numerical events
+ *    (non-finite input, Cholesky breakdown, rank deficiency) are recorded
+ *    asynchronously in a device status word read by kfb_state_status.
+ *
+ * Precision forms
+ *  KFB_FP64        every buffer and operation in FP64.
+ *  KFB_FP32        every buffer and operation in FP32 (plain form).
+ *  KFB_BF16_MIXED  batch M is BF16; U is kept in FP32; projection, residual
+ *                  and rotation products run on BF16 MFMA with FP32
+ *                  accumulation; the CholQR Gram/Cholesky, the core
+ *                  eigensolve and D are FP64.  G and S are FP32.
+ */
+#ifndef KFB_H
+#define KFB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kfb_state_s* kfb_state_t;
+typedef void* kfb_stream_t; /* a hipStream_t; NULL = the default stream */
+
+enum kfb_precision { KFB_FP64 = 0, KFB_FP32 = 1, KFB_BF16_MIXED = 2 };
+
+enum kfb_status_code {
+  KFB_OK = 0,
+  KFB_EINVAL = 1,     /* null pointer, bad size, ld < d, n > n_max, r + n_max > d */
+  KFB_EWORKSPACE = 2, /* workspace smaller than required */
+  KFB_EHIP = 3,       /* a HIP runtime call failed */
+  KFB_ESTATE = 4,     /* states incompatible with the call (widths, precision, same handle) */
+  KFB_EEMPTY = 5      /* the state holds no modes yet */
+};
+
+/* kfb_precondition flags */
+enum kfb_flags {
+  KFB_SPECTRUM_CONTINUATION = 1, /* Section 3.5: lam += min(D), D -= min(D) per factor */
+  KFB_TRUNCATE_AFTER = 2         /* apply with the leading r modes only (default: all r+n) */
+};
+
+/* bits of the device status word */
+enum kfb_event {
+  KFB_EV_NONFINITE = 1u,       /* a non-finite value reached the Gram of the residual */
+  KFB_EV_CHOL_DEFICIENT = 2u,  /* a CholQR pivot was below tolerance: null directions dropped */
+  KFB_EV_JACOBI_MAXSWEEPS = 4u /* the core eigensolver hit its sweep limit */
+};
+
+/* Bytes of the state buffer for a factor of width d, truncation rank r and
+ * batch capacity n_max: two U buffers (d x (r+n_max), front/back) and two
+ * eigenvalue vectors, plus a status word.  Returns 0 on invalid sizes. */
+size_t kfb_state_bytes(int64_t d, int32_t r, int32_t n_max, int32_t prec);
+
+/* Create a handle over a caller-owned state buffer of kfb_state_bytes bytes.
+ * rho is the EA decay (Section 2.1).  The state starts empty (no modes); the
+ * first update uses batch weight 1/n, later ones (1 - rho)/n.
+ * Requires 1 <= n_max, 0 <= r, r + n_max <= d (Brand needs r + n <= d). */
+int kfb_state_create(kfb_state_t* out, int64_t d, int32_t r, int32_t n_max, double rho,
+                     int32_t prec, void* state_buf, size_t state_bytes, kfb_stream_t stream);
+
+/* Free the host-side handle (the caller frees the buffers it owns). */
+int kfb_destroy(kfb_state_t st);
+
+/* Workspace bytes for one kfb_brand_update on this state with batch width n. */
+size_t kfb_update_workspace_bytes(kfb_state_t st, int32_t n);
+
+/* One B-KFAC step (Algorithm 4) on one factor:
+ *   truncate (U, D) to min(k_valid, r) modes, then
+ *   U diag(D) U^T <- rho U diag(D) U^T + w M M^T   exactly (Algorithm 3),
+ * with w = 1/n for the first update and (1 - rho)/n afterwards.
+ * M: d x n column-major (ldm >= d); FP64 / FP32 / BF16 per the precision form.
+ * After the call the state holds k_valid = min(k_valid, r) + n modes. */
+int kfb_brand_update(kfb_state_t st, const void* M, int64_t ldm, int32_t n, void* workspace,
+                     size_t ws_bytes, kfb_stream_t stream);
+
+/* Grouped form: `count` independent updates in one set of launches.  All
+ * states must share d, r, precision and current k_valid, and all batches the
+ * same n and ldm (one shape bucket); results equal `count` separate calls. */
+size_t kfb_update_batched_workspace_bytes(int32_t count, kfb_state_t const* states, int32_t n);
+int kfb_brand_update_batched(int32_t count, kfb_state_t const* states, const void* const* Ms,
+                             int64_t ldm, int32_t n, void* workspace, size_t ws_bytes,
+                             kfb_stream_t stream);
+
+/* Workspace bytes for kfb_precondition on this pair of states. */
+size_t kfb_precondition_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a);
+
+/* Two-sided regularised inverse (Section 2.1, Algorithm 1 inverse lines):
+ *   S = (U_G D_G U_G^T + lam_gamma I)^{-1} G (U_A D_A U_A^T + lam_a I)^{-1}
+ * with G, S row-major d_out x d_in, d_out = st_gamma's d and d_in = st_a's d.
+ * lam > 0 absolute.  Uses all k_valid modes (or r with KFB_TRUNCATE_AFTER).
+ * G and S may not alias.  FP64 form: double G/S; FP32 and mixed: float. */
+int kfb_precondition(kfb_state_t st_gamma, kfb_state_t st_a, const void* G, int64_t ldg, void* S,
+                     int64_t lds, double lam_gamma, double lam_a, uint32_t flags, void* workspace,
+                     size_t ws_bytes, kfb_stream_t stream);
+
+/* Grouped form: `count` layers sharing (d_out, d_in, k_valid of each side,
+ * precision, flags); lambdas per layer. */
+size_t kfb_precondition_batched_workspace_bytes(int32_t count, kfb_state_t const* st_gamma,
+                                                kfb_state_t const* st_a);
+int kfb_precondition_batched(int32_t count, kfb_state_t const* st_gamma, kfb_state_t const* st_a,
+                             const void* const* G, int64_t ldg, void* const* S, int64_t lds,
+                             const double* lam_gamma, const double* lam_a, uint32_t flags,
+                             void* workspace, size_t ws_bytes, kfb_stream_t stream);
+
+/* Host-side metadata: modes held, updates applied, sizes. Any pointer may be NULL. */
+int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,
+                   int32_t* n_max, int32_t* prec);
+
+/* Device pointers of the current (front) eigenvectors and eigenvalues:
+ * U is d x k_valid column-major with leading dimension *ldu (FP64 for the
+ * FP64 form, FP32 otherwise); D is k_valid values, descending (FP64, or FP32
+ * in the FP32 form).  Valid until the next update is enqueued. */
+int kfb_state_front(kfb_state_t st, const void** U, int64_t* ldu, const void** D);
+
+/* Overwrite the state with a caller-supplied representation (checkpoint
+ * restore, or seeding from a randomized SVD as the paper does at k = 0).
+ * U (device, same element type as the state, d x k column-major, ld ldu) must
+ * be orthonormal; D (device, same element type as the state's D) descending.
+ * Stream-ordered copy. */
+int kfb_state_load(kfb_state_t st, const void* U, int64_t ldu, const void* D, int32_t k,
+                   int64_t step, kfb_stream_t stream);
+
+/* Read and clear the device status word (synchronises the given stream). */
+int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
+
+const char* kfb_strerror(int code);
+
+/* Library build identification (compiled target, e.g. "gfx950"). */
+const char* kfb_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFB_H */

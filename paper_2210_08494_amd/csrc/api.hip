@@ -1,0 +1,593 @@
+// C-ABI of the kfb library: state lifecycle, the Brand update (Algorithm 4 on
+// top of Algorithm 3) and the two-sided inverse application (Algorithm 1
+// inverse lines), as stream-ordered sequences of the stage kernels.
+#include <string.h>
+#include <stdlib.h>
+#include <new>
+
+#include "kfb_kernels.h"
+
+using namespace kfb;
+
+struct kfb_state_s {
+  int64_t d = 0;
+  int32_t r = 0, n_max = 0, prec = 0;
+  double rho = 0.0;
+  char* buf = nullptr;
+  size_t bytes = 0;
+  int64_t ldu = 0;
+  size_t off_U[2] = {0, 0}, off_D[2] = {0, 0}, off_status = 0;
+  int front = 0;
+  int32_t k_valid = 0;
+  int64_t step = 0;
+};
+
+namespace {
+
+#define KFB_TRY(x)                                   \
+  do {                                               \
+    hipError_t _e = (x);                             \
+    if (_e != hipSuccess) return KFB_EHIP;           \
+  } while (0)
+
+inline size_t u_elem(int prec) { return prec == KFB_FP64 ? 8 : 4; }
+inline size_t d_elem(int prec) { return prec == KFB_FP32 ? 4 : 8; }
+inline size_t m_elem(int prec) { return prec == KFB_FP64 ? 8 : (prec == KFB_FP32 ? 4 : 2); }
+inline size_t g_elem(int prec) { return prec == KFB_FP64 ? 8 : 4; }
+inline int64_t ldu_for(int64_t d, int prec) {
+  const int64_t q = 256 / (int64_t)u_elem(prec);
+  return ((d + q - 1) / q) * q;
+}
+
+// per-precision element types
+template <int PR> struct Ty;
+template <> struct Ty<KFB_FP64> {
+  typedef double U, M, Z, P, G, Core, W, D, Acc;
+};
+template <> struct Ty<KFB_FP32> {
+  typedef float U, M, Z, P, G, Core, W, D, Acc;
+};
+template <> struct Ty<KFB_BF16_MIXED> {
+  typedef float U, Z, P, W, Acc;
+  typedef bf16 M;
+  typedef double G, Core, D;
+};
+
+constexpr int MAX_SWEEPS = 24;
+
+// ---------------------------------------------------------------------------
+// Brand-update plan: workspace layout of one problem for a shape bucket.
+// ---------------------------------------------------------------------------
+struct UpdPlan {
+  int64_t d, ldu, ldm;
+  int r, n, N, Np, bw;
+  int ksP, ksG;
+  int64_t oZ, oZb, oP, oP2, oGram, oR1, oX1, oR2, oX2, oRt, oPart, oB, oV, oW, oLam, oRank, oCnt;
+  size_t per_problem;
+};
+
+template <int PR>
+bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, UpdPlan* p) {
+  typedef Ty<PR> T;
+  p->d = d; p->ldu = ldu; p->ldm = ldm; p->r = r; p->n = n; p->N = r + n;
+  p->bw = jacobi_pick_block(p->N, (int)sizeof(typename T::Core), &p->Np);
+  if (p->bw == 0) return false;
+  auto ks_for = [&](int m, int nn, int64_t k) {
+    // split depends on the problem's own shape only, never on its batch-mates
+    const int tiles = ((m + 63) / 64) * ((nn + 63) / 64);
+    int ks = 1;
+    while (tiles * ks < 512 && (k / (ks * 2)) >= 256) ks *= 2;
+    return ks;
+  };
+  p->ksP = r > 0 ? ks_for(r, n, d) : 1;
+  p->ksG = ks_for(n, n, d);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at_ = o; o = align256(o + bytes); return (int64_t)at_; };
+  p->oZ = take((size_t)d * n * sizeof(typename T::Z));
+  p->oZb = take((size_t)d * n * sizeof(typename T::Z));
+  p->oP = take((size_t)(r > 0 ? r : 1) * n * sizeof(typename T::P));
+  p->oP2 = take((size_t)(r > 0 ? r : 1) * n * sizeof(typename T::P));
+  const size_t nn = (size_t)n * n * sizeof(typename T::G);
+  p->oGram = take(nn); p->oR1 = take(nn); p->oX1 = take(nn); p->oR2 = take(nn); p->oX2 = take(nn);
+  p->oRt = take(nn);
+  const size_t partP = (size_t)p->ksP * (r > 0 ? r : 1) * n * sizeof(typename T::P);
+  const size_t partG = (size_t)p->ksG * n * n * sizeof(typename T::G);
+  p->oPart = take(partP > partG ? partP : partG);
+  const size_t core = (size_t)p->Np * p->Np * sizeof(typename T::Core);
+  p->oB = take(core); p->oV = take(core);
+  p->oW = take((size_t)p->N * p->N * sizeof(typename T::W));
+  p->oLam = take((size_t)p->Np * sizeof(typename T::Core));
+  p->oRank = take((size_t)p->Np * 4);
+  p->oCnt = take((size_t)MAX_SWEEPS * 4);
+  p->per_problem = o;
+  return true;
+}
+
+inline OpRef op(int slot, int64_t off, int64_t rs, int64_t cs) {
+  OpRef o;
+  o.slot = slot; o.off = off; o.rs = rs; o.cs = cs;
+  return o;
+}
+
+template <int PR>
+int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::M TM; typedef typename T::Z TZ;
+  typedef typename T::P TP; typedef typename T::G TG; typedef typename T::Core TC;
+  typedef typename T::W TW; typedef typename T::D TD; typedef typename T::Acc TA;
+  const int64_t d = p.d, ldu = p.ldu, ldm = p.ldm;
+  const int r = p.r, n = p.n, N = p.N;
+
+  if (r > 0) {
+    // P = U_r^T M   (Algorithm 3: projection)
+    GemmArgs g;
+    g.A = op(U_FRONT, 0, ldu, 1); g.B = op(M_IN, 0, 1, ldm); g.C = op(WS, p.oP, 1, r);
+    g.m = r; g.n = n; g.k = (int)d; g.ksplit = p.ksP; g.Part = op(WS, p.oPart, 1, r);
+    KFB_TRY((gemm<TU, TM, TP, TP, TP>(drecs, nrec, g, s)));
+    // Z = M - U_r P   (component outside span(U))
+    GemmArgs z;
+    z.A = op(U_FRONT, 0, 1, ldu); z.B = op(WS, p.oP, 1, r); z.C0 = op(M_IN, 0, 1, ldm);
+    z.C = op(WS, p.oZ, 1, d); z.m = (int)d; z.n = n; z.k = r; z.alpha = -1.0; z.beta = 1.0;
+    KFB_TRY((gemm<TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
+    // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
+    GemmArgs g2 = g;
+    g2.B = op(WS, p.oZ, 1, d); g2.C = op(WS, p.oP2, 1, r);
+    KFB_TRY((gemm<TU, TZ, TP, TP, TP>(drecs, nrec, g2, s)));
+    GemmArgs z2 = z;
+    z2.B = op(WS, p.oP2, 1, r); z2.C0 = op(WS, p.oZ, 1, d);
+    KFB_TRY((gemm<TU, TP, TZ, TZ, TA>(drecs, nrec, z2, s)));
+  } else {
+    KFB_TRY((copy2d<TZ, TM>(drecs, nrec, op(WS, p.oZ, 1, d), op(M_IN, 0, 1, ldm), (int)d, n, s)));
+  }
+  // CholeskyQR2 of Z (Algorithm 3: thin QR of the residual)
+  const double tau = PR == KFB_FP32 ? 64.0 * 1.1920929e-07 : 64.0 * 2.220446049250313e-16;
+  int64_t srcZ = p.oZ, dstZ = p.oZb;
+  const int64_t oR[2] = {p.oR1, p.oR2}, oX[2] = {p.oX1, p.oX2};
+  for (int pass = 0; pass < 2; ++pass) {
+    GemmArgs gg;
+    gg.A = op(WS, srcZ, d, 1); gg.B = op(WS, srcZ, 1, d); gg.C = op(WS, p.oGram, 1, n);
+    gg.m = n; gg.n = n; gg.k = (int)d; gg.ksplit = p.ksG; gg.Part = op(WS, p.oPart, 1, n);
+    KFB_TRY((gemm<TZ, TZ, TG, TG, TG>(drecs, nrec, gg, s)));
+    CholArgs ca;
+    ca.n = n; ca.off_gram = p.oGram; ca.off_R = oR[pass]; ca.off_Rinv = oX[pass]; ca.off_rowbuf = 0;
+    ca.tau_rel = tau;
+    KFB_TRY(chol_inv<TG>(drecs, nrec, ca, s));
+    GemmArgs q;
+    q.A = op(WS, srcZ, 1, d); q.B = op(WS, oX[pass], 1, n); q.C = op(WS, dstZ, 1, d);
+    q.m = (int)d; q.n = n; q.k = n;
+    KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
+    const int64_t tmp = srcZ; srcZ = dstZ; dstZ = tmp;
+  }
+  // after two passes Q sits in oZ again; R = R2 R1
+  {
+    GemmArgs rr;
+    rr.A = op(WS, p.oR2, 1, n); rr.B = op(WS, p.oR1, 1, n); rr.C = op(WS, p.oRt, 1, n);
+    rr.m = n; rr.n = n; rr.k = n;
+    KFB_TRY((gemm<TG, TG, TG, TG, TG>(drecs, nrec, rr, s)));
+  }
+  // core square factor and Jacobi eigensolve (Algorithm 3: EVD of M_S)
+  CoreArgs co;
+  co.r = r; co.n = n; co.N = N; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = r > 0 ? p.oP2 : -1;
+  co.off_R = p.oRt; co.off_B = p.oB; co.off_V = p.oV;
+  KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, nrec, co, s)));
+  KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
+  JacArgs ja;
+  ja.Np = p.Np; ja.N = N; ja.b = p.bw; ja.max_sweeps = MAX_SWEEPS;
+  ja.off_B = p.oB; ja.off_V = p.oV; ja.off_cnt = p.oCnt;
+  const double eps = sizeof(TC) == 8 ? 2.220446049250313e-16 : 1.1920929e-07;
+  ja.tol = eps * sqrt((double)N) * (sizeof(TC) == 8 ? 1.0 : 4.0);
+  const int nb = p.Np / p.bw;
+  if (nb == 2) {
+    KFB_TRY(jacobi_round<TC>(drecs, nrec, ja, 0, 0, s));
+  } else {
+    for (int sw = 0; sw < MAX_SWEEPS; ++sw)
+      for (int rd = 0; rd < nb - 1; ++rd) KFB_TRY(jacobi_round<TC>(drecs, nrec, ja, sw, rd, s));
+  }
+  FinArgs fa;
+  fa.N = N; fa.Np = p.Np; fa.max_sweeps = MAX_SWEEPS; fa.off_B = p.oB; fa.off_V = p.oV;
+  fa.off_cnt = p.oCnt; fa.off_lam = p.oLam; fa.off_rank = p.oRank; fa.off_W = p.oW;
+  KFB_TRY((finalize_core<TC, TW, TD>(drecs, nrec, fa, s)));
+  // rotation: U' = [U_r Q] W  (Algorithm 3), into the back buffer
+  GemmArgs ro;
+  ro.A = op(U_FRONT, 0, 1, ldu);
+  ro.A.slot2 = WS; ro.A.off2 = p.oZ; ro.A.rs2 = 1; ro.A.cs2 = d; ro.A.split = r;
+  if (r == 0) ro.A = op(WS, p.oZ, 1, d);
+  ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
+  ro.m = (int)d; ro.n = N; ro.k = N;
+  KFB_TRY((gemm<TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
+  return KFB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner plan (one layer)
+// ---------------------------------------------------------------------------
+struct PrePlan {
+  int64_t dG, dA, lduG, lduA, ldg, lds;
+  int NG, NA, ks3;
+  int64_t oT1, oT2, oT3, oPart, ocG, ocA, oBeta;
+  size_t per_problem;
+};
+
+template <int PR>
+void make_pre_plan(int64_t dG, int64_t dA, int64_t lduG, int64_t lduA, int NG, int NA, int64_t ldg,
+                   int64_t lds, int nrec, PrePlan* p) {
+  typedef typename Ty<PR>::Acc TA;
+  p->dG = dG; p->dA = dA; p->lduG = lduG; p->lduA = lduA; p->NG = NG; p->NA = NA;
+  p->ldg = ldg; p->lds = lds;
+  const int tiles = ((NG + 63) / 64) * ((NA + 63) / 64);  // own shape only
+  int ks = 1;
+  while (tiles * ks < 512 && (dA / (ks * 2)) >= 256) ks *= 2;
+  p->ks3 = ks;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at_ = o; o = align256(o + bytes); return (int64_t)at_; };
+  p->oT1 = take((size_t)NG * dA * sizeof(TA));
+  p->oT2 = take((size_t)dG * NA * sizeof(TA));
+  p->oT3 = take((size_t)NG * NA * sizeof(TA));
+  p->oPart = take((size_t)ks * NG * NA * sizeof(TA));
+  p->ocG = take((size_t)2 * NG * sizeof(TA));
+  p->ocA = take((size_t)2 * NA * sizeof(TA) + 16);
+  p->oBeta = ((p->ocA + (int64_t)2 * NA * (int64_t)sizeof(TA)) + 7) & ~int64_t(7);
+  p->per_problem = o;
+}
+
+template <int PR>
+int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::D TD; typedef typename T::Acc TA;
+  typedef TA TGrad;  // G and S element type (FP64 form: double, else float)
+  const int NG = p.NG, NA = p.NA;
+  const int64_t dG = p.dG, dA = p.dA;
+  CoefArgs ca;
+  ca.kG = NG; ca.kA = NA; ca.off_cG = p.ocG; ca.off_cA = p.ocA; ca.flags = flags;
+  KFB_TRY((precond_coefs<TD, TA>(drecs, nrec, ca, s)));
+  // T1 = U_G^T G   (NG x dA, row-major)
+  GemmArgs g1;
+  g1.A = op(PU_G, 0, p.lduG, 1); g1.B = op(P_G, 0, p.ldg, 1); g1.C = op(PWS, p.oT1, dA, 1);
+  g1.m = NG; g1.n = (int)dA; g1.k = (int)dG;
+  KFB_TRY((gemm<TU, TGrad, TA, TA, TA>(drecs, nrec, g1, s)));
+  // T2 = G U_A     (dG x NA, column-major)
+  GemmArgs g2;
+  g2.A = op(P_G, 0, p.ldg, 1); g2.B = op(PU_A, 0, 1, p.lduA); g2.C = op(PWS, p.oT2, 1, dG);
+  g2.m = (int)dG; g2.n = NA; g2.k = (int)dA;
+  KFB_TRY((gemm<TGrad, TU, TA, TA, TA>(drecs, nrec, g2, s)));
+  // T3 = T1 U_A    (NG x NA)
+  GemmArgs g3;
+  g3.A = op(PWS, p.oT1, dA, 1); g3.B = op(PU_A, 0, 1, p.lduA); g3.C = op(PWS, p.oT3, 1, NG);
+  g3.m = NG; g3.n = NA; g3.k = (int)dA; g3.ksplit = p.ks3; g3.Part = op(PWS, p.oPart, 1, NG);
+  KFB_TRY((gemm<TA, TU, TA, TA, TA>(drecs, nrec, g3, s)));
+  // X1 = diag(c_G / lam_A) T1;  T2 <- T2 diag(c_A / lam_G);  T3 <- diag(c_G) T3 diag(c_A)
+  ScaleArgs s1;
+  s1.m = NG; s1.n = (int)dA; s1.X = op(PWS, p.oT1, dA, 1); s1.row_slot = PWS; s1.row_off = p.ocG;
+  s1.col_slot = -1; s1.col_off = 0; s1.extra_mode = 0;
+  KFB_TRY((scale2d<TA, TA>(drecs, nrec, s1, s)));
+  ScaleArgs s2;
+  s2.m = (int)dG; s2.n = NA; s2.X = op(PWS, p.oT2, 1, dG); s2.row_slot = -1; s2.row_off = 0;
+  s2.col_slot = PWS; s2.col_off = p.ocA; s2.extra_mode = 0;
+  KFB_TRY((scale2d<TA, TA>(drecs, nrec, s2, s)));
+  ScaleArgs s3;
+  s3.m = NG; s3.n = NA; s3.X = op(PWS, p.oT3, 1, NG); s3.row_slot = PWS;
+  s3.row_off = p.ocG + (int64_t)NG * sizeof(TA); s3.col_slot = PWS;
+  s3.col_off = p.ocA + (int64_t)NA * sizeof(TA); s3.extra_mode = 0;
+  KFB_TRY((scale2d<TA, TA>(drecs, nrec, s3, s)));
+  // X2 = T2 + U_G T3   (in place over T2)
+  GemmArgs g4;
+  g4.A = op(PU_G, 0, 1, p.lduG); g4.B = op(PWS, p.oT3, 1, NG); g4.C0 = op(PWS, p.oT2, 1, dG);
+  g4.C = op(PWS, p.oT2, 1, dG); g4.m = (int)dG; g4.n = NA; g4.k = NG; g4.beta = 1.0;
+  KFB_TRY((gemm<TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
+  // S = G / (lam_G lam_A) + [U_G | X2] [X1 ; U_A^T]
+  GemmArgs g5;
+  g5.A = op(PU_G, 0, 1, p.lduG);
+  g5.A.slot2 = PWS; g5.A.off2 = p.oT2; g5.A.rs2 = 1; g5.A.cs2 = dG; g5.A.split = NG;
+  g5.B = op(PWS, p.oT1, dA, 1);
+  g5.B.slot2 = PU_A; g5.B.off2 = 0; g5.B.rs2 = p.lduA; g5.B.cs2 = 1; g5.B.split = NG;
+  g5.C0 = op(P_G, 0, p.ldg, 1); g5.beta_slot = PWS; g5.beta_off = p.oBeta;
+  g5.C = op(P_S, 0, p.lds, 1);
+  g5.m = (int)dG; g5.n = (int)dA; g5.k = NG + NA;
+  KFB_TRY((gemm<TU, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
+  return KFB_OK;
+}
+
+inline int upd_r_eff(kfb_state_t st) { return st->k_valid < st->r ? st->k_valid : st->r; }
+
+int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, int64_t ldm, int32_t n,
+                    void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only) {
+  if (count <= 0 || !sts) return KFB_EINVAL;
+  kfb_state_t s0 = sts[0];
+  if (!s0) return KFB_EINVAL;
+  const int prec = s0->prec;
+  const int r_eff = upd_r_eff(s0);
+  if (n <= 0 || n > s0->n_max || ldm < s0->d) return KFB_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t st = sts[i];
+    if (!st) return KFB_EINVAL;
+    if (st->prec != prec || st->d != s0->d || st->r != s0->r || upd_r_eff(st) != r_eff ||
+        n > st->n_max || st->ldu != s0->ldu)
+      return KFB_ESTATE;
+    for (int j = 0; j < i; ++j)
+      if (sts[j] == st) return KFB_ESTATE;
+  }
+  UpdPlan p;
+  bool ok = false;
+  if (prec == KFB_FP64) ok = make_upd_plan<KFB_FP64>(s0->d, s0->ldu, ldm, r_eff, n, count, &p);
+  else if (prec == KFB_FP32) ok = make_upd_plan<KFB_FP32>(s0->d, s0->ldu, ldm, r_eff, n, count, &p);
+  else ok = make_upd_plan<KFB_BF16_MIXED>(s0->d, s0->ldu, ldm, r_eff, n, count, &p);
+  if (!ok) return KFB_EINVAL;
+  const size_t head = align256(sizeof(Rec) * (size_t)count);
+  const size_t need = head + p.per_problem * (size_t)count;
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!Ms || !workspace) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  Rec* host = (Rec*)malloc(sizeof(Rec) * (size_t)count);
+  if (!host) return KFB_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!Ms[i]) { free(host); return KFB_EINVAL; }
+    kfb_state_t st = sts[i];
+    Rec* rc = &host[i];
+    memset(rc, 0, sizeof(Rec));
+    rc->p[U_FRONT] = st->buf + st->off_U[st->front];
+    rc->p[U_BACK] = st->buf + st->off_U[1 - st->front];
+    rc->p[M_IN] = const_cast<void*>(Ms[i]);
+    rc->p[WS] = (char*)workspace + head + p.per_problem * (size_t)i;
+    rc->p[D_FRONT] = st->buf + st->off_D[st->front];
+    rc->p[D_BACK] = st->buf + st->off_D[1 - st->front];
+    rc->p[STATUS] = st->buf + st->off_status;
+    rc->s[0] = st->k_valid > 0 ? st->rho : 0.0;           // decay applied to the kept modes
+    rc->s[1] = st->k_valid > 0 ? (1.0 - st->rho) / n : 1.0 / n;  // batch weight w
+  }
+  Rec* dev = (Rec*)workspace;
+  hipError_t he = upload_recs(host, count, dev, s);
+  free(host);
+  if (he != hipSuccess) return KFB_EHIP;
+  int rc;
+  if (prec == KFB_FP64) rc = run_update<KFB_FP64>(dev, count, p, s);
+  else if (prec == KFB_FP32) rc = run_update<KFB_FP32>(dev, count, p, s);
+  else rc = run_update<KFB_BF16_MIXED>(dev, count, p, s);
+  if (rc != KFB_OK) return rc;
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t st = sts[i];
+    st->front = 1 - st->front;
+    int64_t kv = (int64_t)r_eff + n;
+    if (kv > st->d) kv = st->d;
+    st->k_valid = (int32_t)kv;
+    st->step += 1;
+  }
+  return KFB_OK;
+}
+
+int pre_modes(kfb_state_t st, uint32_t flags) {
+  int k = st->k_valid;
+  if ((flags & KFB_TRUNCATE_AFTER) && k > st->r) k = st->r;
+  return k;
+}
+
+int dispatch_precond(int count, kfb_state_t const* stG, kfb_state_t const* stA, const void* const* G,
+                     int64_t ldg, void* const* S, int64_t lds, const double* lamG, const double* lamA,
+                     uint32_t flags, void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only) {
+  if (count <= 0 || !stG || !stA) return KFB_EINVAL;
+  kfb_state_t g0 = stG[0], a0 = stA[0];
+  if (!g0 || !a0) return KFB_EINVAL;
+  const int prec = g0->prec;
+  const int NG = pre_modes(g0, flags), NA = pre_modes(a0, flags);
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t g = stG[i], a = stA[i];
+    if (!g || !a) return KFB_EINVAL;
+    if (g == a) return KFB_ESTATE;
+    if (g->prec != prec || a->prec != prec || g->d != g0->d || a->d != a0->d ||
+        pre_modes(g, flags) != NG || pre_modes(a, flags) != NA || g->ldu != g0->ldu || a->ldu != a0->ldu)
+      return KFB_ESTATE;
+  }
+  if (NG <= 0 || NA <= 0) return KFB_EEMPTY;
+  if (ldg < a0->d || lds < a0->d) return KFB_EINVAL;
+  PrePlan p;
+  if (prec == KFB_FP64) make_pre_plan<KFB_FP64>(g0->d, a0->d, g0->ldu, a0->ldu, NG, NA, ldg, lds, count, &p);
+  else if (prec == KFB_FP32) make_pre_plan<KFB_FP32>(g0->d, a0->d, g0->ldu, a0->ldu, NG, NA, ldg, lds, count, &p);
+  else make_pre_plan<KFB_BF16_MIXED>(g0->d, a0->d, g0->ldu, a0->ldu, NG, NA, ldg, lds, count, &p);
+  const size_t head = align256(sizeof(Rec) * (size_t)count);
+  const size_t need = head + p.per_problem * (size_t)count;
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!G || !S || !workspace || !lamG || !lamA) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  Rec* host = (Rec*)malloc(sizeof(Rec) * (size_t)count);
+  if (!host) return KFB_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!G[i] || !S[i] || G[i] == S[i] || !(lamG[i] > 0.0) || !(lamA[i] > 0.0)) { free(host); return KFB_EINVAL; }
+    kfb_state_t g = stG[i], a = stA[i];
+    Rec* rc = &host[i];
+    memset(rc, 0, sizeof(Rec));
+    rc->p[PU_G] = g->buf + g->off_U[g->front];
+    rc->p[PD_G] = g->buf + g->off_D[g->front];
+    rc->p[PU_A] = a->buf + a->off_U[a->front];
+    rc->p[PD_A] = a->buf + a->off_D[a->front];
+    rc->p[P_G] = const_cast<void*>(G[i]);
+    rc->p[P_S] = S[i];
+    rc->p[PWS] = (char*)workspace + head + p.per_problem * (size_t)i;
+    rc->s[0] = lamG[i];
+    rc->s[1] = lamA[i];
+  }
+  Rec* dev = (Rec*)workspace;
+  hipError_t he = upload_recs(host, count, dev, s);
+  free(host);
+  if (he != hipSuccess) return KFB_EHIP;
+  if (prec == KFB_FP64) return run_precond<KFB_FP64>(dev, count, p, flags, s);
+  if (prec == KFB_FP32) return run_precond<KFB_FP32>(dev, count, p, flags, s);
+  return run_precond<KFB_BF16_MIXED>(dev, count, p, flags, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kfb_state_bytes(int64_t d, int32_t r, int32_t n_max, int32_t prec) {
+  if (d <= 0 || r < 0 || n_max <= 0 || (int64_t)r + n_max > d) return 0;
+  if (prec < KFB_FP64 || prec > KFB_BF16_MIXED) return 0;
+  const int64_t cap = (int64_t)r + n_max;
+  const size_t ub = align256((size_t)ldu_for(d, prec) * cap * u_elem(prec));
+  const size_t db = align256((size_t)cap * d_elem(prec));
+  return 2 * ub + 2 * db + 256;
+}
+
+int kfb_state_create(kfb_state_t* out, int64_t d, int32_t r, int32_t n_max, double rho, int32_t prec,
+                     void* state_buf, size_t state_bytes, kfb_stream_t stream) {
+  if (!out || !state_buf) return KFB_EINVAL;
+  const size_t need = kfb_state_bytes(d, r, n_max, prec);
+  if (need == 0 || !(rho >= 0.0 && rho < 1.0)) return KFB_EINVAL;
+  if (state_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)state_buf) & 255) return KFB_EINVAL;
+  kfb_state_s* st = new (std::nothrow) kfb_state_s();
+  if (!st) return KFB_EINVAL;
+  st->d = d; st->r = r; st->n_max = n_max; st->prec = prec; st->rho = rho;
+  st->buf = (char*)state_buf; st->bytes = state_bytes;
+  st->ldu = ldu_for(d, prec);
+  const int64_t cap = (int64_t)r + n_max;
+  const size_t ub = align256((size_t)st->ldu * cap * u_elem(prec));
+  const size_t db = align256((size_t)cap * d_elem(prec));
+  st->off_U[0] = 0; st->off_U[1] = ub;
+  st->off_D[0] = 2 * ub; st->off_D[1] = 2 * ub + db;
+  st->off_status = 2 * ub + 2 * db;
+  if (hipMemsetAsync(st->buf + st->off_status, 0, 4, (hipStream_t)stream) != hipSuccess) {
+    delete st;
+    return KFB_EHIP;
+  }
+  *out = st;
+  return KFB_OK;
+}
+
+int kfb_destroy(kfb_state_t st) {
+  if (!st) return KFB_EINVAL;
+  delete st;
+  return KFB_OK;
+}
+
+size_t kfb_update_workspace_bytes(kfb_state_t st, int32_t n) {
+  size_t need = 0;
+  if (!st) return 0;
+  if (dispatch_update(1, &st, nullptr, st->d, n, nullptr, 0, nullptr, &need) != KFB_OK) return 0;
+  return need;
+}
+
+int kfb_brand_update(kfb_state_t st, const void* M, int64_t ldm, int32_t n, void* workspace,
+                     size_t ws_bytes, kfb_stream_t stream) {
+  if (!st || !M) return KFB_EINVAL;
+  const void* Ms[1] = {M};
+  return dispatch_update(1, &st, Ms, ldm, n, workspace, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_update_batched_workspace_bytes(int32_t count, kfb_state_t const* states, int32_t n) {
+  size_t need = 0;
+  if (count <= 0 || !states || !states[0]) return 0;
+  if (dispatch_update(count, states, nullptr, states[0]->d, n, nullptr, 0, nullptr, &need) != KFB_OK)
+    return 0;
+  return need;
+}
+
+int kfb_brand_update_batched(int32_t count, kfb_state_t const* states, const void* const* Ms,
+                             int64_t ldm, int32_t n, void* workspace, size_t ws_bytes,
+                             kfb_stream_t stream) {
+  return dispatch_update(count, states, Ms, ldm, n, workspace, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_precondition_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a) {
+  size_t need = 0;
+  if (!st_gamma || !st_a) return 0;
+  double l = 1.0;
+  if (dispatch_precond(1, &st_gamma, &st_a, nullptr, st_a->d, nullptr, st_a->d, &l, &l, 0, nullptr, 0,
+                       nullptr, &need) != KFB_OK)
+    return 0;
+  return need;
+}
+
+int kfb_precondition(kfb_state_t st_gamma, kfb_state_t st_a, const void* G, int64_t ldg, void* S,
+                     int64_t lds, double lam_gamma, double lam_a, uint32_t flags, void* workspace,
+                     size_t ws_bytes, kfb_stream_t stream) {
+  const void* Gs[1] = {G};
+  void* Ss[1] = {S};
+  return dispatch_precond(1, &st_gamma, &st_a, Gs, ldg, Ss, lds, &lam_gamma, &lam_a, flags, workspace,
+                          ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_precondition_batched_workspace_bytes(int32_t count, kfb_state_t const* st_gamma,
+                                                kfb_state_t const* st_a) {
+  size_t need = 0;
+  if (count <= 0 || !st_gamma || !st_a || !st_a[0]) return 0;
+  double* l = (double*)malloc(sizeof(double) * (size_t)count);
+  if (!l) return 0;
+  for (int i = 0; i < count; ++i) l[i] = 1.0;
+  const int rc = dispatch_precond(count, st_gamma, st_a, nullptr, st_a[0]->d, nullptr, st_a[0]->d, l, l, 0,
+                                  nullptr, 0, nullptr, &need);
+  free(l);
+  return rc == KFB_OK ? need : 0;
+}
+
+int kfb_precondition_batched(int32_t count, kfb_state_t const* st_gamma, kfb_state_t const* st_a,
+                             const void* const* G, int64_t ldg, void* const* S, int64_t lds,
+                             const double* lam_gamma, const double* lam_a, uint32_t flags,
+                             void* workspace, size_t ws_bytes, kfb_stream_t stream) {
+  return dispatch_precond(count, st_gamma, st_a, G, ldg, S, lds, lam_gamma, lam_a, flags, workspace,
+                          ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,
+                   int32_t* n_max, int32_t* prec) {
+  if (!st) return KFB_EINVAL;
+  if (k_valid) *k_valid = st->k_valid;
+  if (step) *step = st->step;
+  if (d) *d = st->d;
+  if (r) *r = st->r;
+  if (n_max) *n_max = st->n_max;
+  if (prec) *prec = st->prec;
+  return KFB_OK;
+}
+
+int kfb_state_front(kfb_state_t st, const void** U, int64_t* ldu, const void** D) {
+  if (!st) return KFB_EINVAL;
+  if (U) *U = st->buf + st->off_U[st->front];
+  if (ldu) *ldu = st->ldu;
+  if (D) *D = st->buf + st->off_D[st->front];
+  return KFB_OK;
+}
+
+int kfb_state_load(kfb_state_t st, const void* U, int64_t ldu, const void* D, int32_t k, int64_t step,
+                   kfb_stream_t stream) {
+  if (!st || !U || !D || k < 0 || k > st->r + st->n_max || k > st->d || ldu < st->d || step < 0)
+    return KFB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t ue = u_elem(st->prec), de = d_elem(st->prec);
+  if (k > 0) {
+    KFB_TRY(hipMemcpy2DAsync(st->buf + st->off_U[st->front], (size_t)st->ldu * ue, U, (size_t)ldu * ue,
+                             (size_t)st->d * ue, (size_t)k, hipMemcpyDeviceToDevice, s));
+    KFB_TRY(hipMemcpyAsync(st->buf + st->off_D[st->front], D, (size_t)k * de, hipMemcpyDeviceToDevice, s));
+  }
+  st->k_valid = k;
+  st->step = step;
+  return KFB_OK;
+}
+
+int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream) {
+  if (!st || !events) return KFB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t v = 0;
+  KFB_TRY(hipMemcpyAsync(&v, st->buf + st->off_status, 4, hipMemcpyDeviceToHost, s));
+  KFB_TRY(hipStreamSynchronize(s));
+  KFB_TRY(hipMemsetAsync(st->buf + st->off_status, 0, 4, s));
+  KFB_TRY(hipStreamSynchronize(s));
+  *events = v;
+  return KFB_OK;
+}
+
+const char* kfb_strerror(int code) {
+  switch (code) {
+    case KFB_OK: return "ok";
+    case KFB_EINVAL: return "invalid argument";
+    case KFB_EWORKSPACE: return "buffer or workspace too small";
+    case KFB_EHIP: return "HIP runtime error";
+    case KFB_ESTATE: return "incompatible states";
+    case KFB_EEMPTY: return "state holds no modes";
+    default: return "unknown error";
+  }
+}
+
+const char* kfb_build_info(void) { return "kfb gfx950 hip"; }
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Internal definitions shared by the kfb HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/kfb.h"
+
+namespace kfb {
+
+typedef __hip_bfloat16 bf16;
+
+// ---------------------------------------------------------------------------
+// Per-problem records.  Every stage kernel of a (possibly grouped) call gets a
+// device array of Rec, one per independent problem, and resolves its operand
+// pointers as rec.p[slot] + byte offset.  Shapes and offsets are shared by
+// all problems of one launch and travel by value in the kernel arguments.
+// ---------------------------------------------------------------------------
+constexpr int REC_SLOTS = 10;
+struct Rec {
+  void* p[REC_SLOTS];
+  double s[4];
+};
+
+// Slots used by the Brand update.
+enum UpdSlot { U_FRONT = 0, U_BACK = 1, M_IN = 2, WS = 3, D_FRONT = 4, D_BACK = 5, STATUS = 6 };
+// Slots used by the preconditioner.
+enum PreSlot { PU_G = 0, PD_G = 1, PU_A = 2, PD_A = 3, P_G = 4, P_S = 5, PWS = 6 };
+
+// A matrix operand resolved per record: element (i, j) of the logical matrix
+// lives at base + i*rs + j*cs, with base = rec.p[slot] + off (bytes).  When
+// slot2 >= 0 the operand is split along its k-index (columns of A, rows of B)
+// at `split`: indices >= split come from the second segment, re-based at 0.
+struct OpRef {
+  int32_t slot = -1, slot2 = -1;
+  int64_t off = 0, off2 = 0;
+  int64_t rs = 0, cs = 0, rs2 = 0, cs2 = 0;
+  int32_t split = 0;
+};
+
+struct GemmArgs {
+  OpRef A, B, C, C0, Part;
+  int32_t m = 0, n = 0, k = 0;
+  double alpha = 1.0, beta = 0.0;
+  int32_t ksplit = 1;  // > 1: partial sums go to Part as [kz][i + j*m]
+  int32_t kchunk = 0;  // k range per split (multiple of the tile depth)
+  // beta read from device memory (a double at rec.p[beta_slot] + beta_off)
+  // when beta_slot >= 0; lets a launch use per-problem values computed on the GPU
+  int32_t beta_slot = -1;
+  int64_t beta_off = 0;
+};
+
+template <typename T>
+__host__ __device__ inline T* at(const Rec& r, int slot, int64_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(r.p[slot]) + off);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Element type tags for the precision forms.
+enum Prec { P64 = KFB_FP64, P32 = KFB_FP32, PMIX = KFB_BF16_MIXED };
+
+}  // namespace kfb

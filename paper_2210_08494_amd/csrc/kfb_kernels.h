@@ -1,0 +1,88 @@
+// Launch wrappers of the kfb device kernels (declarations).
+#pragma once
+#include "kfb_internal.h"
+
+namespace kfb {
+
+// ---- generic strided GEMM:  C = alpha * A(m x k) B(k x n) + beta * C0 -----
+// TA/TB/TC/TC0: element types of the operands; TAcc: accumulation type.
+// With g.ksplit > 1 the k range is cut into chunks whose partial products go
+// to g.Part and are summed in a fixed order by splitk_reduce (deterministic).
+template <typename TA, typename TB, typename TC, typename TC0, typename TAcc>
+hipError_t gemm(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
+
+// BF16 MFMA variant: A and B are read as FP32 or BF16, rounded to BF16 (and,
+// with SPLIT = 3, also the BF16 remainders, so that hi*hi + hi*lo + lo*hi
+// recovers ~16 bits), multiplied on MFMA with FP32 accumulation.
+template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
+hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
+
+// ---- small helpers ---------------------------------------------------------
+hipError_t upload_recs(const Rec* host, int nrec, Rec* dev, hipStream_t s);
+
+// dst(i,j) = src(i,j) for an m x n matrix (types converted)
+template <typename TD, typename TS>
+hipError_t copy2d(const Rec* recs, int nrec, OpRef dst, OpRef src, int m, int n, hipStream_t s);
+
+// fill int32 counters with zero (graph-safe, no memset nodes)
+hipError_t zero_words(const Rec* recs, int nrec, int slot, int64_t off, int nwords, hipStream_t s);
+
+// ---- Brand-update stages ---------------------------------------------------
+struct CholArgs {
+  int n;
+  int64_t off_gram, off_R, off_Rinv;  // n x n column-major in WS
+  int64_t off_rowbuf;                  // n elements scratch
+  double tau_rel;                      // pivot tolerance relative to max diagonal
+};
+template <typename T>
+hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s);
+
+struct CoreArgs {
+  int r, n, N, Np;
+  int64_t off_P, off_P2, off_R;  // P, P2: r x n col-major (TP); R: n x n col-major (TG)
+  int64_t off_B, off_V;          // Np x Np col-major (TCore)
+};
+template <typename TCore, typename TP, typename TG, typename TD>
+hipError_t assemble_core(const Rec* recs, int nrec, const CoreArgs& a, hipStream_t s);
+
+struct JacArgs {
+  int Np, N, b, max_sweeps;
+  int64_t off_B, off_V, off_cnt;
+  double tol;
+};
+// One round of the block one-sided Jacobi (all problems in parallel), or, if
+// the panel holds every column (Np == 2b), the complete iteration.
+template <typename T>
+hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round,
+                        hipStream_t s);
+int jacobi_pick_block(int N, int elem_bytes, int* Np);
+
+struct FinArgs {
+  int N, Np, max_sweeps;
+  int64_t off_B, off_V, off_cnt, off_lam, off_rank;
+  int64_t off_W;  // N x N column-major (TW)
+};
+template <typename TCore, typename TW, typename TD>
+hipError_t finalize_core(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s);
+
+// ---- preconditioner helpers -------------------------------------------------
+struct CoefArgs {
+  int kG, kA;              // modes used per side
+  int64_t off_cG, off_cA;  // coefficient vectors (TAcc) in PWS
+  uint32_t flags;
+};
+template <typename TD, typename TAcc>
+hipError_t precond_coefs(const Rec* recs, int nrec, const CoefArgs& a, hipStream_t s);
+
+// in place: X(i,j) *= rowscale[i] * colscale[j] * extra, optional vectors
+struct ScaleArgs {
+  int m, n;
+  OpRef X;
+  int row_slot, col_slot;  // -1 = none
+  int64_t row_off, col_off;
+  int extra_mode;          // 0: none, 1: multiply by 1/rec.s[0], 2: by 1/rec.s[1]
+};
+template <typename T, typename TS>
+hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s);
+
+}  // namespace kfb

@@ -1,0 +1,539 @@
+// Small dense linear algebra of the Brand update (Algorithm 3):
+//   * Cholesky factor + triangular inverse of the residual Gram (CholeskyQR),
+//   * assembly of the square factor of the core (eqn. for M_S, Section 2.3),
+//   * block one-sided Jacobi eigensolver of the core,
+//   * sort / gather of the eigenpairs,
+// and the coefficient / scaling kernels of the two-sided inverse application.
+#include "kfb_kernels.h"
+
+namespace kfb {
+
+template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
+template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
+
+template <typename T> struct Eps;
+template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
+template <> struct Eps<float> { static constexpr float v = 1.1920929e-07f; };
+
+template <typename To, typename From>
+__device__ __forceinline__ To cvt(From x) { return static_cast<To>(x); }
+
+// ---------------------------------------------------------------------------
+// Cholesky of an n x n symmetric PSD Gram matrix W = R^T R (R upper) and the
+// inverse X = R^{-1}, one workgroup per problem.  A pivot at or below
+// tau_rel * max_i W_ii marks a numerically null direction of the residual:
+// its row of R is set to zero and the matching row and column of X are zero,
+// so the orthonormalised residual Q = Z X gets a zero column there (any
+// orthonormal completion would do; zero columns carry zero eigenvalues and
+// never influence the update or the inverse application).
+// ---------------------------------------------------------------------------
+constexpr int CHOL_NT = 1024;
+constexpr int CHOL_MAXN = 2048;
+
+template <typename T>
+__global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict__ recs, CholArgs a) {
+  const Rec& rec = recs[blockIdx.x];
+  const int n = a.n;
+  const T* Wg = at<const T>(rec, WS, a.off_gram);
+  T* R = at<T>(rec, WS, a.off_R);
+  T* X = at<T>(rec, WS, a.off_Rinv);
+  __shared__ T row[CHOL_MAXN];
+  __shared__ T red[CHOL_NT / 64];
+  __shared__ int deficient, nonfinite;
+  const int t = threadIdx.x;
+  if (t == 0) { deficient = 0; nonfinite = 0; }
+  __syncthreads();
+
+  // max diagonal (tolerance scale) and finiteness (v - v is 0 only for finite v)
+  T mx = T(0);
+  for (int i = t; i < n; i += CHOL_NT) {
+    const T v = Wg[i + (int64_t)i * n];
+    if (!(v - v == T(0))) nonfinite = 1;
+    mx = v > mx ? v : mx;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if ((t & 63) == 0) red[t >> 6] = mx;
+  // copy upper triangle, zero the rest
+  for (int64_t e = t; e < (int64_t)n * n; e += CHOL_NT) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    R[e] = (i <= j) ? Wg[e] : T(0);
+    X[e] = T(0);
+  }
+  __syncthreads();
+  if (t == 0) {
+    T m = red[0];
+    for (int w = 1; w < CHOL_NT / 64; ++w) m = red[w] > m ? red[w] : m;
+    red[0] = m;
+  }
+  __syncthreads();
+  const T tau = T(a.tau_rel) * red[0];
+
+  // right-looking Cholesky, row by row of R
+  for (int j = 0; j < n; ++j) {
+    const T p = R[j + (int64_t)j * n];
+    const bool ok = p > tau && (red[0] > T(0));
+    const T sp = ok ? dev_sqrt(p) : T(0);
+    const T inv = ok ? T(1) / sp : T(0);
+    for (int k = j + t; k < n; k += CHOL_NT) {
+      const T v = (k == j) ? sp : R[j + (int64_t)k * n] * inv;
+      R[j + (int64_t)k * n] = v;
+      row[k] = v;
+    }
+    if (!ok && t == 0) deficient = 1;
+    __syncthreads();
+    const int m = n - j - 1;
+    if (ok && m > 0) {
+      for (int64_t e = t; e < (int64_t)m * m; e += CHOL_NT) {
+        const int ii = (int)(e % m), kk = (int)(e / m);
+        if (ii <= kk) {
+          const int gi = j + 1 + ii, gk = j + 1 + kk;
+          R[gi + (int64_t)gk * n] -= row[gi] * row[gk];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // X = R^{-1}, rows bottom-up; threads of a sub-group share one column
+  int tpc = 1;
+  while (tpc * 2 * n <= CHOL_NT && tpc < 16) tpc *= 2;
+  const int lane = t % tpc, colid = t / tpc, ncolgroups = CHOL_NT / tpc;
+  for (int i = n - 1; i >= 0; --i) {
+    const T rii = R[i + (int64_t)i * n];
+    for (int k = i + 1 + t; k < n; k += CHOL_NT) row[k] = R[i + (int64_t)k * n];
+    __syncthreads();
+    const T dinv = rii > T(0) ? T(1) / rii : T(0);
+    for (int j0 = i; j0 < n; j0 += ncolgroups) {
+      const int j = j0 + colid;
+      T sum = T(0);
+      if (j < n && j > i) {
+        for (int k = i + 1 + lane; k <= j; k += tpc) sum += row[k] * X[k + (int64_t)j * n];
+      }
+      for (int off = tpc / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      if (j < n && lane == 0) {
+        if (j == i) X[i + (int64_t)i * n] = dinv;
+        else X[i + (int64_t)j * n] = -sum * dinv;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    uint32_t ev = (deficient ? KFB_EV_CHOL_DEFICIENT : 0u) | (nonfinite ? KFB_EV_NONFINITE : 0u);
+    if (ev) atomicOr(at<uint32_t>(rec, STATUS, 0), ev);
+  }
+}
+
+template <typename T>
+hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s) {
+  if (a.n <= 0 || nrec <= 0) return hipSuccess;
+  if (a.n > CHOL_MAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((chol_inv_kernel<T>), dim3(nrec), dim3(CHOL_NT), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Core assembly.  With L = [[diag(sqrt(rho D)), sqrt(w) P], [0, sqrt(w) R]]
+// (N x N, P = U^T M including the re-projection, R the residual's triangular
+// factor), the Brand core is M_S = L L^T.  The Jacobi iteration orthogonalises
+// the columns of B = L^T (B^T B = M_S), accumulating V; the kernel writes B
+// and V = I padded to Np x Np (padding columns are zero and never rotate).
+// ---------------------------------------------------------------------------
+template <typename TCore, typename TP, typename TG, typename TD>
+__global__ __launch_bounds__(256) void assemble_core_kernel(const Rec* __restrict__ recs, CoreArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const int r = a.r, N = a.N, Np = a.Np, n = a.n;
+  const double rho = rec.s[0], w = rec.s[1];
+  const TCore sw = TCore(sqrt(w));
+  TCore* Bm = at<TCore>(rec, WS, a.off_B);
+  TCore* Vm = at<TCore>(rec, WS, a.off_V);
+  const TD* D = r > 0 ? at<const TD>(rec, D_FRONT, 0) : nullptr;
+  const TP* P = r > 0 ? at<const TP>(rec, WS, a.off_P) : nullptr;
+  const TP* P2 = (r > 0 && a.off_P2 >= 0) ? at<const TP>(rec, WS, a.off_P2) : nullptr;
+  const TG* R = at<const TG>(rec, WS, a.off_R);
+  const int64_t tot = (int64_t)Np * Np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % Np), j = (int)(e / Np);
+    // B(i, j) = L(j, i)
+    const int p = j, q = i;
+    TCore v = TCore(0);
+    if (p < N && q < N) {
+      if (p < r) {
+        if (q < r) {
+          if (p == q) {
+            const double dv = rho * (double)D[p];
+            v = TCore(dv > 0.0 ? sqrt(dv) : 0.0);
+          }
+        } else {
+          TCore pv = TCore(P[p + (int64_t)(q - r) * r]);
+          if (P2) pv += TCore(P2[p + (int64_t)(q - r) * r]);
+          v = sw * pv;
+        }
+      } else if (q >= r) {
+        v = sw * TCore(R[(p - r) + (int64_t)(q - r) * n]);
+      }
+    }
+    Bm[e] = v;
+    Vm[e] = (i == j) ? TCore(1) : TCore(0);
+  }
+}
+
+template <typename TCore, typename TP, typename TG, typename TD>
+hipError_t assemble_core(const Rec* recs, int nrec, const CoreArgs& a, hipStream_t s) {
+  const int64_t tot = (int64_t)a.Np * a.Np;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((assemble_core_kernel<TCore, TP, TG, TD>), dim3(blocks, nrec), dim3(256), 0, s,
+                     recs, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi (Hestenes) on the columns of B, accumulating V.
+//
+// The Np columns are cut into nb = Np / BW blocks.  A sweep is a round-robin
+// tournament over the blocks (circle method, nb - 1 rounds of nb / 2 disjoint
+// block pairs); one launch performs one round for all problems, one workgroup
+// per block pair.  The workgroup stages the 2*BW columns of B and V of its
+// pair in LDS and applies plane rotations to every column pair not yet met in
+// this sweep: in round 0 all pairs inside the panel (a tournament over its
+// 2*BW columns), in later rounds the BW*BW cross pairs.  Each step runs BW
+// disjoint rotations, one per group of 256/BW lanes.
+//
+// Rotation for a column pair (a, b) with alpha = a.a, beta = b.b, gamma = a.b:
+// skip if |gamma| <= tol * sqrt(alpha * beta); otherwise zeta = (beta - alpha)
+// / (2 gamma), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
+// s = c t, and (a, b) <- (c a - s b, s a + c b), which makes a.b = 0.
+//
+// Convergence: every workgroup adds its rotation count to cnt[sweep]; a launch
+// of sweep s > 0 returns at once when cnt[s-1] == 0 (no rotation in the
+// previous full sweep).  When one panel holds every column (nb == 2) the
+// kernel runs all sweeps itself.
+// ---------------------------------------------------------------------------
+constexpr int JAC_NT = 256;
+constexpr int JAC_LDS_BYTES = 128 * 1024;
+
+__device__ __forceinline__ void tour_pair(int P, int st, int q, int* x, int* y) {
+  // circle method over P players, step st in [0, P-1), pair q in [0, P/2)
+  const int R = P - 1;
+  if (q == 0) { *x = st; *y = P - 1; }
+  else { *x = (st + q) % R; *y = (st - q + R) % R; }
+}
+
+template <typename T, int BW>
+__global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
+                                                        int round) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char jac_smem[];
+  constexpr int PC = 2 * BW;       // panel columns
+  constexpr int GL = JAC_NT / BW;  // lanes per rotation group
+  const Rec& rec = recs[blockIdx.y];
+  int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
+  const int Np = a.Np;
+  const int nb = Np / BW;
+  const bool single = (nb == 2);
+  if (!single && sweep > 0 && cnt[sweep - 1] == 0) return;
+  T* Bm = at<T>(rec, WS, a.off_B);
+  T* Vm = at<T>(rec, WS, a.off_V);
+  int I, J;
+  if (single) { I = 0; J = 1; }
+  else tour_pair(nb, round, blockIdx.x, &I, &J);
+
+  T* pb = reinterpret_cast<T*>(jac_smem);  // B panel: column c at pb + c*Np
+  T* pv = pb + (size_t)PC * Np;             // V panel
+  __shared__ int wg_rot;
+
+  for (int e = threadIdx.x; e < PC * Np; e += JAC_NT) {
+    const int c = e / Np, row = e - c * Np;
+    const int gc = c < BW ? I * BW + c : J * BW + (c - BW);
+    pb[e] = Bm[row + (int64_t)gc * Np];
+    pv[e] = Vm[row + (int64_t)gc * Np];
+  }
+  const int g = threadIdx.x / GL, l = threadIdx.x % GL;
+  const T tol = T(a.tol);
+  int sw = sweep;
+  for (;;) {
+    if (threadIdx.x == 0) wg_rot = 0;
+    __syncthreads();
+    const bool full = single || round == 0;
+    const int nsteps = full ? PC - 1 : BW;
+    for (int st = 0; st < nsteps; ++st) {
+      int ci, cj;
+      if (full) tour_pair(PC, st, g, &ci, &cj);
+      else { ci = g; cj = BW + (g + st) % BW; }
+      T* x = pb + (size_t)ci * Np;
+      T* y = pb + (size_t)cj * Np;
+      T al = T(0), be = T(0), ga = T(0);
+      for (int row = l; row < Np; row += GL) {
+        const T u = x[row], v = y[row];
+        al = fma(u, u, al);
+        be = fma(v, v, be);
+        ga = fma(u, v, ga);
+      }
+#pragma unroll
+      for (int off = GL / 2; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off);
+        be += __shfl_xor(be, off);
+        ga += __shfl_xor(ga, off);
+      }
+      if (ga != T(0) && fabs(ga) > tol * dev_sqrt(al * be)) {
+        const T zeta = (be - al) / (T(2) * ga);
+        const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + dev_sqrt(T(1) + zeta * zeta));
+        const T c = T(1) / dev_sqrt(T(1) + tt * tt);
+        const T s = c * tt;
+        for (int row = l; row < Np; row += GL) {
+          const T u = x[row], v = y[row];
+          x[row] = c * u - s * v;
+          y[row] = s * u + c * v;
+        }
+        T* xv = pv + (size_t)ci * Np;
+        T* yv = pv + (size_t)cj * Np;
+        for (int row = l; row < Np; row += GL) {
+          const T u = xv[row], v = yv[row];
+          xv[row] = c * u - s * v;
+          yv[row] = s * u + c * v;
+        }
+        if (l == 0) atomicAdd(&wg_rot, 1);
+      }
+      __syncthreads();
+    }
+    if (!single) {
+      if (threadIdx.x == 0 && wg_rot > 0) atomicAdd(&cnt[sweep], wg_rot);
+      break;
+    }
+    const int nrot = wg_rot;
+    if (threadIdx.x == 0) cnt[sw] = nrot;
+    ++sw;
+    __syncthreads();
+    if (nrot == 0 || sw >= a.max_sweeps) break;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < PC * Np; e += JAC_NT) {
+    const int c = e / Np, row = e - c * Np;
+    const int gc = c < BW ? I * BW + c : J * BW + (c - BW);
+    Bm[row + (int64_t)gc * Np] = pb[e];
+    Vm[row + (int64_t)gc * Np] = pv[e];
+  }
+}
+
+int jacobi_pick_block(int N, int elem_bytes, int* Np_out) {
+  // largest BW in {32,16,8,4} with both staged panels (2 x Np x 2BW) in LDS
+  const int cands[4] = {32, 16, 8, 4};
+  for (int ci = 0; ci < 4; ++ci) {
+    const int bw = cands[ci];
+    const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
+    if ((size_t)2 * Np * 2 * bw * elem_bytes <= (size_t)JAC_LDS_BYTES) {
+      *Np_out = Np;
+      return bw;
+    }
+  }
+  return 0;
+}
+
+template <typename T, int BW>
+static hipError_t jac_launch(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round,
+                             hipStream_t s) {
+  const int nb = a.Np / BW;
+  const size_t lds = (size_t)2 * a.Np * 2 * BW * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)jacobi_kernel<T, BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        JAC_LDS_BYTES);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((jacobi_kernel<T, BW>), dim3(nb / 2, nrec), dim3(JAC_NT), lds, s, recs, a, sweep,
+                     round);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round, hipStream_t s) {
+  switch (a.b) {
+    case 32: return jac_launch<T, 32>(recs, nrec, a, sweep, round, s);
+    case 16: return jac_launch<T, 16>(recs, nrec, a, sweep, round, s);
+    case 8: return jac_launch<T, 8>(recs, nrec, a, sweep, round, s);
+    case 4: return jac_launch<T, 4>(recs, nrec, a, sweep, round, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: eigenvalues are the squared column norms of B V; sort descending
+// (ties by column index), write D, and gather W = V with permuted columns.
+// ---------------------------------------------------------------------------
+constexpr int FIN_MAXN = 4096;
+
+template <typename TCore, typename TD>
+__global__ __launch_bounds__(256) void fin_sort_kernel(const Rec* __restrict__ recs, FinArgs a) {
+  const Rec& rec = recs[blockIdx.x];
+  const int N = a.N, Np = a.Np;
+  const TCore* Bm = at<const TCore>(rec, WS, a.off_B);
+  TCore* lam = at<TCore>(rec, WS, a.off_lam);
+  int32_t* rank = at<int32_t>(rec, WS, a.off_rank);
+  TD* Dout = at<TD>(rec, D_BACK, 0);
+  __shared__ TCore sl[FIN_MAXN];
+  const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+  for (int j = wv; j < N; j += 4) {
+    const TCore* col = Bm + (int64_t)j * Np;
+    TCore s = TCore(0);
+    for (int i = ln; i < Np; i += 64) s = fma(col[i], col[i], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (ln == 0) sl[j] = s;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += 256) {
+    const TCore v = sl[j];
+    int rk = 0;
+    for (int i = 0; i < N; ++i) {
+      const TCore u = sl[i];
+      rk += (u > v) || (u == v && i < j);
+    }
+    rank[j] = rk;
+    lam[rk] = v;
+    Dout[rk] = TD(v);
+  }
+  if (threadIdx.x == 0) {
+    const int32_t* cnt = at<const int32_t>(rec, WS, a.off_cnt);
+    if (cnt[a.max_sweeps - 1] > 0) atomicOr(at<uint32_t>(rec, STATUS, 0), (uint32_t)KFB_EV_JACOBI_MAXSWEEPS);
+  }
+}
+
+template <typename TCore, typename TW>
+__global__ __launch_bounds__(256) void fin_gather_kernel(const Rec* __restrict__ recs, FinArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const int N = a.N, Np = a.Np;
+  const TCore* Vm = at<const TCore>(rec, WS, a.off_V);
+  const int32_t* rank = at<const int32_t>(rec, WS, a.off_rank);
+  TW* W = at<TW>(rec, WS, a.off_W);
+  const int64_t tot = (int64_t)N * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    W[i + (int64_t)rank[j] * N] = TW(Vm[i + (int64_t)j * Np]);
+  }
+}
+
+template <typename TCore, typename TW, typename TD>
+hipError_t finalize_core(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s) {
+  if (a.N > FIN_MAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fin_sort_kernel<TCore, TD>), dim3(nrec), dim3(256), 0, s, recs, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = (int64_t)a.N * a.N;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((fin_gather_kernel<TCore, TW>), dim3(blocks, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner coefficients (Algorithm 1 inverse lines; Section 3.5):
+//   c_i = 1/(D_i + lam) - 1/lam  per side, with optional spectrum continuation
+//   (lam <- lam + min D, D <- D - min D).  Stored, with the 1/lam factors of
+//   the cross terms folded in:
+//     sG = c_G / lam_A   (rows of U_G^T G)      tG = c_G  (rows of the core)
+//     sA = c_A / lam_G   (cols of G U_A)        tA = c_A  (cols of the core)
+//     beta = 1 / (lam_G lam_A)                   (the G term), as a double.
+// Layout at off_cG: [sG (kG)][tG (kG)]; at off_cA: [sA (kA)][tA (kA)];
+// beta at off_cA + 2*kA*sizeof(TAcc) rounded to 8 bytes.
+// ---------------------------------------------------------------------------
+template <typename TD, typename TAcc>
+__global__ __launch_bounds__(256) void precond_coefs_kernel(const Rec* __restrict__ recs, CoefArgs a) {
+  const Rec& rec = recs[blockIdx.x];
+  const TD* DG = at<const TD>(rec, PD_G, 0);
+  const TD* DA = at<const TD>(rec, PD_A, 0);
+  double lamG = rec.s[0], lamA = rec.s[1];
+  __shared__ double mins[2];
+  if (threadIdx.x == 0) {
+    double mG = 0.0, mA = 0.0;
+    if (a.flags & KFB_SPECTRUM_CONTINUATION) {
+      mG = a.kG > 0 ? (double)DG[0] : 0.0;
+      for (int i = 1; i < a.kG; ++i) mG = fmin(mG, (double)DG[i]);
+      mA = a.kA > 0 ? (double)DA[0] : 0.0;
+      for (int i = 1; i < a.kA; ++i) mA = fmin(mA, (double)DA[i]);
+      mG = fmax(mG, 0.0);
+      mA = fmax(mA, 0.0);
+    }
+    mins[0] = mG;
+    mins[1] = mA;
+  }
+  __syncthreads();
+  const double mG = mins[0], mA = mins[1];
+  const double lG = lamG + mG, lA = lamA + mA;
+  TAcc* cG = at<TAcc>(rec, PWS, a.off_cG);
+  TAcc* cA = at<TAcc>(rec, PWS, a.off_cA);
+  for (int i = threadIdx.x; i < a.kG; i += 256) {
+    const double d = fmax((double)DG[i] - mG, 0.0);
+    const double c = 1.0 / (d + lG) - 1.0 / lG;
+    cG[i] = TAcc(c / lA);
+    cG[a.kG + i] = TAcc(c);
+  }
+  for (int i = threadIdx.x; i < a.kA; i += 256) {
+    const double d = fmax((double)DA[i] - mA, 0.0);
+    const double c = 1.0 / (d + lA) - 1.0 / lA;
+    cA[i] = TAcc(c / lG);
+    cA[a.kA + i] = TAcc(c);
+  }
+  if (threadIdx.x == 0) {
+    const int64_t boff = ((a.off_cA + (int64_t)2 * a.kA * (int64_t)sizeof(TAcc)) + 7) & ~int64_t(7);
+    *at<double>(rec, PWS, boff) = 1.0 / (lG * lA);
+  }
+}
+
+template <typename TD, typename TAcc>
+hipError_t precond_coefs(const Rec* recs, int nrec, const CoefArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((precond_coefs_kernel<TD, TAcc>), dim3(nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename TS>
+__global__ __launch_bounds__(256) void scale2d_kernel(const Rec* __restrict__ recs, ScaleArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  T* X = at<T>(rec, a.X.slot, a.X.off);
+  const TS* rs = a.row_slot >= 0 ? at<const TS>(rec, a.row_slot, a.row_off) : nullptr;
+  const TS* cs = a.col_slot >= 0 ? at<const TS>(rec, a.col_slot, a.col_off) : nullptr;
+  const int64_t tot = (int64_t)a.m * a.n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int i, j;
+    if (a.X.rs == 1) { i = (int)(e % a.m); j = (int)(e / a.m); }
+    else { j = (int)(e % a.n); i = (int)(e / a.n); }
+    TS f = TS(1);
+    if (rs) f *= rs[i];
+    if (cs) f *= cs[j];
+    T* px = X + i * a.X.rs + j * a.X.cs;
+    *px = T(TS(*px) * f);
+  }
+}
+
+template <typename T, typename TS>
+hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s) {
+  const int64_t tot = (int64_t)a.m * a.n;
+  if (tot <= 0 || nrec <= 0) return hipSuccess;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((scale2d_kernel<T, TS>), dim3(blocks, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template hipError_t chol_inv<double>(const Rec*, int, const CholArgs&, hipStream_t);
+template hipError_t chol_inv<float>(const Rec*, int, const CholArgs&, hipStream_t);
+template hipError_t assemble_core<double, double, double, double>(const Rec*, int, const CoreArgs&, hipStream_t);
+template hipError_t assemble_core<float, float, float, float>(const Rec*, int, const CoreArgs&, hipStream_t);
+template hipError_t assemble_core<double, float, double, double>(const Rec*, int, const CoreArgs&, hipStream_t);
+template hipError_t jacobi_round<double>(const Rec*, int, const JacArgs&, int, int, hipStream_t);
+template hipError_t jacobi_round<float>(const Rec*, int, const JacArgs&, int, int, hipStream_t);
+template hipError_t finalize_core<double, double, double>(const Rec*, int, const FinArgs&, hipStream_t);
+template hipError_t finalize_core<float, float, float>(const Rec*, int, const FinArgs&, hipStream_t);
+template hipError_t finalize_core<double, float, double>(const Rec*, int, const FinArgs&, hipStream_t);
+template hipError_t precond_coefs<double, double>(const Rec*, int, const CoefArgs&, hipStream_t);
+template hipError_t precond_coefs<float, float>(const Rec*, int, const CoefArgs&, hipStream_t);
+template hipError_t precond_coefs<double, float>(const Rec*, int, const CoefArgs&, hipStream_t);
+template hipError_t scale2d<double, double>(const Rec*, int, const ScaleArgs&, hipStream_t);
+template hipError_t scale2d<float, float>(const Rec*, int, const ScaleArgs&, hipStream_t);
+
+}  // namespace kfb

@@ -1,0 +1,250 @@
+"""Thin ctypes binding of the kfb C-ABI (include/kfb.h).
+
+Argument marshalling only: every step of the Brand update and of the inverse
+application runs in the HIP kernels of libkfb.so.  PyTorch supplies device
+memory (caller-owned state buffers and workspaces) and the current stream.
+There is no CPU fallback: if the library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkfb.so")
+
+KFB_FP64, KFB_FP32, KFB_BF16_MIXED = 0, 1, 2
+KFB_SPECTRUM_CONTINUATION, KFB_TRUNCATE_AFTER = 1, 2
+KFB_EV_NONFINITE, KFB_EV_CHOL_DEFICIENT, KFB_EV_JACOBI_MAXSWEEPS = 1, 2, 4
+ERRORS = {0: "KFB_OK", 1: "KFB_EINVAL", 2: "KFB_EWORKSPACE", 3: "KFB_EHIP", 4: "KFB_ESTATE",
+          5: "KFB_EEMPTY"}
+
+_lib = None
+_vp, _sz, _i32, _i64, _u32, _dbl = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.c_uint32, ctypes.c_double)
+
+_SIGS = {
+    "kfb_state_bytes": (_sz, [_i64, _i32, _i32, _i32]),
+    "kfb_state_create": (ctypes.c_int, [ctypes.POINTER(_vp), _i64, _i32, _i32, _dbl, _i32, _vp, _sz, _vp]),
+    "kfb_destroy": (ctypes.c_int, [_vp]),
+    "kfb_update_workspace_bytes": (_sz, [_vp, _i32]),
+    "kfb_brand_update": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "kfb_update_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), _i32]),
+    "kfb_brand_update_batched": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64, _i32,
+                                                _vp, _sz, _vp]),
+    "kfb_precondition_workspace_bytes": (_sz, [_vp, _vp]),
+    "kfb_precondition": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _dbl, _dbl, _u32, _vp, _sz, _vp]),
+    "kfb_precondition_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "kfb_precondition_batched": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                ctypes.POINTER(_vp), _i64, ctypes.POINTER(_vp), _i64,
+                                                ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _u32, _vp, _sz,
+                                                _vp]),
+    "kfb_state_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
+    "kfb_state_load": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i64, _vp]),
+    "kfb_state_status": (ctypes.c_int, [_vp, ctypes.POINTER(_u32), _vp]),
+    "kfb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "kfb_build_info": (ctypes.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+
+
+class KfbError(RuntimeError):
+    pass
+
+
+def load(path: str | None = None):
+    """Load libkfb.so (built in-tree by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise KfbError(f"{p} not found: the HIP library must be built (python -c "
+                       "'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise KfbError(f"{what} failed: {ERRORS.get(rc, rc)} ({load().kfb_strerror(rc).decode()})")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Same-named wrappers of the C-ABI (pointers are ints or tensors)
+# ---------------------------------------------------------------------------
+def kfb_state_bytes(d, r, n_max, prec) -> int:
+    return int(load().kfb_state_bytes(d, r, n_max, prec))
+
+
+class Workspace:
+    """A growable device byte buffer (256-byte aligned by the PyTorch allocator)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def _dtype_of(prec):
+    import torch
+    return torch.float64 if prec == KFB_FP64 else torch.float32
+
+
+def _ddtype_of(prec):
+    import torch
+    return torch.float32 if prec == KFB_FP32 else torch.float64
+
+
+def _mdtype_of(prec):
+    import torch
+    return {KFB_FP64: torch.float64, KFB_FP32: torch.float32, KFB_BF16_MIXED: torch.bfloat16}[prec]
+
+
+class Factor:
+    """One K-factor state (caller-owned buffer) behind a kfb handle."""
+
+    def __init__(self, d: int, r: int, n_max: int, rho: float, prec: int, device="cuda"):
+        import torch
+        lib = load()
+        self.d, self.r, self.n_max, self.rho, self.prec = int(d), int(r), int(n_max), float(rho), int(prec)
+        nbytes = lib.kfb_state_bytes(self.d, self.r, self.n_max, self.prec)
+        if nbytes == 0:
+            raise KfbError(f"invalid state sizes d={d} r={r} n_max={n_max}")
+        self.buf = torch.zeros(int(nbytes), dtype=torch.uint8, device=device)
+        self.handle = ctypes.c_void_p()
+        _check(lib.kfb_state_create(ctypes.byref(self.handle), self.d, self.r, self.n_max, self.rho,
+                                    self.prec, _ptr(self.buf), int(nbytes), _stream()), "kfb_state_create")
+        self.ws = Workspace(device)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.kfb_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    @property
+    def mdtype(self):
+        return _mdtype_of(self.prec)
+
+    def info(self):
+        k, s, d, r, nm, pr = _i32(), _i64(), _i64(), _i32(), _i32(), _i32()
+        _check(load().kfb_state_info(self.handle, ctypes.byref(k), ctypes.byref(s), ctypes.byref(d),
+                                     ctypes.byref(r), ctypes.byref(nm), ctypes.byref(pr)), "kfb_state_info")
+        return dict(k_valid=k.value, step=s.value, d=d.value, r=r.value, n_max=nm.value, prec=pr.value)
+
+    def update(self, M, ws: Workspace | None = None):
+        """M: device tensor of shape (n, d) (= column-major d x n), dtype per precision."""
+        lib = load()
+        assert M.is_cuda and M.dim() == 2 and M.shape[1] == self.d and M.dtype == self.mdtype
+        assert M.stride(1) == 1
+        n = int(M.shape[0])
+        need = lib.kfb_update_workspace_bytes(self.handle, n)
+        if need == 0:
+            raise KfbError("kfb_update_workspace_bytes rejected the shape")
+        w = (ws or self.ws).get(need)
+        _check(lib.kfb_brand_update(self.handle, _ptr(M), int(M.stride(0)), n, _ptr(w), int(w.numel()),
+                                    _stream()), "kfb_brand_update")
+
+    def front(self):
+        """(U, D) device views of the current modes: U (d x k), D (k,)."""
+        import torch
+        lib = load()
+        up, ld, dp = _vp(), _i64(), _vp()
+        _check(lib.kfb_state_front(self.handle, ctypes.byref(up), ctypes.byref(ld), ctypes.byref(dp)),
+               "kfb_state_front")
+        k = self.info()["k_valid"]
+        base = self.buf.data_ptr()
+        dt, ddt = _dtype_of(self.prec), _ddtype_of(self.prec)
+        es, des = torch.tensor([], dtype=dt).element_size(), torch.tensor([], dtype=ddt).element_size()
+        uoff, doff = up.value - base, dp.value - base
+        ldu = ld.value
+        Ucols = self.buf[uoff:uoff + max(k, 1) * ldu * es].view(dt).view(max(k, 1), ldu)[:k, :self.d]
+        D = self.buf[doff:doff + max(k, 1) * des].view(ddt)[:k]
+        return Ucols.t(), D
+
+    def load_state(self, U, D, step: int = 1):
+        """Overwrite with (U: d x k device tensor in the state's dtype, D: k)."""
+        lib = load()
+        Uc = U.t().contiguous()  # k x d rows = columns of U
+        k = int(Uc.shape[0])
+        Dc = D.contiguous()
+        _check(lib.kfb_state_load(self.handle, _ptr(Uc), int(Uc.stride(0)), _ptr(Dc), k, int(step), _stream()),
+               "kfb_state_load")
+        import torch
+        torch.cuda.current_stream().synchronize()
+
+    def status(self) -> int:
+        ev = _u32()
+        _check(load().kfb_state_status(self.handle, ctypes.byref(ev), _stream()), "kfb_state_status")
+        return ev.value
+
+
+def precondition(fg: Factor, fa: Factor, G, S, lam_g: float, lam_a: float, flags: int = 0,
+                 ws: Workspace | None = None):
+    """S = (Gamma~ + lam_g I)^{-1} G (A~ + lam_a I)^{-1}; G, S row-major (d_out, d_in) device tensors."""
+    lib = load()
+    assert G.shape == (fg.d, fa.d) and S.shape == G.shape and G.stride(1) == 1 and S.stride(1) == 1
+    need = lib.kfb_precondition_workspace_bytes(fg.handle, fa.handle)
+    if need == 0:
+        raise KfbError("kfb_precondition_workspace_bytes rejected the states")
+    w = (ws or fg.ws).get(need)
+    _check(lib.kfb_precondition(fg.handle, fa.handle, _ptr(G), int(G.stride(0)), _ptr(S), int(S.stride(0)),
+                                float(lam_g), float(lam_a), int(flags), _ptr(w), int(w.numel()), _stream()),
+           "kfb_precondition")
+
+
+def update_batched(factors, Ms, ws: Workspace):
+    """One grouped launch sequence updating every factor with its batch (same shape bucket)."""
+    lib = load()
+    cnt = len(factors)
+    hs = (_vp * cnt)(*[f.handle.value for f in factors])
+    ms = (_vp * cnt)(*[m.data_ptr() for m in Ms])
+    n = int(Ms[0].shape[0])
+    need = lib.kfb_update_batched_workspace_bytes(cnt, hs, n)
+    if need == 0:
+        raise KfbError("kfb_update_batched_workspace_bytes rejected the bucket")
+    w = ws.get(need)
+    _check(lib.kfb_brand_update_batched(cnt, hs, ms, int(Ms[0].stride(0)), n, _ptr(w), int(w.numel()),
+                                        _stream()), "kfb_brand_update_batched")
+
+
+def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):
+    lib = load()
+    cnt = len(fgs)
+    hg = (_vp * cnt)(*[f.handle.value for f in fgs])
+    ha = (_vp * cnt)(*[f.handle.value for f in fas])
+    gp = (_vp * cnt)(*[g.data_ptr() for g in Gs])
+    sp = (_vp * cnt)(*[s.data_ptr() for s in Ss])
+    lg = (_dbl * cnt)(*[float(x) for x in lam_g])
+    la = (_dbl * cnt)(*[float(x) for x in lam_a])
+    need = lib.kfb_precondition_batched_workspace_bytes(cnt, hg, ha)
+    if need == 0:
+        raise KfbError("kfb_precondition_batched_workspace_bytes rejected the bucket")
+    w = ws.get(need)
+    _check(lib.kfb_precondition_batched(cnt, hg, ha, gp, int(Gs[0].stride(0)), sp, int(Ss[0].stride(0)), lg, la,
+                                        int(flags), _ptr(w), int(w.numel()), _stream()),
+           "kfb_precondition_batched")

@@ -1,0 +1,68 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, and its host-side argument checks behave (no device work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2210_08494_amd import kfb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "kfb.h")).read()
+    return sorted(set(re.findall(r"\b(kfb_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(kfb.LIB_PATH):
+        pytest.fail("libkfb.so is not built (run __graft_entry__.build())")
+    return kfb.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert set(names) == set(kfb.EXPORTS)
+
+
+def test_state_bytes_and_limits(lib):
+    b64 = lib.kfb_state_bytes(256, 32, 32, kfb.KFB_FP64)
+    b32 = lib.kfb_state_bytes(256, 32, 32, kfb.KFB_FP32)
+    assert b64 > b32 > 0
+    # two U buffers of ld x (r + n_max) plus eigenvalues and status
+    assert b64 >= 2 * 256 * 64 * 8
+    assert lib.kfb_state_bytes(256, 200, 64, kfb.KFB_FP64) == 0   # r + n_max > d
+    assert lib.kfb_state_bytes(256, 0, 0, kfb.KFB_FP64) == 0      # n_max = 0
+    assert lib.kfb_state_bytes(256, 32, 32, 7) == 0               # bad precision
+    assert lib.kfb_state_bytes(256, 224, 32, kfb.KFB_FP64) > 0    # r + n_max == d accepted
+
+
+def test_create_rejects_bad_arguments_without_touching_memory(lib):
+    h = ctypes.c_void_p()
+    # null buffer
+    rc = lib.kfb_state_create(ctypes.byref(h), 256, 32, 32, 0.95, kfb.KFB_FP64, None, 1 << 20, None)
+    assert rc == 1
+    # rho out of range (checked before any device call)
+    rc = lib.kfb_state_create(ctypes.byref(h), 256, 32, 32, 1.5, kfb.KFB_FP64, ctypes.c_void_p(256), 1 << 20,
+                              None)
+    assert rc == 1
+    # buffer too small
+    rc = lib.kfb_state_create(ctypes.byref(h), 256, 32, 32, 0.5, kfb.KFB_FP64, ctypes.c_void_p(256), 16, None)
+    assert rc == 2
+    # misaligned buffer
+    need = lib.kfb_state_bytes(256, 32, 32, kfb.KFB_FP64)
+    rc = lib.kfb_state_create(ctypes.byref(h), 256, 32, 32, 0.5, kfb.KFB_FP64, ctypes.c_void_p(260), need, None)
+    assert rc == 1
+
+
+def test_strerror_and_build_info(lib):
+    assert lib.kfb_strerror(0) == b"ok"
+    assert lib.kfb_strerror(2).startswith(b"buffer")
+    assert b"gfx950" in lib.kfb_build_info()
+    assert lib.kfb_destroy(None) == 1

@@ -1,0 +1,297 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (through the C-ABI).
+
+Tolerances: relative reconstruction / preconditioned-gradient error <= 1e-10
+(FP64 form), <= 1e-5 (FP32 form), <= 2e-2 (BF16-mixed form).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_08494_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-5, 2: 2e-2}
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _to_dev(x, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=_dev(), dtype=dtype)
+
+
+def _front_np(f):
+    import torch
+    torch.cuda.synchronize()
+    U, D = f.front()
+    return U.double().cpu().numpy(), D.double().cpu().numpy()
+
+
+def _batch(cfg, k, side, n, d, bias=False, prec=0):
+    x = synth.batch_for(cfg, k, side, n, d, bias=bias)
+    if prec == 2:
+        x = synth.to_bf16_values(x)  # the exact values a BF16 buffer holds, for both sides
+    return x
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+# ----------------------------------------------------------------------------
+# FP64 form: the paper's first workload shape (one FC layer, d = 256)
+# ----------------------------------------------------------------------------
+def test_fp64_layer_trajectory_vs_dense_definition(kfb):
+    import torch
+    d, r, n, rho, lam, steps = 256, 32, 32, 0.95, 0.1, 50
+    _announce(f"fp64 trajectory d={d} r={r} n={n} steps={steps}")
+    fa = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+    fg = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+    oa, og = oracle.DenseFactor(d, r, rho), oracle.DenseFactor(d, r, rho)
+    worst = dict(rec=0.0, D=0.0, orth=0.0, S=0.0)
+    for k in range(steps):
+        a, g = _batch(1, k, "A", n, d), _batch(1, k, "G", n, d)
+        fa.update(_to_dev(a, torch.float64))
+        fg.update(_to_dev(g, torch.float64))
+        oa.update(a.T)
+        og.update(g.T)
+        for f, o in ((fa, oa), (fg, og)):
+            U, D = _front_np(f)
+            V, lamv = o.modes()
+            assert U.shape[1] == o.kept
+            worst["rec"] = max(worst["rec"], oracle.e_rec_dense(U, D, o.X))
+            worst["D"] = max(worst["D"], oracle.e_D(D, lamv))
+            worst["orth"] = max(worst["orth"], oracle.e_orth(U))
+        if k % 10 == 9 or k == 0:
+            G = synth.grad_for(1, k, d, d)
+            Gd = _to_dev(G, torch.float64)
+            S = torch.empty_like(Gd)
+            kfb.precondition(fg, fa, Gd, S, lam, lam)
+            torch.cuda.synchronize()
+            S_ref = oracle.precondition_dense(og.X, oa.X, G, lam, lam)
+            worst["S"] = max(worst["S"], oracle.e_S(S.cpu().numpy(), S_ref))
+    _announce(f"  worst: {worst}")
+    assert worst["rec"] <= 1e-10 and worst["D"] <= 1e-10 and worst["S"] <= 1e-10
+    assert worst["orth"] <= 1e-11
+    assert fa.status() == 0 and fg.status() == 0
+
+
+def test_fp64_untruncated_reproduces_ea_factor(kfb):
+    # r + n grows to d: truncation never bites, so U D U^T must equal the EA sum exactly
+    import torch
+    d, n, r, rho = 256, 32, 224, 0.95
+    _announce("fp64 untruncated exactness")
+    f = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+    Ms = []
+    for k in range(8):
+        M = _batch(1, 100 + k, "G", n, d).T
+        Ms.append(M)
+        f.update(_to_dev(M.T, torch.float64))
+        E = sum(((1.0 if i == 0 else 1 - rho) * rho ** (k - i) / n) * (Ms[i] @ Ms[i].T) for i in range(k + 1))
+        U, D = _front_np(f)
+        assert U.shape[1] == min((k + 1) * n, d)
+        e = oracle.e_rec_dense(U, D, E)
+        assert e <= 1e-10, (k, e)
+        assert oracle.e_orth(U) <= 1e-10
+
+
+@pytest.mark.parametrize("d,r,n,steps", [(100, 7, 5, 7), (64, 3, 1, 12), (130, 40, 24, 5), (48, 40, 8, 3)])
+def test_fp64_ragged_shapes(kfb, d, r, n, steps):
+    # ragged tiles, padded Jacobi panels, n = 1, r + n = d
+    import torch
+    _announce(f"fp64 ragged d={d} r={r} n={n}")
+    rho = 0.9
+    f = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+    o = oracle.DenseFactor(d, r, rho)
+    for k in range(steps):
+        M = _batch(7, k, "A", n, d)
+        f.update(_to_dev(M, torch.float64))
+        o.update(M.T)
+        U, D = _front_np(f)
+        V, lamv = o.modes()
+        assert oracle.e_rec_dense(U, D, o.X) <= 1e-10
+        assert oracle.e_D(D, lamv) <= 1e-10
+
+
+def test_fp64_rho_zero_and_first_step(kfb):
+    import torch
+    d, r, n = 128, 16, 16
+    f = kfb.Factor(d, r, n, 0.0, kfb.KFB_FP64)
+    for k in range(3):
+        M = _batch(9, k, "G", n, d)
+        f.update(_to_dev(M, torch.float64))
+        U, D = _front_np(f)
+        s = np.linalg.svd(M.T, compute_uv=False)
+        top = np.sort(D)[::-1][:n]
+        assert np.allclose(top, s ** 2 / n, rtol=1e-10, atol=1e-12 * s[0] ** 2)
+
+
+def test_fp64_degenerate_batches(kfb):
+    import torch
+    d, r, n, rho = 96, 8, 6, 0.9
+    _announce("fp64 degenerate batches")
+    # duplicate columns: the residual is rank deficient
+    f = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+    o = oracle.DenseFactor(d, r, rho)
+    M = _batch(11, 0, "A", n, d)
+    M[3] = M[1]
+    f.update(_to_dev(M, torch.float64))
+    o.update(M.T)
+    U, D = _front_np(f)
+    assert oracle.e_rec_dense(U, D, o.X) <= 1e-10
+    assert f.status() & kfb.KFB_EV_CHOL_DEFICIENT
+    # a batch inside span(U): Z_perp = 0
+    M2 = (U[:, :3] @ np.random.default_rng(0).standard_normal((3, n))).T.copy()
+    f.update(_to_dev(M2, torch.float64))
+    o.update(M2.T)
+    U, D = _front_np(f)
+    assert oracle.e_rec_dense(U, D, o.X) <= 1e-10
+    # a zero batch
+    Z = np.zeros((n, d))
+    f.update(_to_dev(Z, torch.float64))
+    o.update(Z.T)
+    U, D = _front_np(f)
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(D))
+    assert oracle.e_rec_dense(U, D, o.X) <= 1e-10
+    # nonfinite input is reported, never crashes
+    Mn = _batch(11, 3, "A", n, d)
+    Mn[0, 0] = np.nan
+    g = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+    g.update(_to_dev(Mn, torch.float64))
+    assert g.status() & kfb.KFB_EV_NONFINITE
+
+
+def _oracle_state(d, r, n, rho, steps, cfg, side):
+    b = oracle.BrandFactor(d, r, rho)
+    for k in range(steps):
+        b.update(_batch(cfg, k, side, n, d).T)
+    return b
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_fp64_precondition_on_loaded_state(kfb, flags):
+    # the apply in isolation: both sides start from the same oracle-built state
+    import torch
+    dG, dA, r, n, rho = 200, 300, 20, 12, 0.95
+    _announce(f"fp64 precondition flags={flags}")
+    bg = _oracle_state(dG, r, n, rho, 4, 21, "G")
+    ba = _oracle_state(dA, r, n, rho, 4, 21, "A")
+    fg = kfb.Factor(dG, r, n, rho, kfb.KFB_FP64)
+    fa = kfb.Factor(dA, r, n, rho, kfb.KFB_FP64)
+    fg.load_state(_to_dev(bg.U, torch.float64), _to_dev(bg.D, torch.float64), step=4)
+    fa.load_state(_to_dev(ba.U, torch.float64), _to_dev(ba.D, torch.float64), step=4)
+    G = synth.grad_for(21, 0, dG, dA)
+    Gd = _to_dev(G, torch.float64)
+    S = torch.full_like(Gd, float("nan"))
+    lg, la = 0.05, 0.2
+    kfb.precondition(fg, fa, Gd, S, lg, la, flags=flags)
+    torch.cuda.synchronize()
+    UG, DG, UA, DA = bg.U, bg.D, ba.U, ba.D
+    if flags & 2:
+        UG, DG, UA, DA = UG[:, :r], DG[:r], UA[:, :r], DA[:r]
+    lgx, lax = lg, la
+    if flags & 1:
+        DG, lgx = oracle.spectrum_continuation(DG, lg)
+        DA, lax = oracle.spectrum_continuation(DA, la)
+    XG, XA = (UG * DG) @ UG.T, (UA * DA) @ UA.T
+    S_ref = oracle.precondition_dense(XG, XA, G, lgx, lax)
+    Sg = S.cpu().numpy()
+    assert oracle.e_S(Sg, S_ref) <= 1e-10
+    assert np.max(np.abs(Sg - S_ref)) <= 1e-10 * np.max(np.abs(S_ref))
+
+
+# ----------------------------------------------------------------------------
+# FP32 form
+# ----------------------------------------------------------------------------
+def test_fp32_trajectory_small(kfb):
+    import torch
+    d, r, n, rho, steps = 512, 64, 64, 0.95, 20
+    _announce(f"fp32 trajectory d={d} r={r} n={n}")
+    f = kfb.Factor(d, r, n, rho, kfb.KFB_FP32)
+    o = oracle.DenseFactor(d, r, rho)
+    worst = 0.0
+    for k in range(steps):
+        M = _batch(2, k, "A", n, d)
+        Mf = M.astype(np.float32).astype(np.float64)
+        f.update(_to_dev(Mf, torch.float32))
+        o.update(Mf.T)
+        U, D = _front_np(f)
+        worst = max(worst, oracle.e_rec_dense(U, D, o.X))
+    _announce(f"  worst e_rec {worst:.3e}")
+    assert worst <= TOL[1]
+
+
+def test_fp32_realistic_width_with_bias(kfb):
+    # FP32 at the paper-like width: d_in = 4097 (bias row), d_out = 4096, n = r = 256
+    import torch
+    dA, dG, n, r, rho, lam, steps = 4097, 4096, 256, 256, 0.95, 0.01, 4
+    _announce(f"fp32 realistic width dA={dA} dG={dG} steps={steps}")
+    fa = kfb.Factor(dA, r, n, rho, kfb.KFB_FP32)
+    fg = kfb.Factor(dG, r, n, rho, kfb.KFB_FP32)
+    oa, og = oracle.BrandFactor(dA, r, rho), oracle.BrandFactor(dG, r, rho)
+    for k in range(steps):
+        a = _batch(2, k, "A", n, dA, bias=True).astype(np.float32).astype(np.float64)
+        g = _batch(2, k, "G", n, dG).astype(np.float32).astype(np.float64)
+        fa.update(_to_dev(a, torch.float32))
+        fg.update(_to_dev(g, torch.float32))
+        oa.update(a.T)
+        og.update(g.T)
+        for f, o in ((fa, oa), (fg, og)):
+            U, D = _front_np(f)
+            e = oracle.e_rec_lowrank(U, D, o.U, o.D)
+            _announce(f"  step {k} e_rec {e:.3e}")
+            assert e <= TOL[1]
+    G = synth.grad_for(2, steps - 1, dG, dA).astype(np.float32)
+    Gd = _to_dev(G, torch.float32)
+    S = torch.empty_like(Gd)
+    kfb.precondition(fg, fa, Gd, S, lam, lam)
+    torch.cuda.synchronize()
+    S_ref = oracle.precondition_lowrank(og.U, og.D, oa.U, oa.D, G.astype(np.float64), lam, lam)
+    es = oracle.e_S(S.cpu().numpy(), S_ref)
+    _announce(f"  e_S {es:.3e}")
+    assert es <= TOL[1]
+
+
+# ----------------------------------------------------------------------------
+# BF16-mixed form
+# ----------------------------------------------------------------------------
+def test_mixed_trajectory_small(kfb):
+    import torch
+    d, r, n, rho, steps = 1024, 128, 128, 0.95, 12
+    _announce(f"mixed trajectory d={d} r={r} n={n}")
+    f = kfb.Factor(d, r, n, rho, kfb.KFB_BF16_MIXED)
+    o = oracle.BrandFactor(d, r, rho)
+    worst = 0.0
+    for k in range(steps):
+        M = _batch(3, k, "A", n, d, prec=2)
+        f.update(_to_dev(M, torch.bfloat16))
+        o.update(M.T)
+        U, D = _front_np(f)
+        worst = max(worst, oracle.e_rec_lowrank(U, D, o.U, o.D))
+    _announce(f"  worst e_rec {worst:.3e} orth {oracle.e_orth(U):.3e}")
+    assert worst <= TOL[2]
+
+
+def test_batched_equals_single(kfb):
+    import torch
+    d, r, n, rho = 384, 32, 32, 0.95
+    for prec, dt in ((kfb.KFB_FP64, torch.float64), (kfb.KFB_FP32, torch.float32),
+                     (kfb.KFB_BF16_MIXED, torch.bfloat16)):
+        _announce(f"batched == single, prec={prec}")
+        single = [kfb.Factor(d, r, n, rho, prec) for _ in range(3)]
+        grouped = [kfb.Factor(d, r, n, rho, prec) for _ in range(3)]
+        ws = kfb.Workspace()
+        for k in range(3):
+            Ms = [_to_dev(_batch(4, k, "A" if i % 2 else "G", n, d, prec=prec), dt) for i in range(3)]
+            for f, M in zip(single, Ms):
+                f.update(M)
+            kfb.update_batched(grouped, Ms, ws)
+        torch.cuda.synchronize()
+        for a, b in zip(single, grouped):
+            Ua, Da = a.front()
+            Ub, Db = b.front()
+            assert torch.equal(Ua, Ub) and torch.equal(Da, Db)
