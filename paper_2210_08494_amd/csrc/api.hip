@@ -62,7 +62,7 @@ struct UpdPlan {
   int64_t d, ldu, ldm;
   int r, n, N, Np, bw;
   int ksP, ksG;
-  int64_t oZ, oZb, oP, oP2, oGram, oR1, oX1, oR2, oX2, oRt, oPart, oB, oV, oW, oLam, oRank, oCnt;
+  int64_t oZ, oZb, oP, oP2, oGram, oR1, oX1, oR2, oX2, oR3, oRt, oPart, oB, oV, oW, oLam, oRank, oCnt;
   size_t per_problem;
 };
 
@@ -89,6 +89,7 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   p->oP2 = take((size_t)(r > 0 ? r : 1) * n * sizeof(typename T::P));
   const size_t nn = (size_t)n * n * sizeof(typename T::G);
   p->oGram = take(nn); p->oR1 = take(nn); p->oX1 = take(nn); p->oR2 = take(nn); p->oX2 = take(nn);
+  p->oR3 = take(nn);
   p->oRt = take(nn);
   const size_t partP = (size_t)p->ksP * (r > 0 ? r : 1) * n * sizeof(typename T::P);
   const size_t partG = (size_t)p->ksG * n * n * sizeof(typename T::G);
@@ -96,7 +97,7 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   const size_t core = (size_t)p->Np * p->Np * sizeof(typename T::Core);
   p->oB = take(core); p->oV = take(core);
   p->oW = take((size_t)p->N * p->N * sizeof(typename T::W));
-  p->oLam = take((size_t)p->Np * sizeof(typename T::Core));
+  p->oLam = take((size_t)2 * p->Np * sizeof(typename T::Core));  // eigenvalues, then 1/||V_j||
   p->oRank = take((size_t)p->Np * 4);
   p->oCnt = take((size_t)MAX_SWEEPS * 4);
   p->per_problem = o;
@@ -139,43 +140,56 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   } else {
     KFB_TRY((copy2d<TZ, TM>(drecs, nrec, op(WS, p.oZ, 1, d), op(M_IN, 0, 1, ldm), (int)d, n, s)));
   }
-  // CholeskyQR2 of Z (Algorithm 3: thin QR of the residual)
-  const double tau = PR == KFB_FP32 ? 64.0 * 1.1920929e-07 : 64.0 * 2.220446049250313e-16;
+  // Thin QR of the residual (Algorithm 3) by CholeskyQR: two passes when the
+  // Gram is formed in FP64; in the FP32 form a shifted first pass (shifted
+  // CholeskyQR3) keeps the factorisation stable for ill-conditioned residuals.
+  const bool fp32_chol = sizeof(TG) == 4;
+  const int passes = fp32_chol ? 3 : 2;
+  const double ueps = fp32_chol ? 1.1920929e-07 : 2.220446049250313e-16;
+  const double tau = 64.0 * ueps;
   int64_t srcZ = p.oZ, dstZ = p.oZb;
-  const int64_t oR[2] = {p.oR1, p.oR2}, oX[2] = {p.oX1, p.oX2};
-  for (int pass = 0; pass < 2; ++pass) {
+  const int64_t oR[3] = {p.oR1, p.oR2, p.oR3}, oX[2] = {p.oX1, p.oX2};
+  for (int pass = 0; pass < passes; ++pass) {
     GemmArgs gg;
     gg.A = op(WS, srcZ, d, 1); gg.B = op(WS, srcZ, 1, d); gg.C = op(WS, p.oGram, 1, n);
     gg.m = n; gg.n = n; gg.k = (int)d; gg.ksplit = p.ksG; gg.Part = op(WS, p.oPart, 1, n);
     KFB_TRY((gemm<TZ, TZ, TG, TG, TG>(drecs, nrec, gg, s)));
     CholArgs ca;
-    ca.n = n; ca.off_gram = p.oGram; ca.off_R = oR[pass]; ca.off_Rinv = oX[pass]; ca.off_rowbuf = 0;
+    ca.n = n; ca.off_gram = p.oGram; ca.off_R = oR[pass]; ca.off_Rinv = oX[pass & 1]; ca.off_rowbuf = 0;
     ca.tau_rel = tau;
+    ca.shift_rel = (fp32_chol && pass == 0) ? 11.0 * ((double)d * n + (double)n * (n + 1)) * ueps : 0.0;
     KFB_TRY(chol_inv<TG>(drecs, nrec, ca, s));
     GemmArgs q;
-    q.A = op(WS, srcZ, 1, d); q.B = op(WS, oX[pass], 1, n); q.C = op(WS, dstZ, 1, d);
+    q.A = op(WS, srcZ, 1, d); q.B = op(WS, oX[pass & 1], 1, n); q.C = op(WS, dstZ, 1, d);
     q.m = (int)d; q.n = n; q.k = n;
     KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
     const int64_t tmp = srcZ; srcZ = dstZ; dstZ = tmp;
   }
-  // after two passes Q sits in oZ again; R = R2 R1
+  const int64_t oQ = srcZ;  // the orthonormal Q after the last pass
+  // R = R_last ... R_1 (products of upper-triangular factors)
   {
     GemmArgs rr;
     rr.A = op(WS, p.oR2, 1, n); rr.B = op(WS, p.oR1, 1, n); rr.C = op(WS, p.oRt, 1, n);
     rr.m = n; rr.n = n; rr.k = n;
     KFB_TRY((gemm<TG, TG, TG, TG, TG>(drecs, nrec, rr, s)));
+    if (passes == 3) {
+      GemmArgs r3 = rr;
+      r3.A = op(WS, p.oR3, 1, n); r3.B = op(WS, p.oRt, 1, n); r3.C = op(WS, p.oGram, 1, n);
+      KFB_TRY((gemm<TG, TG, TG, TG, TG>(drecs, nrec, r3, s)));
+    }
   }
+  const int64_t oRfin = passes == 3 ? p.oGram : p.oRt;
   // core square factor and Jacobi eigensolve (Algorithm 3: EVD of M_S)
   CoreArgs co;
   co.r = r; co.n = n; co.N = N; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = r > 0 ? p.oP2 : -1;
-  co.off_R = p.oRt; co.off_B = p.oB; co.off_V = p.oV;
+  co.off_R = oRfin; co.off_B = p.oB; co.off_V = p.oV;
   KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, nrec, co, s)));
   KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
   JacArgs ja;
   ja.Np = p.Np; ja.N = N; ja.b = p.bw; ja.max_sweeps = MAX_SWEEPS;
   ja.off_B = p.oB; ja.off_V = p.oV; ja.off_cnt = p.oCnt;
   const double eps = sizeof(TC) == 8 ? 2.220446049250313e-16 : 1.1920929e-07;
-  ja.tol = eps * sqrt((double)N) * (sizeof(TC) == 8 ? 1.0 : 4.0);
+  ja.tol = eps * sqrt((double)N);
   const int nb = p.Np / p.bw;
   if (nb == 2) {
     KFB_TRY(jacobi_round<TC>(drecs, nrec, ja, 0, 0, s));
@@ -190,8 +204,8 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   // rotation: U' = [U_r Q] W  (Algorithm 3), into the back buffer
   GemmArgs ro;
   ro.A = op(U_FRONT, 0, 1, ldu);
-  ro.A.slot2 = WS; ro.A.off2 = p.oZ; ro.A.rs2 = 1; ro.A.cs2 = d; ro.A.split = r;
-  if (r == 0) ro.A = op(WS, p.oZ, 1, d);
+  ro.A.slot2 = WS; ro.A.off2 = oQ; ro.A.rs2 = 1; ro.A.cs2 = d; ro.A.split = r;
+  if (r == 0) ro.A = op(WS, oQ, 1, d);
   ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
   ro.m = (int)d; ro.n = N; ro.k = N;
   KFB_TRY((gemm<TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));

@@ -33,6 +33,7 @@ struct CholArgs {
   int64_t off_gram, off_R, off_Rinv;  // n x n column-major in WS
   int64_t off_rowbuf;                  // n elements scratch
   double tau_rel;                      // pivot tolerance relative to max diagonal
+  double shift_rel;                    // diagonal shift relative to trace(W) (shifted CholeskyQR)
 };
 template <typename T>
 hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s);

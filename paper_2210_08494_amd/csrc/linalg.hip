@@ -40,23 +40,26 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
   T* X = at<T>(rec, WS, a.off_Rinv);
   __shared__ T row[CHOL_MAXN];
   __shared__ T red[CHOL_NT / 64];
+  __shared__ T redt[CHOL_NT / 64];
   __shared__ int deficient, nonfinite;
   const int t = threadIdx.x;
   if (t == 0) { deficient = 0; nonfinite = 0; }
   __syncthreads();
 
   // max diagonal (tolerance scale) and finiteness (v - v is 0 only for finite v)
-  T mx = T(0);
+  T mx = T(0), tr = T(0);
   for (int i = t; i < n; i += CHOL_NT) {
     const T v = Wg[i + (int64_t)i * n];
     if (!(v - v == T(0))) nonfinite = 1;
     mx = v > mx ? v : mx;
+    tr += v;
   }
   for (int off = 32; off > 0; off >>= 1) {
     const T o = __shfl_xor(mx, off);
     mx = o > mx ? o : mx;
+    tr += __shfl_xor(tr, off);
   }
-  if ((t & 63) == 0) red[t >> 6] = mx;
+  if ((t & 63) == 0) { red[t >> 6] = mx; redt[t >> 6] = tr; }
   // copy upper triangle, zero the rest
   for (int64_t e = t; e < (int64_t)n * n; e += CHOL_NT) {
     const int i = (int)(e % n), j = (int)(e / n);
@@ -65,12 +68,20 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
   }
   __syncthreads();
   if (t == 0) {
-    T m = red[0];
-    for (int w = 1; w < CHOL_NT / 64; ++w) m = red[w] > m ? red[w] : m;
+    T m = red[0], tt = redt[0];
+    for (int w = 1; w < CHOL_NT / 64; ++w) { m = red[w] > m ? red[w] : m; tt += redt[w]; }
     red[0] = m;
+    redt[0] = tt;
   }
   __syncthreads();
   const T tau = T(a.tau_rel) * red[0];
+  // shifted CholeskyQR: factor W + s I (s = shift_rel * trace W); Z = Q1 R1 still holds
+  // exactly with Q1 = Z R1^{-1}, which is then well conditioned for the next passes
+  if (a.shift_rel > 0.0) {
+    const T sh = T(a.shift_rel) * redt[0];
+    for (int i = t; i < n; i += CHOL_NT) R[i + (int64_t)i * n] += sh;
+    __syncthreads();
+  }
 
   // right-looking Cholesky, row by row of R
   for (int j = 0; j < n; ++j) {
@@ -361,8 +372,13 @@ hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, 
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: eigenvalues are the squared column norms of B V; sort descending
-// (ties by column index), write D, and gather W = V with permuted columns.
+// Finalize.  B and V received the same plane rotations, so B = L^T V up to
+// rounding.  Rotations computed in floating point are orthogonal only to a
+// few ulps, and over a full iteration the column norms of both drift by the
+// same factor (visible in FP32); the eigenvalue estimate ||B_j||^2 / ||V_j||^2
+// cancels that factor and W takes the normalised columns of V.  Eigenvalues
+// are sorted descending (ties by column index); D and the permuted,
+// normalised W are written.
 // ---------------------------------------------------------------------------
 constexpr int FIN_MAXN = 4096;
 
@@ -371,17 +387,30 @@ __global__ __launch_bounds__(256) void fin_sort_kernel(const Rec* __restrict__ r
   const Rec& rec = recs[blockIdx.x];
   const int N = a.N, Np = a.Np;
   const TCore* Bm = at<const TCore>(rec, WS, a.off_B);
+  const TCore* Vm = at<const TCore>(rec, WS, a.off_V);
   TCore* lam = at<TCore>(rec, WS, a.off_lam);
+  TCore* vscale = lam + Np;
   int32_t* rank = at<int32_t>(rec, WS, a.off_rank);
   TD* Dout = at<TD>(rec, D_BACK, 0);
   __shared__ TCore sl[FIN_MAXN];
   const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
   for (int j = wv; j < N; j += 4) {
     const TCore* col = Bm + (int64_t)j * Np;
-    TCore s = TCore(0);
-    for (int i = ln; i < Np; i += 64) s = fma(col[i], col[i], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (ln == 0) sl[j] = s;
+    const TCore* vc = Vm + (int64_t)j * Np;
+    TCore sb = TCore(0), sv = TCore(0);
+    for (int i = ln; i < Np; i += 64) {
+      sb = fma(col[i], col[i], sb);
+      sv = fma(vc[i], vc[i], sv);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      sb += __shfl_xor(sb, off);
+      sv += __shfl_xor(sv, off);
+    }
+    if (ln == 0) {
+      const bool ok = sv > TCore(0);
+      sl[j] = ok ? sb / sv : sb;
+      vscale[j] = ok ? TCore(1) / dev_sqrt(sv) : TCore(1);
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < N; j += 256) {
@@ -407,12 +436,13 @@ __global__ __launch_bounds__(256) void fin_gather_kernel(const Rec* __restrict__
   const int N = a.N, Np = a.Np;
   const TCore* Vm = at<const TCore>(rec, WS, a.off_V);
   const int32_t* rank = at<const int32_t>(rec, WS, a.off_rank);
+  const TCore* vscale = at<const TCore>(rec, WS, a.off_lam) + Np;
   TW* W = at<TW>(rec, WS, a.off_W);
   const int64_t tot = (int64_t)N * N;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % N), j = (int)(e / N);
-    W[i + (int64_t)rank[j] * N] = TW(Vm[i + (int64_t)j * Np]);
+    W[i + (int64_t)rank[j] * N] = TW(Vm[i + (int64_t)j * Np] * vscale[j]);
   }
 }
 
