@@ -53,7 +53,7 @@ template <> struct Ty<KFB_BF16_MIXED> {
   typedef double G, Core, D;
 };
 
-constexpr int MAX_SWEEPS = 24;
+constexpr int MAX_SWEEPS = 20;
 
 // ---------------------------------------------------------------------------
 // Brand-update plan: workspace layout of one problem for a shape bucket.

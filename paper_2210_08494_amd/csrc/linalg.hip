@@ -209,24 +209,28 @@ hipError_t assemble_core(const Rec* recs, int nrec, const CoreArgs& a, hipStream
 // The Np columns are cut into nb = Np / BW blocks.  A sweep is a round-robin
 // tournament over the blocks (circle method, nb - 1 rounds of nb / 2 disjoint
 // block pairs); one launch performs one round for all problems, one workgroup
-// per block pair.  The workgroup stages the 2*BW columns of B and V of its
-// pair in LDS and applies plane rotations to every column pair not yet met in
-// this sweep: in round 0 all pairs inside the panel (a tournament over its
-// 2*BW columns), in later rounds the BW*BW cross pairs.  Each step runs BW
-// disjoint rotations, one per group of 256/BW lanes.
-//
-// Rotation for a column pair (a, b) with alpha = a.a, beta = b.b, gamma = a.b:
-// skip if |gamma| <= tol * sqrt(alpha * beta); otherwise zeta = (beta - alpha)
-// / (2 gamma), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
-// s = c t, and (a, b) <- (c a - s b, s a + c b), which makes a.b = 0.
+// per block pair.  A visit of the pair (I, J) works on the panel
+// C = [B_I B_J] (Np x P, P = 2 BW) held in LDS:
+//   1. G = C^T C (P x P Gram of the panel columns);
+//   2. one cyclic sweep of two-sided Jacobi on G (P - 1 steps of P/2 disjoint
+//      plane rotations, G <- J^T G J), accumulating Z = J_1 J_2 ...;
+//   3. C <- C Z and [V_I V_J] <- [V_I V_J] Z.
+// The rotations are exactly those scalar one-sided Jacobi would apply to the
+// panel columns, but their parameters come from the small Gram instead of
+// long dot products, and the panel update is a dense product.  A rotation of
+// columns (p, q) is skipped when |G_pq| <= tol sqrt(G_pp G_qq); otherwise
+// zeta = (G_qq - G_pp) / (2 G_pq), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1/sqrt(1 + t^2), s = c t, and (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q).
+// A visit without any rotation leaves C and V untouched.
 //
 // Convergence: every workgroup adds its rotation count to cnt[sweep]; a launch
-// of sweep s > 0 returns at once when cnt[s-1] == 0 (no rotation in the
-// previous full sweep).  When one panel holds every column (nb == 2) the
-// kernel runs all sweeps itself.
+// of sweep s > 0 returns at once when cnt[s-1] == 0 (no rotation anywhere in
+// the previous sweep).  When one panel holds every column (nb == 2) the
+// workgroup repeats steps 1-3 itself until a pass rotates nothing.
 // ---------------------------------------------------------------------------
 constexpr int JAC_NT = 256;
-constexpr int JAC_LDS_BYTES = 128 * 1024;
+constexpr int JAC_LDS_BYTES = 128 * 1024;  // panel budget; G and Z come on top
+constexpr int JAC_LDS_MAX = 156 * 1024;    // whole dynamic allocation (160 KB per CU on gfx950)
 
 __device__ __forceinline__ void tour_pair(int P, int st, int q, int* x, int* y) {
   // circle method over P players, step st in [0, P-1), pair q in [0, P/2)
@@ -235,12 +239,126 @@ __device__ __forceinline__ void tour_pair(int P, int st, int q, int* x, int* y) 
   else { *x = (st + q) % R; *y = (st - q + R) % R; }
 }
 
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double jac_d4;
+
+// G = C^T C for the panel C (Np x P, column stride LDP) into G (row-major P x P).
+// FP64 with P >= 16: 16x16 tiles on MFMA (upper triangle, one wave per tile
+// slot); otherwise 4x4 register blocks on FMA with rows split across lanes.
+template <typename T, int P>
+__device__ __forceinline__ void jac_gram(const T* pb, int Np, int LDP, T* G, int t) {
+  if constexpr (sizeof(T) == 8 && P >= 16) {
+    constexpr int NT16 = P / 16;
+    constexpr int NTILE = NT16 * (NT16 + 1) / 2;
+    const int w = t / 64, l = t % 64;
+    for (int tile = w; tile < NTILE; tile += JAC_NT / 64) {
+      int ti = 0, rem = tile;
+      while (rem >= NT16 - ti) { rem -= NT16 - ti; ++ti; }
+      const int tj = ti + rem;
+      jac_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      const T* ca = pb + (size_t)(ti * 16 + (l % 16)) * LDP + (l / 16);
+      const T* cb = pb + (size_t)(tj * 16 + (l % 16)) * LDP + (l / 16);
+      for (int k0 = 0; k0 < Np; k0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k0], cb[k0], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ti * 16 + l / 16 + 4 * v, j = tj * 16 + l % 16;
+        G[i * P + j] = acc[v];
+        G[j * P + i] = acc[v];
+      }
+    }
+  } else {
+    constexpr int NBLK = (P / 4) * (P / 4);
+    constexpr int RS = JAC_NT / NBLK;
+    static_assert(RS >= 1 && RS <= 64 && (RS & (RS - 1)) == 0, "bad Gram split");
+    const int blk = t / RS, rs = t % RS;
+    const int bi = blk / (P / 4), bj = blk % (P / 4);
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+    if (bi <= bj) {
+      for (int row = rs; row < Np; row += RS) {
+        T x[4], y[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = pb[(size_t)(bi * 4 + i) * LDP + row];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j] = pb[(size_t)(bj * 4 + j) * LDP + row];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
+      }
+    }
+#pragma unroll
+    for (int off = RS / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += __shfl_xor(acc[i][j], off);
+    if (rs == 0 && bi <= bj) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          G[(bi * 4 + i) * P + (bj * 4 + j)] = acc[i][j];
+          G[(bj * 4 + j) * P + (bi * 4 + i)] = acc[i][j];
+        }
+    }
+  }
+}
+
+// X <- X Z for a panel X (Np x P) read through xin(row, k) and written
+// through xout(row, j, value); Z row-major P x P in LDS.  FP64 with P >= 16
+// runs on MFMA as (Z^T X^T), so each lane owns one row and stores coalesce;
+// otherwise one row per thread with P independent FMA sums.
+template <typename T, int P, typename In, typename Out>
+__device__ __forceinline__ void jac_apply(int Np, const T* Z, int t, In xin, Out xout) {
+  if constexpr (sizeof(T) == 8 && P >= 16) {
+    constexpr int NT16 = P / 16;
+    const int w = t / 64, l = t % 64;
+    for (int rb = w; rb < Np / 16; rb += JAC_NT / 64) {
+      jac_d4 acc[NT16];
+#pragma unroll
+      for (int c = 0; c < NT16; ++c) acc[c] = jac_d4{0.0, 0.0, 0.0, 0.0};
+      const int row = rb * 16 + (l % 16);
+#pragma unroll 2
+      for (int k0 = 0; k0 < P; k0 += 4) {
+        const double xb = xin(row, k0 + l / 16);
+#pragma unroll
+        for (int c = 0; c < NT16; ++c) {
+          const double za = Z[(k0 + l / 16) * P + c * 16 + (l % 16)];
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb, acc[c], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NT16; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xout(rb * 16 + (l % 16), c * 16 + l / 16 + 4 * v, acc[c][v]);
+    }
+  } else {
+    for (int row = t; row < Np; row += JAC_NT) {
+      T acc[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] = T(0);
+#pragma unroll 1
+      for (int k = 0; k < P; ++k) {
+        const T xk = xin(row, k);
+        const T* zr = Z + k * P;
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[j] = fma(xk, zr[j], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) xout(row, j, acc[j]);
+    }
+  }
+}
+
 template <typename T, int BW>
 __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
                                                         int round) {
   extern __shared__ __attribute__((aligned(16))) unsigned char jac_smem[];
-  constexpr int PC = 2 * BW;       // panel columns
-  constexpr int GL = JAC_NT / BW;  // lanes per rotation group
+  constexpr int P = 2 * BW;  // panel columns
+  constexpr int NP2 = P / 2;
   const Rec& rec = recs[blockIdx.y];
   int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
   const int Np = a.Np;
@@ -253,90 +371,126 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   if (single) { I = 0; J = 1; }
   else tour_pair(nb, round, blockIdx.x, &I, &J);
 
-  T* pb = reinterpret_cast<T*>(jac_smem);  // B panel: column c at pb + c*Np
-  T* pv = pb + (size_t)PC * Np;             // V panel
-  __shared__ int wg_rot;
+  const int LDP = Np + 16 / (int)sizeof(T);  // padded column stride, keeps 16-byte alignment
+  T* pb = reinterpret_cast<T*>(jac_smem);   // panel: column c at pb + c*LDP
+  T* G = pb + (size_t)P * LDP;               // G[i*P + j]
+  T* Z = G + P * P;                          // Z(i, j) at Z[i*P + j] (row-major)
+  T* rc = Z + P * P;                         // rotation c, s per pair of a step
+  T* rsn = rc + NP2;
+  __shared__ int pp[P / 2], qq[P / 2];
+  __shared__ int wg_rot, pass_rot, any_rot;
+  const int t = threadIdx.x;
+  if (t == 0) { wg_rot = 0; any_rot = 0; }
 
-  for (int e = threadIdx.x; e < PC * Np; e += JAC_NT) {
-    const int c = e / Np, row = e - c * Np;
-    const int gc = c < BW ? I * BW + c : J * BW + (c - BW);
-    pb[e] = Bm[row + (int64_t)gc * Np];
-    pv[e] = Vm[row + (int64_t)gc * Np];
+  auto gcol = [&](int c) { return c < BW ? I * BW + c : J * BW + (c - BW); };
+  // ---- load the panel (16-byte vectors, coalesced along the rows)
+  constexpr int VE = 16 / sizeof(T);
+  typedef __attribute__((__vector_size__(16))) T vec_t;
+  for (int c = 0; c < P; ++c) {
+    const vec_t* src = reinterpret_cast<const vec_t*>(Bm + (int64_t)gcol(c) * Np);
+    vec_t* dst = reinterpret_cast<vec_t*>(pb + (size_t)c * LDP);
+    for (int v = t; v < Np / VE; v += JAC_NT) dst[v] = src[v];
   }
-  const int g = threadIdx.x / GL, l = threadIdx.x % GL;
   const T tol = T(a.tol);
   int sw = sweep;
   for (;;) {
-    if (threadIdx.x == 0) wg_rot = 0;
+    if (t == 0) pass_rot = 0;
     __syncthreads();
+    // ---- 1. Gram of the panel
+    jac_gram<T, P>(pb, Np, LDP, G, t);
+    for (int e = t; e < P * P; e += JAC_NT) Z[e] = (e % P == e / P) ? T(1) : T(0);
+    __syncthreads();
+    // ---- 2. plane rotations on G (G <- J^T G J), accumulating Z <- Z J.
+    // Round 0 of a sweep (and the single-panel case) runs a full tournament over
+    // the P columns; later rounds only the BW x BW pairs across the two blocks.
     const bool full = single || round == 0;
-    const int nsteps = full ? PC - 1 : BW;
+    const int nsteps = full ? P - 1 : BW;
     for (int st = 0; st < nsteps; ++st) {
-      int ci, cj;
-      if (full) tour_pair(PC, st, g, &ci, &cj);
-      else { ci = g; cj = BW + (g + st) % BW; }
-      T* x = pb + (size_t)ci * Np;
-      T* y = pb + (size_t)cj * Np;
-      T al = T(0), be = T(0), ga = T(0);
-      for (int row = l; row < Np; row += GL) {
-        const T u = x[row], v = y[row];
-        al = fma(u, u, al);
-        be = fma(v, v, be);
-        ga = fma(u, v, ga);
-      }
-#pragma unroll
-      for (int off = GL / 2; off > 0; off >>= 1) {
-        al += __shfl_xor(al, off);
-        be += __shfl_xor(be, off);
-        ga += __shfl_xor(ga, off);
-      }
-      if (ga != T(0) && fabs(ga) > tol * dev_sqrt(al * be)) {
-        const T zeta = (be - al) / (T(2) * ga);
-        const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + dev_sqrt(T(1) + zeta * zeta));
-        const T c = T(1) / dev_sqrt(T(1) + tt * tt);
-        const T s = c * tt;
-        for (int row = l; row < Np; row += GL) {
-          const T u = x[row], v = y[row];
-          x[row] = c * u - s * v;
-          y[row] = s * u + c * v;
+      if (t < NP2) {
+        int p, q;
+        if (full) tour_pair(P, st, t, &p, &q);
+        else { p = t; q = BW + (t + st) % BW; }
+        const T gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
+        T c = T(1), s = T(0);
+        if (gpq != T(0) && fabs(gpq) > tol * dev_sqrt(gpp * gqq)) {
+          const T aa = gqq - gpp, bb = T(2) * gpq;
+          const T rr = dev_sqrt(aa * aa + bb * bb);
+          const T tt = (aa >= T(0) ? bb : -bb) / (fabs(aa) + rr);
+          c = T(1) / dev_sqrt(T(1) + tt * tt);
+          s = c * tt;
+          atomicAdd(&pass_rot, 1);
         }
-        T* xv = pv + (size_t)ci * Np;
-        T* yv = pv + (size_t)cj * Np;
-        for (int row = l; row < Np; row += GL) {
-          const T u = xv[row], v = yv[row];
-          xv[row] = c * u - s * v;
-          yv[row] = s * u + c * v;
-        }
-        if (l == 0) atomicAdd(&wg_rot, 1);
+        rc[t] = c;
+        rsn[t] = s;
+        pp[t] = p;
+        qq[t] = q;
+      }
+      __syncthreads();
+      // each 2x2 block (pair A rows, pair B columns) of G: J_A^T G_AB J_B
+      for (int e = t; e < NP2 * NP2; e += JAC_NT) {
+        const int ia = e / NP2, ib = e % NP2;
+        const T sa = rsn[ia], sb = rsn[ib];
+        if (sa == T(0) && sb == T(0)) continue;
+        const T ca = rc[ia], cb = rc[ib];
+        const int pa = pp[ia], qa = qq[ia], pbb = pp[ib], qb = qq[ib];
+        const T g00 = G[pa * P + pbb], g01 = G[pa * P + qb], g10 = G[qa * P + pbb], g11 = G[qa * P + qb];
+        const T r00 = cb * g00 - sb * g01, r01 = sb * g00 + cb * g01;
+        const T r10 = cb * g10 - sb * g11, r11 = sb * g10 + cb * g11;
+        G[pa * P + pbb] = ca * r00 - sa * r10;
+        G[qa * P + pbb] = sa * r00 + ca * r10;
+        G[pa * P + qb] = ca * r01 - sa * r11;
+        G[qa * P + qb] = sa * r01 + ca * r11;
+      }
+      for (int e = t; e < NP2 * P; e += JAC_NT) {
+        const int ia = e / P, i = e % P;
+        const T sa = rsn[ia];
+        if (sa == T(0)) continue;
+        const T ca = rc[ia];
+        const int pa = pp[ia], qa = qq[ia];
+        const T zp = Z[i * P + pa], zq = Z[i * P + qa];
+        Z[i * P + pa] = ca * zp - sa * zq;
+        Z[i * P + qa] = sa * zp + ca * zq;
       }
       __syncthreads();
     }
-    if (!single) {
-      if (threadIdx.x == 0 && wg_rot > 0) atomicAdd(&cnt[sweep], wg_rot);
-      break;
+    const int nrot = pass_rot;
+    if (nrot > 0) {
+      // ---- 3. C <- C Z in LDS, then V_panel <- V_panel Z in global memory
+      jac_apply<T, P>(
+          Np, Z, t, [&](int row, int k) { return pb[(size_t)k * LDP + row]; },
+          [&](int row, int j, T v) { pb[(size_t)j * LDP + row] = v; });
+      jac_apply<T, P>(
+          Np, Z, t, [&](int row, int k) { return Vm[row + (int64_t)gcol(k) * Np]; },
+          [&](int row, int j, T v) { Vm[row + (int64_t)gcol(j) * Np] = v; });
+      if (t == 0) { wg_rot += nrot; any_rot = 1; }
     }
-    const int nrot = wg_rot;
-    if (threadIdx.x == 0) cnt[sw] = nrot;
-    ++sw;
     __syncthreads();
+    if (!single) break;
+    if (t == 0) cnt[sw] = nrot;
+    ++sw;
     if (nrot == 0 || sw >= a.max_sweeps) break;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < PC * Np; e += JAC_NT) {
-    const int c = e / Np, row = e - c * Np;
-    const int gc = c < BW ? I * BW + c : J * BW + (c - BW);
-    Bm[row + (int64_t)gc * Np] = pb[e];
-    Vm[row + (int64_t)gc * Np] = pv[e];
+  if (any_rot) {
+    for (int c = 0; c < P; ++c) {
+      vec_t* dst = reinterpret_cast<vec_t*>(Bm + (int64_t)gcol(c) * Np);
+      const vec_t* src = reinterpret_cast<const vec_t*>(pb + (size_t)c * LDP);
+      for (int v = t; v < Np / VE; v += JAC_NT) dst[v] = src[v];
+    }
   }
+  if (!single && t == 0 && wg_rot > 0) atomicAdd(&cnt[sweep], wg_rot);
 }
 
 int jacobi_pick_block(int N, int elem_bytes, int* Np_out) {
-  // largest BW in {32,16,8,4} with both staged panels (2 x Np x 2BW) in LDS
+  // largest panel (P = 2 BW <= 64 columns) whose Np x P slice fits the LDS budget
   const int cands[4] = {32, 16, 8, 4};
   for (int ci = 0; ci < 4; ++ci) {
     const int bw = cands[ci];
     const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
-    if ((size_t)2 * Np * 2 * bw * elem_bytes <= (size_t)JAC_LDS_BYTES) {
+    const size_t P = 2 * (size_t)bw;
+    const size_t ldp = (size_t)Np + 16 / elem_bytes;
+    if ((size_t)Np * P * elem_bytes <= (size_t)JAC_LDS_BYTES &&
+        (ldp * P + 2 * P * P + P) * elem_bytes <= (size_t)JAC_LDS_MAX) {
       *Np_out = Np;
       return bw;
     }
@@ -347,12 +501,13 @@ int jacobi_pick_block(int N, int elem_bytes, int* Np_out) {
 template <typename T, int BW>
 static hipError_t jac_launch(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round,
                              hipStream_t s) {
+  constexpr int P = 2 * BW;
   const int nb = a.Np / BW;
-  const size_t lds = (size_t)2 * a.Np * 2 * BW * sizeof(T);
+  const size_t lds = ((size_t)(a.Np + 16 / sizeof(T)) * P + 2 * P * P + P) * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)jacobi_kernel<T, BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        JAC_LDS_BYTES);
+    (void)hipFuncSetAttribute((const void*)jacobi_kernel<T, BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              JAC_LDS_MAX);
     attr_set = true;
   }
   hipLaunchKernelGGL((jacobi_kernel<T, BW>), dim3(nb / 2, nrec), dim3(JAC_NT), lds, s, recs, a, sweep,
