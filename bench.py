@@ -1,0 +1,249 @@
+"""Benchmark of the Brand-update K-factor path on one MI355X.
+
+Workload (the headline shape): a 24-layer MLP-like stack with both K-factors
+of every layer at width d = 4096 (48 independent factor states), truncation
+rank r = 256, batch width n = 256, rho = 0.95, lambda = 0.01, in the
+BF16-mixed precision form.  One step is one pass of the whole hot path over
+one synthetic batch per state: a grouped Brand update of all 48 states
+(truncate, projection, residual, CholeskyQR, core eigensolve, rotation) plus a
+grouped two-sided preconditioning of all 24 layer gradients.  All inputs are
+generated on the device before the timed region.
+
+Reported: B-updates/s over the timed steps (the 24 preconditionings are done
+inside the same steps), the FP32-plain form's B-updates/s (one state at a
+time, no grouping) beside it, per-step latency p50/p99, the roofline of the
+dominant kernel from HIP events recorded live around every stage, and the
+FP64 CPU oracle timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm_gbs": 8000.0}
+LAYERS, D, R, N_BATCH, RHO, LAM = 24, 4096, 256, 256, 0.95, 0.01
+
+
+def _gen_batches(torch, dev, states, n, d, seed, dtype):
+    """Seeded synthetic batches on the device: ReLU(z k^-1) for A, z k^-0.7 for Gamma."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    k = torch.arange(1, d + 1, device=dev, dtype=torch.float32)
+    out = []
+    for i in range(states):
+        z = torch.randn(n, d, generator=g, device=dev)
+        x = torch.relu(z * k ** -1.0) if i % 2 == 0 else z * k ** -0.7
+        out.append(x.to(dtype).contiguous())
+    return out
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """The FP64 oracle (structured Brand update, Algorithm 3) on the host cores."""
+    import numpy as np
+    import oracle
+    from paper_2210_08494_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        threads = os.cpu_count()
+    f = oracle.BrandFactor(D, R, RHO)
+    for k in range(2):  # bring the state to r + n = 512 modes (untimed)
+        f.update(synth.batch_for(6, k, "A", N_BATCH, D).T)
+    times = []
+    t_all = time.perf_counter()
+    k = 2
+    while time.perf_counter() - t_all < budget_s and len(times) < 100:
+        M = synth.batch_for(6, k, "A", N_BATCH, D).T
+        t0 = time.perf_counter()
+        f.update(M)
+        times.append(time.perf_counter() - t0)
+        k += 1
+    med = float(np.median(times))
+    return {"value": 1.0 / med, "unit": "B-updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(times)} structured FP64 Brand updates (oracle/brand.py) at d={D} r={R} "
+                      f"n={N_BATCH} on the host, median {med:.3f} s each"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layers", type=int, default=LAYERS)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-updates", type=int, default=6)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (factor states "
+              "are independent, see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2210_08494_amd import kfb
+    kfb.load()
+    dev = torch.device("cuda:0")
+    L = args.layers
+    S = 2 * L
+    MIX = kfb.KFB_BF16_MIXED
+
+    # ---- states: even index = A factor (d_in), odd = Gamma factor (d_out) of a layer
+    states = [kfb.Factor(D, R, N_BATCH, RHO, MIX, device=dev) for _ in range(S)]
+    batches = [_gen_batches(torch, dev, S, N_BATCH, D, seed=1000 + j, dtype=torch.bfloat16) for j in range(2)]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    Gs = [torch.randn(D, D, generator=gen, device=dev) for _ in range(L)]
+    Ss = [torch.empty(D, D, device=dev) for _ in range(L)]
+    ws_u, ws_p = kfb.Workspace(dev), kfb.Workspace(dev)
+    fa = states[0::2]
+    fg = states[1::2]
+    lam = [LAM] * L
+
+    def step(j):
+        kfb.update_batched(states, batches[j % 2], ws_u)
+        kfb.precondition_batched(fg, fa, Gs, Ss, lam, lam, 0, ws_p)
+
+    # first update takes every state from empty to n modes; warmup reaches r + n
+    kfb.update_batched(states, batches[1], ws_u)
+    for j in range(args.warmup):
+        step(j)
+    torch.cuda.synchronize()
+
+    # ---- timed region (stage events recorded live on the same stream)
+    kfb.profile_enable(True)
+    kfb.profile_report(reset=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for j in range(args.steps):
+        step(j)
+        ev[j + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = kfb.profile_report(reset=True)
+    kfb.profile_enable(False)
+    step_ms = [ev[j].elapsed_time(ev[j + 1]) for j in range(args.steps)]
+    status = [f.status() for f in states]
+
+    bups = S * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+
+    # ---- roofline of the dominant kernel (core eigensolver rounds)
+    Ncore = R + N_BATCH
+    jac = prof.get("jacobi", {"ms": float("nan"), "launches": 1, "calls": 1})
+    calls = max(jac["calls"], 1)
+    launches_per_call = jac["launches"] / calls
+    avg_launch_ms = jac["ms"] / max(jac["launches"], 1)
+    flops_per_call = S * 9.0 * Ncore ** 3  # textbook symmetric EVD count per core
+    flops_per_launch = flops_per_call / launches_per_call
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    roofline = {"kernel": "jacobi_kernel<double,16> (block one-sided Jacobi round, FP64)",
+                "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
+                "per_launch": {"algorithmic_flops": flops_per_launch, "avg_ms": avg_launch_ms,
+                               "launches_per_update_call": launches_per_call,
+                               "unit_work": "9*(r+n)^3 FP64 flops per core eigensolve, 48 cores per call"}}
+
+    # other stages, algorithmic work per call
+    def _rate(stage, flops):
+        st = prof.get(stage)
+        if not st or st["calls"] == 0:
+            return None
+        ms = st["ms"] / st["calls"]
+        return {"ms_per_call": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 3)}
+
+    r, n, N = R, N_BATCH, Ncore
+    stages = {
+        "proj": _rate("proj", S * (2 * 2.0 * D * r * n + 2 * 2.0 * D * r * n)),
+        "cholqr": _rate("cholqr", S * 2 * (2.0 * D * n * n + 2.0 * D * n * n)),
+        "core": _rate("core", S * 2.0 * N * N),
+        "jacobi": _rate("jacobi", S * 9.0 * N ** 3),
+        "finalize": _rate("finalize", S * 2.0 * N * N),
+        "rotate": _rate("rotate", S * 2.0 * D * N * N),
+        "pre_coef_T1_T2_T3": _rate("pre_coef_T1_T2_T3", L * (2 * 2.0 * N * D * D + 2.0 * N * N * D)),
+        "pre_scale_X2": _rate("pre_scale_X2", L * 2.0 * D * N * N),
+        "pre_S": _rate("pre_S", L * 2.0 * D * D * 2 * N),
+    }
+
+    # ---- FP32 plain form: one state at a time, no grouping
+    f32 = [kfb.Factor(D, R, N_BATCH, RHO, kfb.KFB_FP32, device=dev) for _ in range(2)]
+    b32 = _gen_batches(torch, dev, 2, N_BATCH, D, seed=99, dtype=torch.float32)
+    for _ in range(2):
+        for f, M in zip(f32, b32):
+            f.update(M)
+    torch.cuda.synchronize()
+    lat32 = []
+    for i in range(args.fp32_updates):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        f32[i % 2].update(b32[i % 2])
+        e1.record()
+        torch.cuda.synchronize()
+        lat32.append(e0.elapsed_time(e1))
+    fp32_plain = {"value": round(1e3 / (sum(lat32) / len(lat32)), 2), "unit": "B-updates/s",
+                  "ms_per_update_p50": round(_percentile(lat32, 50), 3), "states": 2,
+                  "mode": "one update at a time, no grouping"}
+
+    # ---- single mixed update latency (no grouping), for the latency columns
+    lat1 = []
+    for i in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        states[i].update(batches[0][i])
+        e1.record()
+        torch.cuda.synchronize()
+        lat1.append(e0.elapsed_time(e1))
+
+    out = {
+        "metric": "B-updates/s + p50/p99 latency, BF16-mixed vs FP32 plain, d=4096 r=256 n=256",
+        "value": round(bups, 2),
+        "unit": "B-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64",
+        "data": "synthetic (seeded decaying-spectrum batches and N(0,1) gradients generated on the device)",
+        "config": {"workload": f"{L}-layer stack, 2 K-factors per layer ({S} states) at d={D}, r={R}, "
+                               f"n={N_BATCH}, rho={RHO}, lambda={LAM}; step = grouped Brand update of all "
+                               f"states + grouped two-sided preconditioning of all {L} layers",
+                   "layers": L, "states": S, "d": D, "r": R, "n": N_BATCH, "precision": "bf16-mixed",
+                   "parallelism": "single-gpu"},
+        "latency_ms": {"step_p50": round(_percentile(step_ms, 50), 3),
+                       "step_p99": round(_percentile(step_ms, 99), 3),
+                       "single_update_p50": round(_percentile(lat1, 50), 3),
+                       "single_update_p99": round(_percentile(lat1, 99), 3),
+                       "note": "closed loop; step = 48 updates + 24 preconditionings"},
+        "fp32_plain": fp32_plain,
+        "roofline": roofline,
+        "stages": stages,
+        "status_events": sorted(set(status)),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,19 @@ int kfb_state_load(kfb_state_t st, const void* U, int64_t ldu, const void* D, in
 /* Read and clear the device status word (synchronises the given stream). */
 int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
 
+/* Optional stage timing (diagnostics).  While enabled, each stage of the
+ * update and precondition calls (projection, residual, CholeskyQR, core
+ * assembly, Jacobi rounds, finalize, rotation; the apply's products) is
+ * bracketed by HIP events recorded on the call's stream, and the number of
+ * kernel launches of the stage is counted.  kfb_profile_report synchronises
+ * on the recorded events, then writes a JSON object
+ *   {"stage": {"calls": C, "launches": L, "ms": T}, ...}
+ * into buf (NUL-terminated, truncated to len) and optionally clears the
+ * totals.  Not for use while a stream is being captured into a graph.
+ * Returns KFB_OK, or KFB_EHIP if an event query fails. */
+int kfb_profile_enable(int on);
+int kfb_profile_report(char* buf, size_t len, int reset);
+
 const char* kfb_strerror(int code);
 
 /* Library build identification (compiled target, e.g. "gfx950"). */

@@ -4,6 +4,11 @@
 #include <string.h>
 #include <stdlib.h>
 #include <new>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+#include <stdio.h>
 
 #include "kfb_kernels.h"
 
@@ -29,6 +34,66 @@ namespace {
     hipError_t _e = (x);                             \
     if (_e != hipSuccess) return KFB_EHIP;           \
   } while (0)
+
+// ---------------------------------------------------------------------------
+// Optional stage timing (kfb_profile_enable / kfb_profile_report)
+// ---------------------------------------------------------------------------
+struct ProfStage {
+  const char* name;
+  long calls = 0, launches = 0;
+  double ms = 0.0;
+};
+struct ProfPending {
+  int stage;
+  hipEvent_t a, b;
+};
+struct Prof {
+  bool on = false;
+  std::mutex mu;
+  std::vector<ProfStage> stages;
+  std::vector<ProfPending> pending;
+  std::vector<hipEvent_t> pool;
+  int index(const char* nm) {
+    for (size_t i = 0; i < stages.size(); ++i)
+      if (strcmp(stages[i].name, nm) == 0) return (int)i;
+    ProfStage st;
+    st.name = nm;
+    stages.push_back(st);
+    return (int)stages.size() - 1;
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Prof g_prof;
+
+// RAII bracket: records an event at construction and at destruction (on s)
+struct StageTimer {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  int launches;
+  StageTimer(const char* nm, hipStream_t st, int nl) : name(nm), s(st), launches(nl) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    a = g_prof.get();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!g_prof.on || !a) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    hipEvent_t b = g_prof.get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    const int ix = g_prof.index(name);
+    g_prof.stages[ix].calls += 1;
+    g_prof.stages[ix].launches += launches;
+    g_prof.pending.push_back(ProfPending{ix, a, b});
+  }
+};
 
 inline size_t u_elem(int prec) { return prec == KFB_FP64 ? 8 : 4; }
 inline size_t d_elem(int prec) { return prec == KFB_FP32 ? 4 : 8; }
@@ -119,8 +184,10 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   const int64_t d = p.d, ldu = p.ldu, ldm = p.ldm;
   const int r = p.r, n = p.n, N = p.N;
 
+  const int kl_P = p.ksP > 1 ? 2 : 1, kl_G = p.ksG > 1 ? 2 : 1;
   if (r > 0) {
     // P = U_r^T M   (Algorithm 3: projection)
+    StageTimer st_proj("proj", s, 2 * kl_P + 2);
     GemmArgs g;
     g.A = op(U_FRONT, 0, ldu, 1); g.B = op(M_IN, 0, 1, ldm); g.C = op(WS, p.oP, 1, r);
     g.m = r; g.n = n; g.k = (int)d; g.ksplit = p.ksP; g.Part = op(WS, p.oPart, 1, r);
@@ -138,6 +205,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     z2.B = op(WS, p.oP2, 1, r); z2.C0 = op(WS, p.oZ, 1, d);
     KFB_TRY((gemm<TU, TP, TZ, TZ, TA>(drecs, nrec, z2, s)));
   } else {
+    StageTimer st_copy("proj", s, 1);
     KFB_TRY((copy2d<TZ, TM>(drecs, nrec, op(WS, p.oZ, 1, d), op(M_IN, 0, 1, ldm), (int)d, n, s)));
   }
   // Thin QR of the residual (Algorithm 3) by CholeskyQR: two passes when the
@@ -145,6 +213,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   // CholeskyQR3) keeps the factorisation stable for ill-conditioned residuals.
   const bool fp32_chol = sizeof(TG) == 4;
   const int passes = fp32_chol ? 3 : 2;
+  std::unique_ptr<StageTimer> st_qr(new StageTimer("cholqr", s, passes * (kl_G + 2) + passes - 1));
   const double ueps = fp32_chol ? 1.1920929e-07 : 2.220446049250313e-16;
   const double tau = 64.0 * ueps;
   int64_t srcZ = p.oZ, dstZ = p.oZb;
@@ -179,28 +248,38 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     }
   }
   const int64_t oRfin = passes == 3 ? p.oGram : p.oRt;
+  st_qr.reset();
   // core square factor and Jacobi eigensolve (Algorithm 3: EVD of M_S)
   CoreArgs co;
   co.r = r; co.n = n; co.N = N; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = r > 0 ? p.oP2 : -1;
   co.off_R = oRfin; co.off_B = p.oB; co.off_V = p.oV;
-  KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, nrec, co, s)));
-  KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
+  {
+    StageTimer st_core("core", s, 2);
+    KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, nrec, co, s)));
+    KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
+  }
   JacArgs ja;
   ja.Np = p.Np; ja.N = N; ja.b = p.bw; ja.max_sweeps = MAX_SWEEPS;
   ja.off_B = p.oB; ja.off_V = p.oV; ja.off_cnt = p.oCnt;
   const double eps = sizeof(TC) == 8 ? 2.220446049250313e-16 : 1.1920929e-07;
   ja.tol = eps * sqrt((double)N);
   const int nb = p.Np / p.bw;
+  {
+  StageTimer st_jac("jacobi", s, nb == 2 ? 1 : MAX_SWEEPS * (nb - 1));
   if (nb == 2) {
     KFB_TRY(jacobi_round<TC>(drecs, nrec, ja, 0, 0, s));
   } else {
     for (int sw = 0; sw < MAX_SWEEPS; ++sw)
       for (int rd = 0; rd < nb - 1; ++rd) KFB_TRY(jacobi_round<TC>(drecs, nrec, ja, sw, rd, s));
   }
+  }
   FinArgs fa;
   fa.N = N; fa.Np = p.Np; fa.max_sweeps = MAX_SWEEPS; fa.off_B = p.oB; fa.off_V = p.oV;
   fa.off_cnt = p.oCnt; fa.off_lam = p.oLam; fa.off_rank = p.oRank; fa.off_W = p.oW;
-  KFB_TRY((finalize_core<TC, TW, TD>(drecs, nrec, fa, s)));
+  {
+    StageTimer st_fin("finalize", s, 2);
+    KFB_TRY((finalize_core<TC, TW, TD>(drecs, nrec, fa, s)));
+  }
   // rotation: U' = [U_r Q] W  (Algorithm 3), into the back buffer
   GemmArgs ro;
   ro.A = op(U_FRONT, 0, 1, ldu);
@@ -208,6 +287,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   if (r == 0) ro.A = op(WS, oQ, 1, d);
   ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
   ro.m = (int)d; ro.n = N; ro.k = N;
+  StageTimer st_rot("rotate", s, 1);
   KFB_TRY((gemm<TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
   return KFB_OK;
 }
@@ -251,6 +331,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   typedef TA TGrad;  // G and S element type (FP64 form: double, else float)
   const int NG = p.NG, NA = p.NA;
   const int64_t dG = p.dG, dA = p.dA;
+  std::unique_ptr<StageTimer> st_pre(new StageTimer("pre_coef_T1_T2_T3", s, 4 + (p.ks3 > 1 ? 1 : 0)));
   CoefArgs ca;
   ca.kG = NG; ca.kA = NA; ca.off_cG = p.ocG; ca.off_cA = p.ocA; ca.flags = flags;
   KFB_TRY((precond_coefs<TD, TA>(drecs, nrec, ca, s)));
@@ -269,6 +350,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g3.A = op(PWS, p.oT1, dA, 1); g3.B = op(PU_A, 0, 1, p.lduA); g3.C = op(PWS, p.oT3, 1, NG);
   g3.m = NG; g3.n = NA; g3.k = (int)dA; g3.ksplit = p.ks3; g3.Part = op(PWS, p.oPart, 1, NG);
   KFB_TRY((gemm<TA, TU, TA, TA, TA>(drecs, nrec, g3, s)));
+  st_pre.reset(new StageTimer("pre_scale_X2", s, 4));
   // X1 = diag(c_G / lam_A) T1;  T2 <- T2 diag(c_A / lam_G);  T3 <- diag(c_G) T3 diag(c_A)
   ScaleArgs s1;
   s1.m = NG; s1.n = (int)dA; s1.X = op(PWS, p.oT1, dA, 1); s1.row_slot = PWS; s1.row_off = p.ocG;
@@ -288,6 +370,8 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g4.A = op(PU_G, 0, 1, p.lduG); g4.B = op(PWS, p.oT3, 1, NG); g4.C0 = op(PWS, p.oT2, 1, dG);
   g4.C = op(PWS, p.oT2, 1, dG); g4.m = (int)dG; g4.n = NA; g4.k = NG; g4.beta = 1.0;
   KFB_TRY((gemm<TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
+  st_pre.reset();
+  StageTimer st_s("pre_S", s, 1);
   // S = G / (lam_G lam_A) + [U_G | X2] [X1 ; U_A^T]
   GemmArgs g5;
   g5.A = op(PU_G, 0, 1, p.lduG);
@@ -588,6 +672,43 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream) {
   KFB_TRY(hipStreamSynchronize(s));
   *events = v;
   return KFB_OK;
+}
+
+int kfb_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return KFB_OK;
+}
+
+int kfb_profile_report(char* buf, size_t len, int reset) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  int rc = KFB_OK;
+  for (auto& pe : g_prof.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pe.b) != hipSuccess || hipEventElapsedTime(&ms, pe.a, pe.b) != hipSuccess) rc = KFB_EHIP;
+    g_prof.stages[pe.stage].ms += ms;
+    g_prof.pool.push_back(pe.a);
+    g_prof.pool.push_back(pe.b);
+  }
+  g_prof.pending.clear();
+  if (buf && len > 0) {
+    std::string out = "{";
+    char item[256];
+    for (size_t i = 0; i < g_prof.stages.size(); ++i) {
+      const ProfStage& st = g_prof.stages[i];
+      snprintf(item, sizeof(item), "%s\"%s\": {\"calls\": %ld, \"launches\": %ld, \"ms\": %.6f}",
+               i ? ", " : "", st.name, st.calls, st.launches, st.ms);
+      out += item;
+    }
+    out += "}";
+    const size_t nc = out.size() < len - 1 ? out.size() : len - 1;
+    memcpy(buf, out.data(), nc);
+    buf[nc] = 0;
+  }
+  if (reset) {
+    for (auto& st : g_prof.stages) { st.calls = 0; st.launches = 0; st.ms = 0.0; }
+  }
+  return rc;
 }
 
 const char* kfb_strerror(int code) {

@@ -44,6 +44,8 @@ _SIGS = {
     "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
     "kfb_state_load": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i64, _vp]),
     "kfb_state_status": (ctypes.c_int, [_vp, ctypes.POINTER(_u32), _vp]),
+    "kfb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "kfb_profile_report": (ctypes.c_int, [ctypes.c_char_p, _sz, ctypes.c_int]),
     "kfb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kfb_build_info": (ctypes.c_char_p, []),
 }
@@ -248,3 +250,15 @@ def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):
     _check(lib.kfb_precondition_batched(cnt, hg, ha, gp, int(Gs[0].stride(0)), sp, int(Ss[0].stride(0)), lg, la,
                                         int(flags), _ptr(w), int(w.numel()), _stream()),
            "kfb_precondition_batched")
+
+
+def profile_enable(on: bool = True):
+    _check(load().kfb_profile_enable(1 if on else 0), "kfb_profile_enable")
+
+
+def profile_report(reset: bool = True) -> dict:
+    """Stage timings recorded while profiling was enabled: {stage: {calls, launches, ms}}."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().kfb_profile_report(buf, len(buf), 1 if reset else 0), "kfb_profile_report")
+    return json.loads(buf.value.decode() or "{}")
