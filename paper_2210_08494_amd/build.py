@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libkfb.so")
-SOURCES = ["gemm.hip", "linalg.hip", "api.hip"]
+SOURCES = ["gemm.hip", "gemm_mfma.hip", "linalg.hip", "api.hip"]
 ARCH = os.environ.get("KFB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -175,6 +175,19 @@ inline OpRef op(int slot, int64_t off, int64_t rs, int64_t cs) {
   return o;
 }
 
+// Product dispatch: the mixed form runs its FP32 products on BF16 MFMA
+// (SPLIT = 1: operands carried as BF16 hi + lo terms), the other forms on the
+// FP64 / FP32 FMA engine.
+template <int PR, int SPLIT, typename TA, typename TB, typename TC, typename TC0, typename TAcc>
+hipError_t mm(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
+  if constexpr (PR == KFB_BF16_MIXED && sizeof(TA) == 4 && sizeof(TC) == 4 && sizeof(TAcc) == 4 &&
+                (sizeof(TB) == 4 || sizeof(TB) == 2)) {
+    return gemm_bf16<TA, TB, TC, TC0, SPLIT>(recs, nrec, g, s);
+  } else {
+    return gemm<TA, TB, TC, TC0, TAcc>(recs, nrec, g, s);
+  }
+}
+
 template <int PR>
 int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   typedef Ty<PR> T;
@@ -191,19 +204,19 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     GemmArgs g;
     g.A = op(U_FRONT, 0, ldu, 1); g.B = op(M_IN, 0, 1, ldm); g.C = op(WS, p.oP, 1, r);
     g.m = r; g.n = n; g.k = (int)d; g.ksplit = p.ksP; g.Part = op(WS, p.oPart, 1, r);
-    KFB_TRY((gemm<TU, TM, TP, TP, TP>(drecs, nrec, g, s)));
+    KFB_TRY((mm<PR, 1, TU, TM, TP, TP, TP>(drecs, nrec, g, s)));
     // Z = M - U_r P   (component outside span(U))
     GemmArgs z;
     z.A = op(U_FRONT, 0, 1, ldu); z.B = op(WS, p.oP, 1, r); z.C0 = op(M_IN, 0, 1, ldm);
     z.C = op(WS, p.oZ, 1, d); z.m = (int)d; z.n = n; z.k = r; z.alpha = -1.0; z.beta = 1.0;
-    KFB_TRY((gemm<TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
+    KFB_TRY((mm<PR, 1, TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
     // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
     GemmArgs g2 = g;
     g2.B = op(WS, p.oZ, 1, d); g2.C = op(WS, p.oP2, 1, r);
-    KFB_TRY((gemm<TU, TZ, TP, TP, TP>(drecs, nrec, g2, s)));
+    KFB_TRY((mm<PR, 1, TU, TZ, TP, TP, TP>(drecs, nrec, g2, s)));
     GemmArgs z2 = z;
     z2.B = op(WS, p.oP2, 1, r); z2.C0 = op(WS, p.oZ, 1, d);
-    KFB_TRY((gemm<TU, TP, TZ, TZ, TA>(drecs, nrec, z2, s)));
+    KFB_TRY((mm<PR, 1, TU, TP, TZ, TZ, TA>(drecs, nrec, z2, s)));
   } else {
     StageTimer st_copy("proj", s, 1);
     KFB_TRY((copy2d<TZ, TM>(drecs, nrec, op(WS, p.oZ, 1, d), op(M_IN, 0, 1, ldm), (int)d, n, s)));
@@ -288,7 +301,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
   ro.m = (int)d; ro.n = N; ro.k = N;
   StageTimer st_rot("rotate", s, 1);
-  KFB_TRY((gemm<TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
+  KFB_TRY((mm<PR, 1, TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
   return KFB_OK;
 }
 
@@ -339,17 +352,17 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   GemmArgs g1;
   g1.A = op(PU_G, 0, p.lduG, 1); g1.B = op(P_G, 0, p.ldg, 1); g1.C = op(PWS, p.oT1, dA, 1);
   g1.m = NG; g1.n = (int)dA; g1.k = (int)dG;
-  KFB_TRY((gemm<TU, TGrad, TA, TA, TA>(drecs, nrec, g1, s)));
+  KFB_TRY((mm<PR, 0, TU, TGrad, TA, TA, TA>(drecs, nrec, g1, s)));
   // T2 = G U_A     (dG x NA, column-major)
   GemmArgs g2;
   g2.A = op(P_G, 0, p.ldg, 1); g2.B = op(PU_A, 0, 1, p.lduA); g2.C = op(PWS, p.oT2, 1, dG);
   g2.m = (int)dG; g2.n = NA; g2.k = (int)dA;
-  KFB_TRY((gemm<TGrad, TU, TA, TA, TA>(drecs, nrec, g2, s)));
+  KFB_TRY((mm<PR, 0, TGrad, TU, TA, TA, TA>(drecs, nrec, g2, s)));
   // T3 = T1 U_A    (NG x NA)
   GemmArgs g3;
   g3.A = op(PWS, p.oT1, dA, 1); g3.B = op(PU_A, 0, 1, p.lduA); g3.C = op(PWS, p.oT3, 1, NG);
   g3.m = NG; g3.n = NA; g3.k = (int)dA; g3.ksplit = p.ks3; g3.Part = op(PWS, p.oPart, 1, NG);
-  KFB_TRY((gemm<TA, TU, TA, TA, TA>(drecs, nrec, g3, s)));
+  KFB_TRY((mm<PR, 0, TA, TU, TA, TA, TA>(drecs, nrec, g3, s)));
   st_pre.reset(new StageTimer("pre_scale_X2", s, 4));
   // X1 = diag(c_G / lam_A) T1;  T2 <- T2 diag(c_A / lam_G);  T3 <- diag(c_G) T3 diag(c_A)
   ScaleArgs s1;
@@ -369,7 +382,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   GemmArgs g4;
   g4.A = op(PU_G, 0, 1, p.lduG); g4.B = op(PWS, p.oT3, 1, NG); g4.C0 = op(PWS, p.oT2, 1, dG);
   g4.C = op(PWS, p.oT2, 1, dG); g4.m = (int)dG; g4.n = NA; g4.k = NG; g4.beta = 1.0;
-  KFB_TRY((gemm<TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
+  KFB_TRY((mm<PR, 0, TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
   st_pre.reset();
   StageTimer st_s("pre_S", s, 1);
   // S = G / (lam_G lam_A) + [U_G | X2] [X1 ; U_A^T]
@@ -381,7 +394,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g5.C0 = op(P_G, 0, p.ldg, 1); g5.beta_slot = PWS; g5.beta_off = p.oBeta;
   g5.C = op(P_S, 0, p.lds, 1);
   g5.m = (int)dG; g5.n = (int)dA; g5.k = NG + NA;
-  KFB_TRY((gemm<TU, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
+  KFB_TRY((mm<PR, 0, TU, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
   return KFB_OK;
 }
 

@@ -1,0 +1,354 @@
+// BF16 MFMA GEMM for the mixed precision form:  C = alpha A B + beta C0.
+//
+// Operands are FP32 or BF16 in memory, rounded to BF16 (round to nearest
+// even) while staged into LDS; with SPLIT the FP32 remainder x - bf16(x) is
+// staged as a second BF16 term and three products hi*hi + hi*lo + lo*hi are
+// accumulated (about 16 significant bits per operand, FP32 accumulation).
+// Tiles of 128 x 128 x 32 are computed by four waves (64 x 64 each) with
+// v_mfma_f32_16x16x32_bf16.  Lane layout of that instruction: A element
+// (i, k) sits in lane i + 16*(k/8), slot k%8; B element (k, j) in lane
+// j + 16*(k/8), slot k%8; result (i, j) in lane j + 16*(i/4), slot i%4.
+// When C is column-major the product is issued transposed (B^T A^T), so the
+// 16 lanes that share a result slot hold 16 consecutive rows and the stores
+// coalesce.  LDS is double buffered: the next k tile is loaded into registers
+// while the current one is multiplied.  Split-K partials and the fixed-order
+// reduction follow the same GemmArgs contract as the FMA engine.
+#include "kfb_kernels.h"
+
+namespace kfb {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+template <typename T> __device__ __forceinline__ float to_f(T x);
+template <> __device__ __forceinline__ float to_f<float>(float x) { return x; }
+template <> __device__ __forceinline__ float to_f<bf16>(bf16 x) { return __bfloat162float(x); }
+
+__device__ __forceinline__ __bf16 rne_bf16(float x) {
+  // round to nearest even (NaN stays NaN)
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return __builtin_bit_cast(__bf16, (uint16_t)((u >> 16) | 0x40));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
+}
+__device__ __forceinline__ float bf_to_f(__bf16 h) {
+  return __uint_as_float(((uint32_t)__builtin_bit_cast(uint16_t, h)) << 16);
+}
+
+constexpr int MBM = 128, MBN = 128, MBK = 32, MNT = 256;
+constexpr int MLD = MBK + 8;  // padded LDS row (bf16 elements)
+
+template <typename T>
+struct MSeg {
+  const T* p;
+  int64_t rs, cs;
+  const T* p2;
+  int64_t rs2, cs2;
+  int split;
+  __device__ MSeg(const Rec& r, const OpRef& o) {
+    p = o.slot >= 0 ? at<const T>(r, o.slot, o.off) : nullptr;
+    rs = o.rs; cs = o.cs;
+    p2 = o.slot2 >= 0 ? at<const T>(r, o.slot2, o.off2) : nullptr;
+    rs2 = o.rs2; cs2 = o.cs2;
+    split = o.slot2 >= 0 ? o.split : 0x7fffffff;
+  }
+  // element (row, k) of an A operand / (k, col) of a B operand, k along the split
+  __device__ __forceinline__ float a(int i, int k) const {
+    return k < split ? to_f(p[i * rs + k * cs]) : to_f(p2[i * rs2 + (k - split) * cs2]);
+  }
+  __device__ __forceinline__ float b(int k, int j) const {
+    return k < split ? to_f(p[k * rs + j * cs]) : to_f(p2[(k - split) * rs2 + j * cs2]);
+  }
+};
+
+// One thread moves one 4 x 4 sub-block (rows x k) of a 128 x 32 operand tile.
+// kc: k is the contiguous memory direction (4 k per row, 8 threads cover a
+// 32-wide row segment); otherwise rows are contiguous (4 consecutive rows per
+// k, transposed in registers).  In-range sub-blocks with aligned strides use
+// 16-byte (FP32) or 8-byte (BF16) loads; the rest use element loads with
+// zero fill.
+struct Frag {
+  float v[4][4];  // [row][k]
+};
+
+__device__ __forceinline__ void frag_pos(bool kc, int t, int* rb, int* kb) {
+  if (kc) { *kb = t % 8; *rb = t / 8; } else { *rb = t % 32; *kb = t / 32; }
+}
+
+template <typename T, bool ISA>
+__device__ __forceinline__ void load_frag(const MSeg<T>& s, bool kc, bool vec_ok, int row0, int nrows, int k0,
+                                          int kend, int t, Frag& f) {
+  int rb, kb;
+  frag_pos(kc, t, &rb, &kb);
+  const int gr = row0 + 4 * rb, gk = k0 + 4 * kb;
+  const bool one_seg = (gk + 3 < s.split) || (gk >= s.split);
+  if (vec_ok && one_seg && gr + 3 < nrows && gk + 3 < kend) {
+    const bool seg2 = gk >= s.split;
+    const T* base = seg2 ? s.p2 : s.p;
+    const int64_t rsd = ISA ? (seg2 ? s.rs2 : s.rs) : (seg2 ? s.cs2 : s.cs);  // stride along rows
+    const int64_t ksd = ISA ? (seg2 ? s.cs2 : s.cs) : (seg2 ? s.rs2 : s.rs);  // stride along k
+    const int kk = seg2 ? gk - s.split : gk;
+    if constexpr (sizeof(T) == 4) {
+      typedef __attribute__((__vector_size__(16))) float v4;
+      if (kc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const v4 x = *reinterpret_cast<const v4*>(base + (int64_t)(gr + r) * rsd + (int64_t)kk * ksd);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) f.v[r][c] = x[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const v4 x = *reinterpret_cast<const v4*>(base + (int64_t)gr * rsd + (int64_t)(kk + c) * ksd);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) f.v[r][c] = x[r];
+        }
+      }
+    } else {
+      typedef __attribute__((__vector_size__(8))) unsigned short v4h;
+      if (kc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const v4h x = *reinterpret_cast<const v4h*>(base + (int64_t)(gr + r) * rsd + (int64_t)kk * ksd);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) f.v[r][c] = __uint_as_float(((uint32_t)x[c]) << 16);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const v4h x = *reinterpret_cast<const v4h*>(base + (int64_t)gr * rsd + (int64_t)(kk + c) * ksd);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) f.v[r][c] = __uint_as_float(((uint32_t)x[r]) << 16);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int rr = gr + r, k = gk + c;
+        float v = 0.f;
+        if (rr < nrows && k < kend) v = ISA ? s.a(rr, k) : s.b(k, rr);
+        f.v[r][c] = v;
+      }
+  }
+}
+
+template <bool LO>
+__device__ __forceinline__ void store_frag(const Frag& f, bool kc, int t, __bf16* hi, __bf16* lo) {
+  int rb, kb;
+  frag_pos(kc, t, &rb, &kb);
+  typedef __attribute__((__vector_size__(8))) __bf16 v4b;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    v4b h, l2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const __bf16 x = rne_bf16(f.v[r][c]);
+      h[c] = x;
+      if (LO) l2[c] = rne_bf16(f.v[r][c] - bf_to_f(x));
+    }
+    *reinterpret_cast<v4b*>(&hi[(4 * rb + r) * MLD + 4 * kb]) = h;
+    if (LO) *reinterpret_cast<v4b*>(&lo[(4 * rb + r) * MLD + 4 * kb]) = l2;
+  }
+}
+
+// 4-element vectors along the contiguous direction need aligned bases, a
+// 4-multiple stride in the other direction and a 4-multiple split point
+template <typename T>
+__device__ __forceinline__ bool vec_aligned(const MSeg<T>& s, bool kc, bool isa) {
+  const uintptr_t al = sizeof(T) * 4 - 1;
+  auto ok = [&](const T* p, int64_t rs, int64_t cs) {
+    if (!p) return true;
+    const int64_t along = kc ? (isa ? cs : rs) : (isa ? rs : cs);   // must be 1
+    const int64_t other = kc ? (isa ? rs : cs) : (isa ? cs : rs);
+    return along == 1 && (((uintptr_t)p) & al) == 0 && (other % 4) == 0;
+  };
+  return ok(s.p, s.rs, s.cs) && ok(s.p2, s.rs2, s.cs2) && (s.p2 == nullptr || (s.split % 4) == 0);
+}
+
+template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
+__global__ __launch_bounds__(MNT) void gemm_bf16_kernel(const Rec* __restrict__ recs, GemmArgs g) {
+  constexpr bool A_LO = SPLIT && sizeof(TA) == 4;  // BF16 inputs are exact: no remainder
+  constexpr bool B_LO = SPLIT && sizeof(TB) == 4;
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][MBM * MLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][MBN * MLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[A_LO ? 2 : 1][A_LO ? MBM * MLD : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[B_LO ? 2 : 1][B_LO ? MBN * MLD : 8];
+  const Rec& rec = recs[blockIdx.z];
+  const int tiles_m = (g.m + MBM - 1) / MBM;
+  const int tm = blockIdx.x % tiles_m, kz = blockIdx.x / tiles_m, tn = blockIdx.y;
+  const int kbeg = kz * g.kchunk;
+  const int kend = min(g.k, kbeg + g.kchunk);
+  const MSeg<TA> A(rec, g.A);
+  const MSeg<TB> B(rec, g.B);
+  const bool a_kc = (g.A.cs == 1);
+  const bool b_kc = (g.B.rs == 1);
+  const bool a_vec = vec_aligned(A, a_kc, true);
+  const bool b_vec = vec_aligned(B, b_kc, false);
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;  // wave's 64 x 64 sub-tile
+  // transposed issue when the output (or the split-K partial) is column-major
+  const bool swp = (g.ksplit > 1) || (g.C.rs == 1);
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  Frag fa, fb;
+  int cur = 0;
+  if (kbeg < kend) {
+    load_frag<TA, true>(A, a_kc, a_vec, tm * MBM, g.m, kbeg, kend, t, fa);
+    load_frag<TB, false>(B, b_kc, b_vec, tn * MBN, g.n, kbeg, kend, t, fb);
+    store_frag<A_LO>(fa, a_kc, t, sAh[0], sAl[0]);
+    store_frag<B_LO>(fb, b_kc, t, sBh[0], sBl[0]);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += MBK) {
+    const bool more = k0 + MBK < kend;
+    if (more) {  // prefetch the next k tile into registers
+      load_frag<TA, true>(A, a_kc, a_vec, tm * MBM, g.m, k0 + MBK, kend, t, fa);
+      load_frag<TB, false>(B, b_kc, b_vec, tn * MBN, g.n, k0 + MBK, kend, t, fb);
+    }
+    const int kq = 8 * (l / 16);
+    bf16x8 af[4], bfr[4], afl[4], bfl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      af[i] = *reinterpret_cast<const bf16x8*>(&sAh[cur][(wm + i * 16 + (l % 16)) * MLD + kq]);
+      if (A_LO) afl[i] = *reinterpret_cast<const bf16x8*>(&sAl[A_LO ? cur : 0][(wm + i * 16 + (l % 16)) * MLD + kq]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bfr[j] = *reinterpret_cast<const bf16x8*>(&sBh[cur][(wn + j * 16 + (l % 16)) * MLD + kq]);
+      if (B_LO) bfl[j] = *reinterpret_cast<const bf16x8*>(&sBl[B_LO ? cur : 0][(wn + j * 16 + (l % 16)) * MLD + kq]);
+    }
+    if (!swp) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          if (B_LO) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
+          if (A_LO) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+          if (B_LO) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfl[j], af[i], acc[i][j], 0, 0, 0);
+          if (A_LO) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], afl[i], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) {
+      const int nx = cur ^ 1;
+      store_frag<A_LO>(fa, a_kc, t, sAh[nx], sAl[A_LO ? nx : 0]);
+      store_frag<B_LO>(fb, b_kc, t, sBh[nx], sBl[B_LO ? nx : 0]);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // result element positions: slot v of lane l in tile (i, j)
+  //   normal:     row = 16i + 4(l/16) + v, col = 16j + l%16
+  //   transposed: row = 16i + l%16,         col = 16j + 4(l/16) + v
+  const int gm0 = tm * MBM + wm, gn0 = tn * MBN + wn;
+  if (g.ksplit > 1) {
+    float* part = at<float>(rec, g.Part.slot, g.Part.off) + (int64_t)kz * g.m * g.n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = gm0 + 16 * i + (l % 16), gj = gn0 + 16 * j + 4 * (l / 16) + v;
+          if (gi < g.m && gj < g.n) part[gi + (int64_t)gj * g.m] = acc[i][j][v];
+        }
+    return;
+  }
+  TC* C = at<TC>(rec, g.C.slot, g.C.off);
+  const bool use_c0 = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
+  const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
+  const float alpha = (float)g.alpha;
+  const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi, gj;
+        if (swp) { gi = gm0 + 16 * i + (l % 16); gj = gn0 + 16 * j + 4 * (l / 16) + v; }
+        else { gi = gm0 + 16 * i + 4 * (l / 16) + v; gj = gn0 + 16 * j + (l % 16); }
+        if (gi < g.m && gj < g.n) {
+          float val = alpha * acc[i][j][v];
+          if (C0) val += beta * to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+          C[gi * g.C.rs + gj * g.C.cs] = TC(val);
+        }
+      }
+}
+
+// fixed-order sum of split-K partials (FP32), then alpha / beta epilogue
+template <typename TC, typename TC0>
+__global__ __launch_bounds__(256) void mfma_splitk_reduce(const Rec* __restrict__ recs, GemmArgs g) {
+  const Rec& rec = recs[blockIdx.y];
+  const int64_t mn = (int64_t)g.m * g.n;
+  const float* part = at<const float>(rec, g.Part.slot, g.Part.off);
+  TC* C = at<TC>(rec, g.C.slot, g.C.off);
+  const bool use_c0 = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
+  const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
+  const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % g.m), j = (int)(e / g.m);
+    float sum = 0.f;
+    for (int kz = 0; kz < g.ksplit; ++kz) sum += part[kz * mn + e];
+    float v = (float)g.alpha * sum;
+    if (C0) v += beta * to_f(C0[i * g.C0.rs + j * g.C0.cs]);
+    C[i * g.C.rs + j * g.C.cs] = TC(v);
+  }
+}
+
+template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
+hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t s) {
+  if (g0.m <= 0 || g0.n <= 0 || nrec <= 0) return hipSuccess;
+  GemmArgs g = g0;
+  if (g.k < 0) g.k = 0;
+  const int tiles_m = (g.m + MBM - 1) / MBM, tiles_n = (g.n + MBN - 1) / MBN;
+  int ks = g.ksplit < 1 ? 1 : g.ksplit;
+  if (ks > 1) {
+    int chunk = (g.k + ks - 1) / ks;
+    chunk = ((chunk + MBK - 1) / MBK) * MBK;
+    ks = (g.k + chunk - 1) / chunk;
+    g.kchunk = chunk;
+  } else {
+    g.kchunk = g.k > 0 ? g.k : 1;
+  }
+  g.ksplit = ks;
+  dim3 grid(tiles_m * ks, tiles_n, nrec);
+  hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, TC, TC0, SPLIT>), grid, dim3(MNT), 0, s, recs, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  const int64_t mn = (int64_t)g.m * g.n;
+  int blocks = (int)((mn + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL((mfma_splitk_reduce<TC, TC0>), dim3(blocks, nrec), dim3(256), 0, s, recs, g);
+  return hipGetLastError();
+}
+
+#define KFB_GEMM_BF16(TA, TB, TC, TC0, SP) \
+  template hipError_t gemm_bf16<TA, TB, TC, TC0, SP>(const Rec*, int, const GemmArgs&, hipStream_t);
+// mixed-form update: projections (U FP32 split, M BF16 exact), residuals, rotation
+KFB_GEMM_BF16(float, bf16, float, float, 1)
+KFB_GEMM_BF16(float, float, float, bf16, 1)
+KFB_GEMM_BF16(float, float, float, float, 1)
+// mixed-form preconditioner (single BF16 terms)
+KFB_GEMM_BF16(float, float, float, float, 0)
+#undef KFB_GEMM_BF16
+
+}  // namespace kfb

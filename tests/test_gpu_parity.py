@@ -295,3 +295,51 @@ def test_batched_equals_single(kfb):
             Ua, Da = a.front()
             Ub, Db = b.front()
             assert torch.equal(Ua, Ub) and torch.equal(Da, Db)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_mixed_precondition_on_loaded_state(kfb, flags):
+    # BF16-MFMA apply on an oracle-built state (U in FP32, D in FP64), G FP32
+    import torch
+    dG, dA, r, n, rho = 768, 1024, 64, 64, 0.95
+    _announce(f"mixed precondition flags={flags}")
+    bg = _oracle_state(dG, r, n, rho, 4, 31, "G")
+    ba = _oracle_state(dA, r, n, rho, 4, 31, "A")
+    fg = kfb.Factor(dG, r, n, rho, kfb.KFB_BF16_MIXED)
+    fa = kfb.Factor(dA, r, n, rho, kfb.KFB_BF16_MIXED)
+    UG32, UA32 = bg.U.astype(np.float32), ba.U.astype(np.float32)
+    fg.load_state(_to_dev(UG32, torch.float32), _to_dev(bg.D, torch.float64), step=4)
+    fa.load_state(_to_dev(UA32, torch.float32), _to_dev(ba.D, torch.float64), step=4)
+    G = synth.grad_for(31, 0, dG, dA).astype(np.float32)
+    Gd = _to_dev(G, torch.float32)
+    S = torch.empty_like(Gd)
+    lg, la = 0.01, 0.01
+    kfb.precondition(fg, fa, Gd, S, lg, la, flags=flags)
+    torch.cuda.synchronize()
+    DG, DA, lgx, lax = bg.D, ba.D, lg, la
+    if flags & 1:
+        DG, lgx = oracle.spectrum_continuation(DG, lg)
+        DA, lax = oracle.spectrum_continuation(DA, la)
+    S_ref = oracle.precondition_lowrank(UG32.astype(np.float64), DG, UA32.astype(np.float64), DA,
+                                        G.astype(np.float64), lgx, lax)
+    es = oracle.e_S(S.cpu().numpy(), S_ref)
+    _announce(f"  e_S {es:.3e}")
+    assert es <= TOL[2]
+
+
+def test_mixed_wide_layer_spot(kfb):
+    # the wide mixed configuration: d = 8192, r = n = 512 (core N = 1024), a few steps vs Oracle-B
+    import torch
+    d, r, n, rho, steps = 8192, 512, 512, 0.95, 3
+    _announce(f"mixed wide layer d={d} r={r} n={n} steps={steps}")
+    f = kfb.Factor(d, r, n, rho, kfb.KFB_BF16_MIXED)
+    o = oracle.BrandFactor(d, r, rho)
+    for k in range(steps):
+        M = _batch(3, 100 + k, "A", n, d, prec=2)
+        f.update(_to_dev(M, torch.bfloat16))
+        o.update(M.T)
+        U, D = _front_np(f)
+        e = oracle.e_rec_lowrank(U, D, o.U, o.D)
+        _announce(f"  step {k} e_rec {e:.3e} orth {oracle.e_orth(U):.2e}")
+        assert e <= TOL[2]
+    assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
