@@ -12,6 +12,20 @@ template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
 template <> __device__ __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
 
+// 1/sqrt(x) from the hardware estimate refined by Newton steps
+// (y <- y (3 - x y^2) / 2): two steps reach FP64 round-off from the FP64
+// estimate, one step FP32 round-off.
+template <typename T> __device__ __forceinline__ T dev_rsqrt(T x);
+template <> __device__ __forceinline__ double dev_rsqrt<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+template <> __device__ __forceinline__ float dev_rsqrt<float>(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  return y * (1.5f - 0.5f * x * y * y);
+}
+
 template <typename T> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 template <> struct Eps<float> { static constexpr float v = 1.1920929e-07f; };
@@ -228,7 +242,7 @@ hipError_t assemble_core(const Rec* recs, int nrec, const CoreArgs& a, hipStream
 // the previous sweep).  When one panel holds every column (nb == 2) the
 // workgroup repeats steps 1-3 itself until a pass rotates nothing.
 // ---------------------------------------------------------------------------
-constexpr int JAC_NT = 256;
+constexpr int JAC_NT = 512;
 constexpr int JAC_LDS_BYTES = 128 * 1024;  // panel budget; G and Z come on top
 constexpr int JAC_LDS_MAX = 156 * 1024;    // whole dynamic allocation (160 KB per CU on gfx950)
 
@@ -245,30 +259,55 @@ typedef __attribute__((__vector_size__(4 * sizeof(double)))) double jac_d4;
 // FP64 with P >= 16: 16x16 tiles on MFMA (upper triangle, one wave per tile
 // slot); otherwise 4x4 register blocks on FMA with rows split across lanes.
 template <typename T, int P>
-__device__ __forceinline__ void jac_gram(const T* pb, int Np, int LDP, T* G, int t) {
+__device__ __forceinline__ void jac_gram(const T* pb, int Np, int LDP, T* G, T* scratch, int t) {
   if constexpr (sizeof(T) == 8 && P >= 16) {
+    // upper-triangle 16x16 tiles x KP slices of the rows; slice 0 writes G, the
+    // others write partial tiles into scratch (P x P doubles) that are added after
+    // a barrier by the caller via jac_gram_finish
     constexpr int NT16 = P / 16;
     constexpr int NTILE = NT16 * (NT16 + 1) / 2;
+    constexpr int NW = JAC_NT / 64;
+    constexpr int KP = (NTILE * 2 <= NW) ? 2 : 1;
     const int w = t / 64, l = t % 64;
-    for (int tile = w; tile < NTILE; tile += JAC_NT / 64) {
+    for (int item = w; item < NTILE * KP; item += NW) {
+      const int tile = item % NTILE, kp = item / NTILE;
       int ti = 0, rem = tile;
       while (rem >= NT16 - ti) { rem -= NT16 - ti; ++ti; }
       const int tj = ti + rem;
-      jac_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      jac_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const T* ca = pb + (size_t)(ti * 16 + (l % 16)) * LDP + (l / 16);
       const T* cb = pb + (size_t)(tj * 16 + (l % 16)) * LDP + (l / 16);
-      for (int k0 = 0; k0 < Np; k0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k0], cb[k0], acc, 0, 0, 0);
+      const int kb = kp * (Np / KP), ke = kb + Np / KP;
+      for (int k0 = kb; k0 < ke; k0 += 8) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k0], cb[k0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k0 + 4], cb[k0 + 4], acc1, 0, 0, 0);
+      }
+      T* dst = kp == 0 ? G : scratch + (size_t)(kp - 1) * P * P;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = ti * 16 + l / 16 + 4 * v, j = tj * 16 + l % 16;
-        G[i * P + j] = acc[v];
-        G[j * P + i] = acc[v];
+        const T x = acc0[v] + acc1[v];
+        dst[i * P + j] = x;
+        if (kp == 0) G[j * P + i] = x;
+      }
+    }
+    if constexpr (KP > 1) {
+      __syncthreads();
+      for (int e = t; e < P * P; e += JAC_NT) {
+        const int i = e / P, j = e % P;
+        if (i <= j && (i / 16) <= (j / 16)) {
+          const T x = G[i * P + j] + scratch[i * P + j];
+          G[i * P + j] = x;
+          G[j * P + i] = x;
+        }
       }
     }
   } else {
     constexpr int NBLK = (P / 4) * (P / 4);
-    constexpr int RS = JAC_NT / NBLK;
-    static_assert(RS >= 1 && RS <= 64 && (RS & (RS - 1)) == 0, "bad Gram split");
+    constexpr int RS0 = JAC_NT / NBLK;
+    constexpr int RS = RS0 > 64 ? 64 : RS0;  // lanes of one wave share a block
+    static_assert(RS >= 1 && (RS & (RS - 1)) == 0, "bad Gram split");
+    if (t >= NBLK * RS) return;  // whole idle waves (NBLK * RS is a multiple of 64)
     const int blk = t / RS, rs = t % RS;
     const int bi = blk / (P / 4), bj = blk % (P / 4);
     T acc[4][4];
@@ -386,10 +425,16 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   // ---- load the panel (16-byte vectors, coalesced along the rows)
   constexpr int VE = 16 / sizeof(T);
   typedef __attribute__((__vector_size__(16))) T vec_t;
-  for (int c = 0; c < P; ++c) {
-    const vec_t* src = reinterpret_cast<const vec_t*>(Bm + (int64_t)gcol(c) * Np);
-    vec_t* dst = reinterpret_cast<vec_t*>(pb + (size_t)c * LDP);
-    for (int v = t; v < Np / VE; v += JAC_NT) dst[v] = src[v];
+  {
+    const int nv = Np / VE, cpp = JAC_NT / 256;  // columns per pass when nv <= 256
+    const int lane = (nv <= 256) ? t % 256 : t, c0 = (nv <= 256) ? t / 256 : 0, cst = (nv <= 256) ? cpp : 1;
+    const int vst = (nv <= 256) ? 256 : JAC_NT;
+#pragma unroll 4
+    for (int c = c0; c < P; c += cst) {
+      const vec_t* src = reinterpret_cast<const vec_t*>(Bm + (int64_t)gcol(c) * Np);
+      vec_t* dst = reinterpret_cast<vec_t*>(pb + (size_t)c * LDP);
+      for (int v = lane; v < nv; v += vst) dst[v] = src[v];
+    }
   }
   const T tol = T(a.tol);
   int sw = sweep;
@@ -397,7 +442,8 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
     if (t == 0) pass_rot = 0;
     __syncthreads();
     // ---- 1. Gram of the panel
-    jac_gram<T, P>(pb, Np, LDP, G, t);
+    jac_gram<T, P>(pb, Np, LDP, G, Z, t);
+    __syncthreads();
     for (int e = t; e < P * P; e += JAC_NT) Z[e] = (e % P == e / P) ? T(1) : T(0);
     __syncthreads();
     // ---- 2. plane rotations on G (G <- J^T G J), accumulating Z <- Z J.
@@ -412,12 +458,15 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
         else { p = t; q = BW + (t + st) % BW; }
         const T gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
         T c = T(1), s = T(0);
-        if (gpq != T(0) && fabs(gpq) > tol * dev_sqrt(gpp * gqq)) {
+        if (gpq != T(0) && gpq * gpq > tol * tol * (gpp * gqq)) {
+          // tan(2 theta) = b / a with theta in (-pi/4, pi/4]:
+          //   cos(2 theta) = |a| / r,  c = sqrt((1 + cos 2theta) / 2),  s = sin(2 theta) / (2 c)
           const T aa = gqq - gpp, bb = T(2) * gpq;
-          const T rr = dev_sqrt(aa * aa + bb * bb);
-          const T tt = (aa >= T(0) ? bb : -bb) / (fabs(aa) + rr);
-          c = T(1) / dev_sqrt(T(1) + tt * tt);
-          s = c * tt;
+          const T ir = dev_rsqrt(aa * aa + bb * bb);
+          const T y = T(0.5) * (T(1) + fabs(aa) * ir);
+          const T ry = dev_rsqrt(y);
+          c = y * ry;
+          s = (aa >= T(0) ? bb : -bb) * ir * T(0.5) * ry;
           atomicAdd(&pass_rot, 1);
         }
         rc[t] = c;
@@ -472,10 +521,14 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   }
   __syncthreads();
   if (any_rot) {
-    for (int c = 0; c < P; ++c) {
+    const int nv = Np / VE, cpp = JAC_NT / 256;
+    const int lane = (nv <= 256) ? t % 256 : t, c0 = (nv <= 256) ? t / 256 : 0, cst = (nv <= 256) ? cpp : 1;
+    const int vst = (nv <= 256) ? 256 : JAC_NT;
+#pragma unroll 4
+    for (int c = c0; c < P; c += cst) {
       vec_t* dst = reinterpret_cast<vec_t*>(Bm + (int64_t)gcol(c) * Np);
       const vec_t* src = reinterpret_cast<const vec_t*>(pb + (size_t)c * LDP);
-      for (int v = t; v < Np / VE; v += JAC_NT) dst[v] = src[v];
+      for (int v = lane; v < nv; v += vst) dst[v] = src[v];
     }
   }
   if (!single && t == 0 && wg_rot > 0) atomicAdd(&cnt[sweep], wg_rot);
