@@ -275,7 +275,9 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   ja.Np = p.Np; ja.N = N; ja.b = p.bw; ja.max_sweeps = MAX_SWEEPS;
   ja.off_B = p.oB; ja.off_V = p.oV; ja.off_cnt = p.oCnt;
   const double eps = sizeof(TC) == 8 ? 2.220446049250313e-16 : 1.1920929e-07;
-  ja.tol = eps * sqrt((double)N);
+  // stopping rule |g_pq| <= tol sqrt(g_pp g_qq): machine precision in the FP64 and
+  // FP32 forms; in the mixed form 1e-10 (FP64 arithmetic, far below its BF16 error)
+  ja.tol = PR == KFB_BF16_MIXED ? 1e-10 : eps * sqrt((double)N);
   const int nb = p.Np / p.bw;
   {
   StageTimer st_jac("jacobi", s, nb == 2 ? 1 : MAX_SWEEPS * (nb - 1));
