@@ -82,6 +82,52 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"n={N_BATCH} on the host, median {med:.3f} s each"}
 
 
+def serve_leg(torch, kfb, dev, args):
+    """Open-loop Poisson serving at the headline shape: 70% updates (uniform over
+    layer and factor), 30% preconditionings (uniform layer), continuous batching."""
+    from paper_2210_08494_amd import serve
+    L = args.layers
+    layers = [(D, D, R, R)] * L
+    res = {}
+    srv = serve.Server(layers, n_max=N_BATCH, rho=RHO, prec=kfb.KFB_BF16_MIXED, streams=4,
+                       byte_budget=24 << 30, max_group=48)
+    pool = {}
+    for l in range(L):
+        for s_i, side in enumerate(("A", "G")):
+            pool[(l, side)] = _gen_batches(torch, dev, 2, N_BATCH, D, seed=5000 + 2 * l + s_i,
+                                           dtype=torch.bfloat16)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    grads = [torch.randn(D, D, generator=gen, device=dev) for _ in range(L)]
+    outs = [torch.empty(D, D, device=dev) for _ in range(L)]
+    torch.cuda.synchronize()
+    for j in range(2):  # bring every state to r + n modes
+        for l in range(L):
+            for side in ("A", "G"):
+                srv.submit(serve.UpdateRequest(l, side, pool[(l, side)][j]))
+    srv.drain()
+    torch.cuda.synchronize()
+
+    def make(i, rng):
+        l = int(rng.integers(L))
+        if rng.random() < 0.7:
+            side = "A" if rng.random() < 0.5 else "G"
+            return serve.UpdateRequest(l, side, pool[(l, side)][i % 2])
+        return serve.PrecondRequest(l, grads[l], outs[l], LAM, LAM)
+
+    for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+        srv.stats = serve.ServerStats()
+        wall, done = serve.poisson_run(srv, make, rate, args.serve_requests, seed=int(rate))
+        lat_ms = [1e3 * (r.t_done - r.t_arrival) for r in done]
+        upd = sum(1 for r in done if isinstance(r, serve.UpdateRequest))
+        res[f"{int(rate)}_req_per_s"] = {
+            "requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
+            "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
+            "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
+            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +136,8 @@ def main():
     ap.add_argument("--layers", type=int, default=LAYERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-updates", type=int, default=6)
+    ap.add_argument("--serve-requests", type=int, default=1200)
+    ap.add_argument("--serve-rates", default="400,2000")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (factor states "
@@ -212,6 +260,8 @@ def main():
         torch.cuda.synchronize()
         lat1.append(e0.elapsed_time(e1))
 
+    serving = serve_leg(torch, kfb, dev, args) if args.serve_requests > 0 else None
+
     out = {
         "metric": "B-updates/s + p50/p99 latency, BF16-mixed vs FP32 plain, d=4096 r=256 n=256",
         "value": round(bups, 2),
@@ -236,6 +286,7 @@ def main():
                        "single_update_p99": round(_percentile(lat1, 99), 3),
                        "note": "closed loop; step = 48 updates + 24 preconditionings"},
         "fp32_plain": fp32_plain,
+        "serving": serving,
         "roofline": roofline,
         "stages": stages,
         "status_events": sorted(set(status)),
