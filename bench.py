@@ -152,6 +152,10 @@ def main():
     S = 2 * L
     MIX = kfb.KFB_BF16_MIXED
 
+    # ---- autotune the core eigensolver's block width for this bucket (untimed)
+    from paper_2210_08494_amd import tune
+    best_bw, tune_ms = tune.tune_jacobi(MIX, D, R, N_BATCH, count=S, reps=2, device=dev)
+
     # ---- states: even index = A factor (d_in), odd = Gamma factor (d_out) of a layer
     states = [kfb.Factor(D, R, N_BATCH, RHO, MIX, device=dev) for _ in range(S)]
     batches = [_gen_batches(torch, dev, S, N_BATCH, D, seed=1000 + j, dtype=torch.bfloat16) for j in range(2)]
@@ -290,6 +294,8 @@ def main():
         "roofline": roofline,
         "stages": stages,
         "status_events": sorted(set(status)),
+        "autotune": {"jacobi_block_width": best_bw,
+                     "candidates_ms": {str(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

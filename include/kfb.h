@@ -150,6 +150,16 @@ int kfb_state_load(kfb_state_t st, const void* U, int64_t ldu, const void* D, in
 /* Read and clear the device status word (synchronises the given stream). */
 int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
 
+/* Tuning table of the core eigensolver (filled by the project's autotuner,
+ * paper_2210_08494_amd/tune.py): for cores of size N = r_eff + n in precision
+ * form prec, use column blocks of width bw (one of 4, 8, 16, 32; the LDS
+ * limit must admit it, else KFB_EINVAL).  bw = 0 removes the entry, restoring
+ * the built-in choice (the widest block that fits).  Affects calls made
+ * after it returns; results of a given table are deterministic.
+ * kfb_tune_get_jacobi reports the width and padded size a call would use. */
+int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw);
+int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np);
+
 /* Optional stage timing (diagnostics).  While enabled, each stage of the
  * update and precondition calls (projection, residual, CholeskyQR, core
  * assembly, Jacobi rounds, finalize, rotation; the apply's products) is

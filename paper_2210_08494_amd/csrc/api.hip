@@ -95,6 +95,22 @@ struct StageTimer {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Tuning table: core eigensolver block width per (precision form, N)
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  int prec, N, bw;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int tuned_bw(int prec, int N) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : g_tune)
+    if (e.prec == prec && e.N == N) return e.bw;
+  return 0;
+}
+
 inline size_t u_elem(int prec) { return prec == KFB_FP64 ? 8 : 4; }
 inline size_t d_elem(int prec) { return prec == KFB_FP32 ? 4 : 8; }
 inline size_t m_elem(int prec) { return prec == KFB_FP64 ? 8 : (prec == KFB_FP32 ? 4 : 2); }
@@ -135,7 +151,14 @@ template <int PR>
 bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, UpdPlan* p) {
   typedef Ty<PR> T;
   p->d = d; p->ldu = ldu; p->ldm = ldm; p->r = r; p->n = n; p->N = r + n;
-  p->bw = jacobi_pick_block(p->N, (int)sizeof(typename T::Core), &p->Np);
+  const int tbw = tuned_bw(PR, p->N);
+  const int tNp = tbw ? jacobi_block_fits(p->N, (int)sizeof(typename T::Core), tbw) : 0;
+  if (tNp) {
+    p->bw = tbw;
+    p->Np = tNp;
+  } else {
+    p->bw = jacobi_pick_block(p->N, (int)sizeof(typename T::Core), &p->Np);
+  }
   if (p->bw == 0) return false;
   auto ks_for = [&](int m, int nn, int64_t k) {
     // split depends on the problem's own shape only, never on its batch-mates
@@ -687,6 +710,32 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream) {
   KFB_TRY(hipStreamSynchronize(s));
   *events = v;
   return KFB_OK;
+}
+
+int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw) {
+  if (prec < KFB_FP64 || prec > KFB_BF16_MIXED || N <= 0) return KFB_EINVAL;
+  const int eb = prec == KFB_FP32 ? 4 : 8;
+  if (bw != 0 && jacobi_block_fits(N, eb, bw) == 0) return KFB_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (size_t i = 0; i < g_tune.size(); ++i)
+    if (g_tune[i].prec == prec && g_tune[i].N == N) {
+      if (bw == 0) g_tune.erase(g_tune.begin() + i);
+      else g_tune[i].bw = bw;
+      return KFB_OK;
+    }
+  if (bw != 0) g_tune.push_back(TuneEntry{prec, N, bw});
+  return KFB_OK;
+}
+
+int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np) {
+  if (prec < KFB_FP64 || prec > KFB_BF16_MIXED || N <= 0) return KFB_EINVAL;
+  const int eb = prec == KFB_FP32 ? 4 : 8;
+  int b = tuned_bw(prec, N), np = 0;
+  if (b) np = jacobi_block_fits(N, eb, b);
+  if (!np) b = jacobi_pick_block(N, eb, &np);
+  if (bw) *bw = b;
+  if (Np) *Np = np;
+  return b ? KFB_OK : KFB_EINVAL;
 }
 
 int kfb_profile_enable(int on) {

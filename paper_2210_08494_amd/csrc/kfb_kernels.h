@@ -57,6 +57,8 @@ template <typename T>
 hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round,
                         hipStream_t s);
 int jacobi_pick_block(int N, int elem_bytes, int* Np);
+// padded size for a given block width, or 0 if the panel does not fit LDS
+int jacobi_block_fits(int N, int elem_bytes, int bw);
 
 struct FinArgs {
   int N, Np, max_sweeps;

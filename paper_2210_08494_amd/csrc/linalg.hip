@@ -417,7 +417,7 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   T* rc = Z + P * P;                         // rotation c, s per pair of a step
   T* rsn = rc + NP2;
   __shared__ int pp[P / 2], qq[P / 2];
-  __shared__ int wg_rot, pass_rot, any_rot;
+  __shared__ int wg_rot, pass_rot, any_rot, any_off;
   const int t = threadIdx.x;
   if (t == 0) { wg_rot = 0; any_rot = 0; }
 
@@ -443,14 +443,23 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
     __syncthreads();
     // ---- 1. Gram of the panel
     jac_gram<T, P>(pb, Np, LDP, G, Z, t);
+    if (t == 0) any_off = 0;
     __syncthreads();
-    for (int e = t; e < P * P; e += JAC_NT) Z[e] = (e % P == e / P) ? T(1) : T(0);
+    for (int e = t; e < P * P; e += JAC_NT) {
+      const int i = e / P, j = e % P;
+      Z[e] = (i == j) ? T(1) : T(0);
+      // pairs this visit may rotate: every pair in round 0 / single panel, cross pairs otherwise
+      if (i < j && (single || round == 0 || (i < BW && j >= BW))) {
+        const T gij = G[e];
+        if (gij != T(0) && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
+      }
+    }
     __syncthreads();
     // ---- 2. plane rotations on G (G <- J^T G J), accumulating Z <- Z J.
     // Round 0 of a sweep (and the single-panel case) runs a full tournament over
     // the P columns; later rounds only the BW x BW pairs across the two blocks.
     const bool full = single || round == 0;
-    const int nsteps = full ? P - 1 : BW;
+    const int nsteps = any_off ? (full ? P - 1 : BW) : 0;  // nothing to rotate: skip the sweep
     for (int st = 0; st < nsteps; ++st) {
       if (t < NP2) {
         int p, q;
@@ -532,6 +541,16 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
     }
   }
   if (!single && t == 0 && wg_rot > 0) atomicAdd(&cnt[sweep], wg_rot);
+}
+
+int jacobi_block_fits(int N, int elem_bytes, int bw) {
+  if (bw != 4 && bw != 8 && bw != 16 && bw != 32) return 0;
+  const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
+  const size_t P = 2 * (size_t)bw;
+  const size_t ldp = (size_t)Np + 16 / elem_bytes;
+  if ((size_t)Np * P * elem_bytes <= (size_t)JAC_LDS_BYTES && (ldp * P + 2 * P * P + P) * elem_bytes <= (size_t)JAC_LDS_MAX)
+    return Np;
+  return 0;
 }
 
 int jacobi_pick_block(int N, int elem_bytes, int* Np_out) {

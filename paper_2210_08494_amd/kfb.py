@@ -44,6 +44,8 @@ _SIGS = {
     "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
     "kfb_state_load": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i64, _vp]),
     "kfb_state_status": (ctypes.c_int, [_vp, ctypes.POINTER(_u32), _vp]),
+    "kfb_tune_set_jacobi": (ctypes.c_int, [_i32, _i32, _i32]),
+    "kfb_tune_get_jacobi": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kfb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "kfb_profile_report": (ctypes.c_int, [ctypes.c_char_p, _sz, ctypes.c_int]),
     "kfb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -262,3 +264,13 @@ def profile_report(reset: bool = True) -> dict:
     buf = ctypes.create_string_buffer(1 << 16)
     _check(load().kfb_profile_report(buf, len(buf), 1 if reset else 0), "kfb_profile_report")
     return json.loads(buf.value.decode() or "{}")
+
+
+def tune_set_jacobi(prec: int, N: int, bw: int):
+    _check(load().kfb_tune_set_jacobi(int(prec), int(N), int(bw)), "kfb_tune_set_jacobi")
+
+
+def tune_get_jacobi(prec: int, N: int):
+    bw, Np = _i32(), _i32()
+    _check(load().kfb_tune_get_jacobi(int(prec), int(N), ctypes.byref(bw), ctypes.byref(Np)), "kfb_tune_get_jacobi")
+    return bw.value, Np.value
