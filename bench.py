@@ -152,7 +152,7 @@ def main():
     S = 2 * L
     MIX = kfb.KFB_BF16_MIXED
 
-    # ---- autotune the core eigensolver's block width for this bucket (untimed)
+    # ---- autotune the core eigensolver's configuration for this bucket (untimed)
     from paper_2210_08494_amd import tune
     best_bw, tune_ms = tune.tune_jacobi(MIX, D, R, N_BATCH, count=S, reps=2, device=dev)
 
@@ -294,8 +294,8 @@ def main():
         "roofline": roofline,
         "stages": stages,
         "status_events": sorted(set(status)),
-        "autotune": {"jacobi_block_width": best_bw,
-                     "candidates_ms": {str(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},
+        "autotune": {"jacobi_config": tune.config_name(best_bw) if best_bw else None,
+                     "candidates_ms": {tune.config_name(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -152,11 +152,18 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
 
 /* Tuning table of the core eigensolver (filled by the project's autotuner,
  * paper_2210_08494_amd/tune.py): for cores of size N = r_eff + n in precision
- * form prec, use column blocks of width bw (one of 4, 8, 16, 32; the LDS
- * limit must admit it, else KFB_EINVAL).  bw = 0 removes the entry, restoring
- * the built-in choice (the widest block that fits).  Affects calls made
+ * form prec, use the configuration bw:
+ *   4, 8, 16, 32             column blocks of that width, the block pair's
+ *                            panel held in LDS (the LDS limit must admit it);
+ *   KFB_JAC_STREAMED | 16/32 column blocks of that width, panels read from
+ *                            global memory (FP64 core: the FP64 and
+ *                            BF16-mixed forms; at least four blocks).
+ * Inadmissible values give KFB_EINVAL.  bw = 0 removes the entry, restoring
+ * the built-in choice (the widest LDS block that fits).  Affects calls made
  * after it returns; results of a given table are deterministic.
- * kfb_tune_get_jacobi reports the width and padded size a call would use. */
+ * kfb_tune_get_jacobi reports the configuration and padded size a call would
+ * use. */
+#define KFB_JAC_STREAMED 0x100
 int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw);
 int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np);
 

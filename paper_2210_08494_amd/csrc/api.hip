@@ -301,7 +301,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   // stopping rule |g_pq| <= tol sqrt(g_pp g_qq): machine precision in the FP64 and
   // FP32 forms; in the mixed form 1e-10 (FP64 arithmetic, far below its BF16 error)
   ja.tol = PR == KFB_BF16_MIXED ? 1e-10 : eps * sqrt((double)N);
-  const int nb = p.Np / p.bw;
+  const int nb = p.Np / (p.bw & 0xff);
   {
   StageTimer st_jac("jacobi", s, nb == 2 ? 1 : MAX_SWEEPS * (nb - 1));
   if (nb == 2) {

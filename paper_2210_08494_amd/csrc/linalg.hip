@@ -543,7 +543,386 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   if (!single && t == 0 && wg_rot > 0) atomicAdd(&cnt[sweep], wg_rot);
 }
 
-int jacobi_block_fits(int N, int elem_bytes, int bw) {
+// ---------------------------------------------------------------------------
+// Streamed-panel variants (FP64).  P = 64: panels of two 32-column blocks.
+//
+// Same visit as above (Gram of the panel, one sweep of plane rotations on the
+// Gram, panel and V times the accumulated rotation), but the panel is not
+// staged in LDS: the Gram and the products read B and V straight from global
+// memory as MFMA operands.  LDS holds only the 64 x 64 Gram and rotation
+// (64 KB), so two workgroups share a CU and hide each other's latency, and
+// the wider panel halves the number of visits per sweep relative to 32
+// columns.  For the Gram, each lane feeds four consecutive rows of its column
+// to four MFMA steps (the row order of a sum does not matter), so every load
+// is a full 32-byte segment.
+// ---------------------------------------------------------------------------
+constexpr int JG_NT = 512;
+constexpr int JG_P = 64, JG_BW = 32;
+
+__global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
+                                                            int round) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char jg_smem[];
+  constexpr int P = JG_P, BW = JG_BW, NP2 = P / 2;
+  double* G = reinterpret_cast<double*>(jg_smem);  // G[i*P + j]
+  double* Z = G + P * P;                           // Z[i*P + j]; also Gram scratch
+  __shared__ double rc[NP2], rsn[NP2];
+  __shared__ int pp[NP2], qq[NP2];
+  __shared__ int pass_rot, any_off;
+  const Rec& rec = recs[blockIdx.y];
+  int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
+  const int Np = a.Np;
+  const int nb = Np / BW;  // >= 4
+  if (sweep > 0 && cnt[sweep - 1] == 0) return;
+  double* Bm = at<double>(rec, WS, a.off_B);
+  double* Vm = at<double>(rec, WS, a.off_V);
+  int I, J;
+  tour_pair(nb, round, blockIdx.x, &I, &J);
+  auto gcol = [&](int c) { return c < BW ? I * BW + c : J * BW + (c - BW); };
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  const double tol = a.tol;
+  typedef __attribute__((__vector_size__(4 * sizeof(double)))) double dv4;
+  {
+    if (t == 0) pass_rot = 0;
+    __syncthreads();
+    // ---- 1. Gram: 10 upper 16x16 tiles x 2 row halves over 8 waves
+    for (int item = w; item < 20; item += JG_NT / 64) {
+      const int tile = item % 10, kh = item / 10;
+      int ti = 0, rem = tile;
+      while (rem >= 4 - ti) { rem -= 4 - ti; ++ti; }
+      const int tj = ti + rem;
+      const double* ca = Bm + (int64_t)gcol(ti * 16 + (l % 16)) * Np + 4 * (l / 16);
+      const double* cb = Bm + (int64_t)gcol(tj * 16 + (l % 16)) * Np + 4 * (l / 16);
+      jac_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      const int kb = kh * (Np / 2), ke = kb + Np / 2;
+      for (int k0 = kb; k0 < ke; k0 += 16) {
+        const dv4 xa = *reinterpret_cast<const dv4*>(ca + k0);
+        const dv4 xb = *reinterpret_cast<const dv4*>(cb + k0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0], xb[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[1], xb[1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[2], xb[2], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[3], xb[3], acc1, 0, 0, 0);
+      }
+      double* dst = kh == 0 ? G : Z;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ti * 16 + l / 16 + 4 * v, j = tj * 16 + l % 16;
+        dst[i * P + j] = acc0[v] + acc1[v];
+      }
+    }
+    if (t == 0) any_off = 0;
+    __syncthreads();
+    for (int e = t; e < P * P; e += JG_NT) {
+      const int i = e / P, j = e % P;
+      if ((i / 16) <= (j / 16)) {  // upper tiles: add the two row halves, mirror below
+        const double x = G[e] + Z[e];
+        G[e] = x;
+        if ((i / 16) < (j / 16)) G[j * P + i] = x;
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < P * P; e += JG_NT) {
+      const int i = e / P, j = e % P;
+      Z[e] = (i == j) ? 1.0 : 0.0;
+      if (i < j && (round == 0 || (i < BW && j >= BW))) {
+        const double gij = G[e];
+        if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
+      }
+    }
+    __syncthreads();
+    // ---- 2. plane rotations on G, accumulating Z (as in the LDS-panel kernel)
+    const bool full = round == 0;
+    const int nsteps = any_off ? (full ? P - 1 : BW) : 0;
+    for (int st = 0; st < nsteps; ++st) {
+      if (t < NP2) {
+        int p, q;
+        if (full) tour_pair(P, st, t, &p, &q);
+        else { p = t; q = BW + (t + st) % BW; }
+        const double gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
+        double c = 1.0, s = 0.0;
+        if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
+          const double aa = gqq - gpp, bb = 2.0 * gpq;
+          const double ir = dev_rsqrt(aa * aa + bb * bb);
+          const double y = 0.5 * (1.0 + fabs(aa) * ir);
+          const double ry = dev_rsqrt(y);
+          c = y * ry;
+          s = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
+          atomicAdd(&pass_rot, 1);
+        }
+        rc[t] = c;
+        rsn[t] = s;
+        pp[t] = p;
+        qq[t] = q;
+      }
+      __syncthreads();
+      for (int e = t; e < NP2 * NP2; e += JG_NT) {
+        const int ia = e / NP2, ib = e % NP2;
+        const double sa = rsn[ia], sb = rsn[ib];
+        if (sa == 0.0 && sb == 0.0) continue;
+        const double ca = rc[ia], cb = rc[ib];
+        const int pa = pp[ia], qa = qq[ia], pbb = pp[ib], qb = qq[ib];
+        const double g00 = G[pa * P + pbb], g01 = G[pa * P + qb], g10 = G[qa * P + pbb], g11 = G[qa * P + qb];
+        const double r00 = cb * g00 - sb * g01, r01 = sb * g00 + cb * g01;
+        const double r10 = cb * g10 - sb * g11, r11 = sb * g10 + cb * g11;
+        G[pa * P + pbb] = ca * r00 - sa * r10;
+        G[qa * P + pbb] = sa * r00 + ca * r10;
+        G[pa * P + qb] = ca * r01 - sa * r11;
+        G[qa * P + qb] = sa * r01 + ca * r11;
+      }
+      for (int e = t; e < NP2 * P; e += JG_NT) {
+        const int ia = e / P, i = e % P;
+        const double sa = rsn[ia];
+        if (sa == 0.0) continue;
+        const double ca = rc[ia];
+        const int pa = pp[ia], qa = qq[ia];
+        const double zp = Z[i * P + pa], zq = Z[i * P + qa];
+        Z[i * P + pa] = ca * zp - sa * zq;
+        Z[i * P + qa] = sa * zp + ca * zq;
+      }
+      __syncthreads();
+    }
+    const int nrot = pass_rot;
+    if (nrot > 0) {
+      // ---- 3. X <- X Z for X = panel of B, then of V, in global memory, as (Z^T X^T)
+      for (int pass = 0; pass < 2; ++pass) {
+        double* X = pass == 0 ? Bm : Vm;
+        for (int rb = w; rb < Np / 16; rb += JG_NT / 64) {
+          jac_d4 acc[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c] = jac_d4{0.0, 0.0, 0.0, 0.0};
+          const int row = rb * 16 + (l % 16);
+#pragma unroll 4
+          for (int k0 = 0; k0 < P; k0 += 4) {
+            const double xb = X[row + (int64_t)gcol(k0 + l / 16) * Np];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const double za = Z[(k0 + l / 16) * P + c * 16 + (l % 16)];
+              acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb, acc[c], 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) X[row + (int64_t)gcol(c * 16 + l / 16 + 4 * v) * Np] = acc[c][v];
+        }
+      }
+    }
+    if (t == 0 && nrot > 0) atomicAdd(&cnt[sweep], nrot);
+  }
+}
+
+// P = 32 (two 16-column blocks), four waves, several workgroups per CU.  The
+// Gram is split over the waves by 16-row steps and their partial tiles are
+// summed in a fixed order; one wave runs the plane rotations on the 32 x 32
+// Gram with no workgroup barrier between steps (a wave's LDS accesses are
+// performed in program order); the panel products keep the rotation's MFMA
+// operands in registers and prefetch the next 16-row block of the panel.
+constexpr int JS_NT = 256, JS_P = 32, JS_BW = 16;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void js_pair(bool full, int st, int ia, int* p, int* q) {
+  if (full) tour_pair(JS_P, st, ia, p, q);
+  else { *p = ia; *q = JS_BW + (ia + st) % JS_BW; }
+}
+
+__global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
+                                                            int round) {
+  constexpr int P = JS_P, BW = JS_BW, NR = P / 2, NW = JS_NT / 64;
+  __shared__ __attribute__((aligned(16))) double G[P * P];
+  __shared__ __attribute__((aligned(16))) double red[NW * 3 * 256];  // Gram partials; Z (P x P) reuses it
+  __shared__ double rc[NR], rsn[NR];
+  __shared__ int pass_rot, any_off;
+  double* Z = red;
+  const Rec& rec = recs[blockIdx.y];
+  int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
+  const int Np = a.Np, Ns = Np / 16;
+  if (sweep > 0 && cnt[sweep - 1] == 0) return;
+  double* Bm = at<double>(rec, WS, a.off_B);
+  double* Vm = at<double>(rec, WS, a.off_V);
+  int I, J;
+  tour_pair(Np / BW, round, blockIdx.x, &I, &J);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const double tol = a.tol;
+  const bool full = round == 0;
+
+  // ---- 1. Gram of the panel [B_I B_J]
+  {
+    const int r0 = 4 * (l >> 4);
+    const double* ca = Bm + (int64_t)(I * BW + (l & 15)) * Np + r0;
+    const double* cb = Bm + (int64_t)(J * BW + (l & 15)) * Np + r0;
+    jac_d4 g00 = {0.0, 0.0, 0.0, 0.0}, g01 = g00, g11 = g00;
+    jac_d4 xa = g00, xb = g00, ya = g00, yb = g00;
+    int st = w;
+    if (st < Ns) {
+      xa = *reinterpret_cast<const jac_d4*>(ca + 16 * st);
+      xb = *reinterpret_cast<const jac_d4*>(cb + 16 * st);
+    }
+    for (; st < Ns; st += NW) {
+      if (st + NW < Ns) {
+        ya = *reinterpret_cast<const jac_d4*>(ca + 16 * (st + NW));
+        yb = *reinterpret_cast<const jac_d4*>(cb + 16 * (st + NW));
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        g00 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[e], xa[e], g00, 0, 0, 0);
+        g01 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[e], xb[e], g01, 0, 0, 0);
+        g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[e], xb[e], g11, 0, 0, 0);
+      }
+      xa = ya;
+      xb = yb;
+    }
+    double* rw = red + w * 768;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = ((l >> 4) + 4 * v) * 16 + (l & 15);
+      rw[e] = g00[v];
+      rw[256 + e] = g01[v];
+      rw[512 + e] = g11[v];
+    }
+  }
+  if (t == 0) { any_off = 0; pass_rot = 0; }
+  __syncthreads();
+  for (int e = t; e < 768; e += JS_NT) {
+    const double x = ((red[e] + red[768 + e]) + red[1536 + e]) + red[2304 + e];
+    const int tile = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    const int ti = tile == 2 ? 16 : 0, tj = tile == 0 ? 0 : 16;
+    G[(ti + i) * P + tj + j] = x;
+    if (tile == 1) G[(16 + j) * P + i] = x;
+  }
+  __syncthreads();
+  for (int e = t; e < P * P; e += JS_NT) {
+    const int i = e >> 5, j = e & 31;
+    Z[e] = (i == j) ? 1.0 : 0.0;
+    if (i < j && (full || (i < BW && j >= BW))) {
+      const double gij = G[e];
+      if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. plane rotations on G, accumulated into Z, by wave 0
+  if (w == 0 && any_off) {
+    const int nsteps = full ? P - 1 : BW;
+    int nrot = 0;
+    for (int st = 0; st < nsteps; ++st) {
+      bool rot = false;
+      if (l < NR) {
+        int p, q;
+        js_pair(full, st, l, &p, &q);
+        const double gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
+        double c = 1.0, sn = 0.0;
+        if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
+          const double aa = gqq - gpp, bb = 2.0 * gpq;
+          const double ir = dev_rsqrt(aa * aa + bb * bb);
+          const double y = 0.5 * (1.0 + fabs(aa) * ir);
+          const double ry = dev_rsqrt(y);
+          c = y * ry;
+          sn = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
+          rot = true;
+        }
+        rc[l] = c;
+        rsn[l] = sn;
+      }
+      nrot += __popcll(__ballot(rot));
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int ia = (l >> 4) + 4 * k, ib = l & 15;
+        const double sa = rsn[ia], sb = rsn[ib];
+        if (sa == 0.0 && sb == 0.0) continue;
+        const double ca = rc[ia], cb = rc[ib];
+        int pa, qa, pb, qb;
+        js_pair(full, st, ia, &pa, &qa);
+        js_pair(full, st, ib, &pb, &qb);
+        const double g00 = G[pa * P + pb], g01 = G[pa * P + qb], g10 = G[qa * P + pb], g11 = G[qa * P + qb];
+        const double r00 = cb * g00 - sb * g01, r01 = sb * g00 + cb * g01;
+        const double r10 = cb * g10 - sb * g11, r11 = sb * g10 + cb * g11;
+        G[pa * P + pb] = ca * r00 - sa * r10;
+        G[qa * P + pb] = sa * r00 + ca * r10;
+        G[pa * P + qb] = ca * r01 - sa * r11;
+        G[qa * P + qb] = sa * r01 + ca * r11;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int ia = (l >> 5) + 2 * k, i = l & 31;
+        const double sa = rsn[ia];
+        if (sa == 0.0) continue;
+        const double ca = rc[ia];
+        int pa, qa;
+        js_pair(full, st, ia, &pa, &qa);
+        const double zp = Z[i * P + pa], zq = Z[i * P + qa];
+        Z[i * P + pa] = ca * zp - sa * zq;
+        Z[i * P + qa] = sa * zp + ca * zq;
+      }
+      wave_sync();
+    }
+    if (l == 0) pass_rot = nrot;
+  }
+  __syncthreads();
+  const int nrot = pass_rot;
+  if (nrot == 0) return;
+
+  // ---- 3. [B_I B_J] <- [B_I B_J] Z and [V_I V_J] <- [V_I V_J] Z, as (Z^T X^T) on MFMA
+  double za[2][8];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    za[0][kk] = Z[(4 * kk + (l >> 4)) * P + (l & 15)];
+    za[1][kk] = Z[(4 * kk + (l >> 4)) * P + 16 + (l & 15)];
+  }
+  int co[8], oo[8];  // source column offsets (k = 4 kk + l/16), destination (16 c + l/16 + 4 v)
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    const int k = 4 * kk + (l >> 4);
+    co[kk] = (k < BW ? I * BW + k : J * BW + k - BW) * Np;
+    const int c = (kk >> 2) * 16 + (l >> 4) + 4 * (kk & 3);
+    oo[kk] = (c < BW ? I * BW + c : J * BW + c - BW) * Np;
+  }
+  const int njobs = 2 * Ns;  // (matrix, 16-row block)
+  double xb[8], yb[8];
+  int job = w;
+  if (job < njobs) {
+    const double* src = (job < Ns ? Bm : Vm) + (job < Ns ? job : job - Ns) * 16 + (l & 15);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) xb[kk] = src[co[kk]];
+  }
+  for (; job < njobs; job += NW) {
+    const int nx = job + NW;
+    if (nx < njobs) {
+      const double* src = (nx < Ns ? Bm : Vm) + (nx < Ns ? nx : nx - Ns) * 16 + (l & 15);
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) yb[kk] = src[co[kk]];
+    }
+    jac_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(za[0][kk], xb[kk], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(za[1][kk], xb[kk], acc1, 0, 0, 0);
+    }
+    double* dst = (job < Ns ? Bm : Vm) + (job < Ns ? job : job - Ns) * 16 + (l & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      dst[oo[v]] = acc0[v];
+      dst[oo[4 + v]] = acc1[v];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) xb[kk] = yb[kk];
+  }
+  if (t == 0) atomicAdd(&cnt[sweep], nrot);
+}
+
+int jacobi_block_fits(int N, int elem_bytes, int cfg) {
+  const int bw = cfg & 0xff;
+  if (cfg & JAC_STREAMED) {
+    // streamed panels: FP64, 16- or 32-column blocks, at least four blocks
+    if ((cfg & ~(JAC_STREAMED | 0xff)) || elem_bytes != 8 || (bw != 16 && bw != 32)) return 0;
+    const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
+    return Np / bw >= 4 ? Np : 0;
+  }
+  if (cfg & ~0xff) return 0;
   if (bw != 4 && bw != 8 && bw != 16 && bw != 32) return 0;
   const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
   const size_t P = 2 * (size_t)bw;
@@ -589,6 +968,21 @@ static hipError_t jac_launch(const Rec* recs, int nrec, const JacArgs& a, int sw
 
 template <typename T>
 hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round, hipStream_t s) {
+  if (a.b & JAC_STREAMED) {
+    if (sizeof(T) != 8) return hipErrorInvalidValue;
+    if ((a.b & 0xff) == JS_BW) {
+      hipLaunchKernelGGL(jacobi_s_kernel, dim3(a.Np / JS_BW / 2, nrec), dim3(JS_NT), 0, s, recs, a, sweep, round);
+      return hipGetLastError();
+    }
+    static bool attr = false;
+    const size_t lds = 2 * 64 * 64 * sizeof(double);
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)jacobi_g_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr = true;
+    }
+    hipLaunchKernelGGL(jacobi_g_kernel, dim3(a.Np / JG_BW / 2, nrec), dim3(JG_NT), lds, s, recs, a, sweep, round);
+    return hipGetLastError();
+  }
   switch (a.b) {
     case 32: return jac_launch<T, 32>(recs, nrec, a, sweep, round, s);
     case 16: return jac_launch<T, 16>(recs, nrec, a, sweep, round, s);

@@ -1,9 +1,11 @@
-"""Autotuner for the core eigensolver's block width.
+"""Autotuner for the core eigensolver's configuration.
 
 For a shape bucket (precision form, width d, rank r, batch n, group size),
-times grouped Brand updates under every admissible block width of the block
-Jacobi eigensolver (the LDS limit bounds it) and installs the fastest in the
-library's tuning table (kfb_tune_set_jacobi), keyed by (precision, N = r + n).
+times grouped Brand updates under every admissible configuration of the block
+Jacobi eigensolver (block width, with the block pair's panel in LDS where the
+LDS limit admits it, or streamed from global memory) and installs the fastest
+in the library's tuning table (kfb_tune_set_jacobi), keyed by
+(precision, N = r + n).
 Results with a given table are deterministic; different widths change only
 the rotation order (all within the form's tolerance).
 """
@@ -14,8 +16,15 @@ import time
 from . import kfb
 
 
+DEFAULT_CANDIDATES = (4, 8, 16, 32, kfb.KFB_JAC_STREAMED | 16, kfb.KFB_JAC_STREAMED | 32)
+
+
+def config_name(cfg: int) -> str:
+    return f"s{cfg & 0xff}" if cfg & kfb.KFB_JAC_STREAMED else str(cfg)
+
+
 def tune_jacobi(prec: int, d: int, r: int, n: int, count: int = 8, reps: int = 3, device="cuda",
-                candidates=(4, 8, 16, 32), seed: int = 0, verbose: bool = False):
+                candidates=DEFAULT_CANDIDATES, seed: int = 0, verbose: bool = False):
     import torch
     dev = torch.device(device)
     N = r + n
@@ -43,7 +52,7 @@ def tune_jacobi(prec: int, d: int, r: int, n: int, count: int = 8, reps: int = 3
             ts.append(time.perf_counter() - t0)
         timings[bw] = sorted(ts)[len(ts) // 2]
         if verbose:
-            print(f"tune prec={prec} N={N} count={count} bw={bw}: {1e3 * timings[bw]:.2f} ms", flush=True)
+            print(f"tune prec={prec} N={N} count={count} cfg={config_name(bw)}: {1e3 * timings[bw]:.2f} ms", flush=True)
         del states
     if not timings:
         kfb.tune_set_jacobi(prec, N, 0)

@@ -343,3 +343,57 @@ def test_mixed_wide_layer_spot(kfb):
         _announce(f"  step {k} e_rec {e:.3e} orth {oracle.e_orth(U):.2e}")
         assert e <= TOL[2]
     assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
+
+
+# ----------------------------------------------------------------------------
+# FP64 core eigensolver with panels read from global memory (streamed
+# configurations of the tuning table: 16- and 32-column blocks)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("bw", [16, 32])
+@pytest.mark.parametrize("d,r,n,steps", [(300, 80, 70, 4), (400, 96, 96, 4), (1024, 256, 256, 3), (90, 40, 24, 3)])
+def test_fp64_streamed_panel_eigensolver(kfb, d, r, n, steps, bw):
+    import torch
+    N = r + n
+    if N < 4 * bw:
+        pytest.skip("fewer than four blocks")
+    kfb.tune_set_jacobi(kfb.KFB_FP64, N, kfb.KFB_JAC_STREAMED | bw)
+    try:
+        _announce(f"fp64 streamed-panel Jacobi bw={bw} d={d} r={r} n={n} N={N}")
+        rho = 0.95
+        f = kfb.Factor(d, r, n, rho, kfb.KFB_FP64)
+        o = oracle.DenseFactor(d, r, rho)
+        for k in range(steps):
+            M = _batch(11, k, "A", n, d)
+            f.update(_to_dev(M, torch.float64))
+            o.update(M.T)
+            U, D = _front_np(f)
+            V, lamv = o.modes()
+            er, ed, eo = oracle.e_rec_dense(U, D, o.X), oracle.e_D(D, lamv), oracle.e_orth(U)
+            _announce(f"  step {k} e_rec {er:.3e} e_D {ed:.3e} orth {eo:.2e}")
+            assert er <= 1e-10 and ed <= 1e-10 and eo <= 1e-11
+        assert f.status() == 0
+    finally:
+        kfb.tune_set_jacobi(kfb.KFB_FP64, N, 0)
+
+
+@pytest.mark.parametrize("bw", [16, 32])
+def test_mixed_streamed_panel_headline_core(kfb, bw):
+    # the headline shape's core (N = 512) through the streamed-panel eigensolvers, vs Oracle-B
+    import torch
+    d, r, n, rho, steps = 4096, 256, 256, 0.95, 3
+    kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, r + n, kfb.KFB_JAC_STREAMED | bw)
+    try:
+        _announce(f"mixed streamed-panel bw={bw} d={d} r={r} n={n}")
+        f = kfb.Factor(d, r, n, rho, kfb.KFB_BF16_MIXED)
+        o = oracle.BrandFactor(d, r, rho)
+        for k in range(steps):
+            M = _batch(3, 200 + k, "A", n, d, prec=2)
+            f.update(_to_dev(M, torch.bfloat16))
+            o.update(M.T)
+            U, D = _front_np(f)
+            e = oracle.e_rec_lowrank(U, D, o.U, o.D)
+            _announce(f"  step {k} e_rec {e:.3e} orth {oracle.e_orth(U):.2e}")
+            assert e <= TOL[2]
+        assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
+    finally:
+        kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, r + n, 0)
