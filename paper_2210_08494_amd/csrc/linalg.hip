@@ -347,10 +347,10 @@ __device__ __forceinline__ void jac_gram(const T* pb, int Np, int LDP, T* G, T* 
 }
 
 // X <- X Z for a panel X (Np x P) read through xin(row, k) and written
-// through xout(row, j, value); Z row-major P x P in LDS.  FP64 with P >= 16
+// through xout(row, j, value); Z row-major P x P in LDS with row stride ZP.  FP64 with P >= 16
 // runs on MFMA as (Z^T X^T), so each lane owns one row and stores coalesce;
 // otherwise one row per thread with P independent FMA sums.
-template <typename T, int P, typename In, typename Out>
+template <typename T, int P, int ZP, typename In, typename Out>
 __device__ __forceinline__ void jac_apply(int Np, const T* Z, int t, In xin, Out xout) {
   if constexpr (sizeof(T) == 8 && P >= 16) {
     constexpr int NT16 = P / 16;
@@ -365,7 +365,7 @@ __device__ __forceinline__ void jac_apply(int Np, const T* Z, int t, In xin, Out
         const double xb = xin(row, k0 + l / 16);
 #pragma unroll
         for (int c = 0; c < NT16; ++c) {
-          const double za = Z[(k0 + l / 16) * P + c * 16 + (l % 16)];
+          const double za = Z[(k0 + l / 16) * ZP + c * 16 + (l % 16)];
           acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb, acc[c], 0, 0, 0);
         }
       }
@@ -382,7 +382,7 @@ __device__ __forceinline__ void jac_apply(int Np, const T* Z, int t, In xin, Out
 #pragma unroll 1
       for (int k = 0; k < P; ++k) {
         const T xk = xin(row, k);
-        const T* zr = Z + k * P;
+        const T* zr = Z + k * ZP;
 #pragma unroll
         for (int j = 0; j < P; ++j) acc[j] = fma(xk, zr[j], acc[j]);
       }
@@ -398,6 +398,7 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   extern __shared__ __attribute__((aligned(16))) unsigned char jac_smem[];
   constexpr int P = 2 * BW;  // panel columns
   constexpr int NP2 = P / 2;
+  constexpr int ZP = P + 1;  // row stride of Z: a column of Z spreads over the LDS banks
   const Rec& rec = recs[blockIdx.y];
   int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
   const int Np = a.Np;
@@ -413,8 +414,8 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
   const int LDP = Np + 16 / (int)sizeof(T);  // padded column stride, keeps 16-byte alignment
   T* pb = reinterpret_cast<T*>(jac_smem);   // panel: column c at pb + c*LDP
   T* G = pb + (size_t)P * LDP;               // G[i*P + j]
-  T* Z = G + P * P;                          // Z(i, j) at Z[i*P + j] (row-major)
-  T* rc = Z + P * P;                         // rotation c, s per pair of a step
+  T* Z = G + P * P;                          // Z(i, j) at Z[i*ZP + j] (row-major)
+  T* rc = Z + P * ZP;                        // rotation c, s per pair of a step
   T* rsn = rc + NP2;
   __shared__ int pp[P / 2], qq[P / 2];
   __shared__ int wg_rot, pass_rot, any_rot, any_off;
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
     __syncthreads();
     for (int e = t; e < P * P; e += JAC_NT) {
       const int i = e / P, j = e % P;
-      Z[e] = (i == j) ? T(1) : T(0);
+      Z[i * ZP + j] = (i == j) ? T(1) : T(0);
       // pairs this visit may rotate: every pair in round 0 / single panel, cross pairs otherwise
       if (i < j && (single || round == 0 || (i < BW && j >= BW))) {
         const T gij = G[e];
@@ -505,19 +506,19 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
         if (sa == T(0)) continue;
         const T ca = rc[ia];
         const int pa = pp[ia], qa = qq[ia];
-        const T zp = Z[i * P + pa], zq = Z[i * P + qa];
-        Z[i * P + pa] = ca * zp - sa * zq;
-        Z[i * P + qa] = sa * zp + ca * zq;
+        const T zp = Z[i * ZP + pa], zq = Z[i * ZP + qa];
+        Z[i * ZP + pa] = ca * zp - sa * zq;
+        Z[i * ZP + qa] = sa * zp + ca * zq;
       }
       __syncthreads();
     }
     const int nrot = pass_rot;
     if (nrot > 0) {
       // ---- 3. C <- C Z in LDS, then V_panel <- V_panel Z in global memory
-      jac_apply<T, P>(
+      jac_apply<T, P, ZP>(
           Np, Z, t, [&](int row, int k) { return pb[(size_t)k * LDP + row]; },
           [&](int row, int j, T v) { pb[(size_t)j * LDP + row] = v; });
-      jac_apply<T, P>(
+      jac_apply<T, P, ZP>(
           Np, Z, t, [&](int row, int k) { return Vm[row + (int64_t)gcol(k) * Np]; },
           [&](int row, int j, T v) { Vm[row + (int64_t)gcol(j) * Np] = v; });
       if (t == 0) { wg_rot += nrot; any_rot = 1; }
@@ -563,8 +564,9 @@ __global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restric
                                                             int round) {
   extern __shared__ __attribute__((aligned(16))) unsigned char jg_smem[];
   constexpr int P = JG_P, BW = JG_BW, NP2 = P / 2;
+  constexpr int ZP = P + 1;  // row stride of Z
   double* G = reinterpret_cast<double*>(jg_smem);  // G[i*P + j]
-  double* Z = G + P * P;                           // Z[i*P + j]; also Gram scratch
+  double* Z = G + P * P;                           // Z[i*ZP + j]; also Gram scratch (P x P)
   __shared__ double rc[NP2], rsn[NP2];
   __shared__ int pp[NP2], qq[NP2];
   __shared__ int pass_rot, any_off;
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restric
     __syncthreads();
     for (int e = t; e < P * P; e += JG_NT) {
       const int i = e / P, j = e % P;
-      Z[e] = (i == j) ? 1.0 : 0.0;
+      Z[i * ZP + j] = (i == j) ? 1.0 : 0.0;
       if (i < j && (round == 0 || (i < BW && j >= BW))) {
         const double gij = G[e];
         if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
@@ -674,9 +676,9 @@ __global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restric
         if (sa == 0.0) continue;
         const double ca = rc[ia];
         const int pa = pp[ia], qa = qq[ia];
-        const double zp = Z[i * P + pa], zq = Z[i * P + qa];
-        Z[i * P + pa] = ca * zp - sa * zq;
-        Z[i * P + qa] = sa * zp + ca * zq;
+        const double zp = Z[i * ZP + pa], zq = Z[i * ZP + qa];
+        Z[i * ZP + pa] = ca * zp - sa * zq;
+        Z[i * ZP + qa] = sa * zp + ca * zq;
       }
       __syncthreads();
     }
@@ -695,7 +697,7 @@ __global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restric
             const double xb = X[row + (int64_t)gcol(k0 + l / 16) * Np];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-              const double za = Z[(k0 + l / 16) * P + c * 16 + (l % 16)];
+              const double za = Z[(k0 + l / 16) * ZP + c * 16 + (l % 16)];
               acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb, acc[c], 0, 0, 0);
             }
           }
@@ -732,8 +734,9 @@ __device__ __forceinline__ void js_pair(bool full, int st, int ia, int* p, int* 
 __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
                                                             int round) {
   constexpr int P = JS_P, BW = JS_BW, NR = P / 2, NW = JS_NT / 64;
+  constexpr int ZS = P + 1;  // row stride of Z: a column of Z spreads over the LDS banks
   __shared__ __attribute__((aligned(16))) double G[P * P];
-  __shared__ __attribute__((aligned(16))) double red[NW * 3 * 256];  // Gram partials; Z (P x P) reuses it
+  __shared__ __attribute__((aligned(16))) double red[NW * 3 * 256];  // Gram partials; Z (P x ZS) reuses it
   __shared__ double rc[NR], rsn[NR];
   __shared__ int pass_rot, any_off;
   double* Z = red;
@@ -755,16 +758,20 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
     const double* ca = Bm + (int64_t)(I * BW + (l & 15)) * Np + r0;
     const double* cb = Bm + (int64_t)(J * BW + (l & 15)) * Np + r0;
     jac_d4 g00 = {0.0, 0.0, 0.0, 0.0}, g01 = g00, g11 = g00;
-    jac_d4 xa = g00, xb = g00, ya = g00, yb = g00;
+    jac_d4 xa = g00, xb = g00, ya = g00, yb = g00, za = g00, zb = g00;  // two 16-row steps ahead
     int st = w;
     if (st < Ns) {
       xa = *reinterpret_cast<const jac_d4*>(ca + 16 * st);
       xb = *reinterpret_cast<const jac_d4*>(cb + 16 * st);
     }
+    if (st + NW < Ns) {
+      ya = *reinterpret_cast<const jac_d4*>(ca + 16 * (st + NW));
+      yb = *reinterpret_cast<const jac_d4*>(cb + 16 * (st + NW));
+    }
     for (; st < Ns; st += NW) {
-      if (st + NW < Ns) {
-        ya = *reinterpret_cast<const jac_d4*>(ca + 16 * (st + NW));
-        yb = *reinterpret_cast<const jac_d4*>(cb + 16 * (st + NW));
+      if (st + 2 * NW < Ns) {
+        za = *reinterpret_cast<const jac_d4*>(ca + 16 * (st + 2 * NW));
+        zb = *reinterpret_cast<const jac_d4*>(cb + 16 * (st + 2 * NW));
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -774,6 +781,8 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
       }
       xa = ya;
       xb = yb;
+      ya = za;
+      yb = zb;
     }
     double* rw = red + w * 768;
 #pragma unroll
@@ -796,7 +805,7 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
   __syncthreads();
   for (int e = t; e < P * P; e += JS_NT) {
     const int i = e >> 5, j = e & 31;
-    Z[e] = (i == j) ? 1.0 : 0.0;
+    Z[i * ZS + j] = (i == j) ? 1.0 : 0.0;
     if (i < j && (full || (i < BW && j >= BW))) {
       const double gij = G[e];
       if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
@@ -829,34 +838,48 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
       }
       nrot += __popcll(__ballot(rot));
       wave_sync();
+      // lane l: 2x2 blocks (pair l/16 + 4k, pair l%16) of G, k < 4, and rows
+      // l/16 + 4k, k < 8, of Z in the columns of pair l%16.  All operands are
+      // read before any result is written (the blocks and Z entries of one
+      // step are disjoint), so the reads overlap; a pair with s = 0 is an
+      // exact identity and needs no test.
+      int pg[4], qg[4], pb, qb;
+      double cg[4], sg[4], g[4][4], zv[8][2];
+      const int ib = l & 15;
+      js_pair(full, st, ib, &pb, &qb);
+      const double cb = rc[ib], sb = rsn[ib];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int ia = (l >> 4) + 4 * k, ib = l & 15;
-        const double sa = rsn[ia], sb = rsn[ib];
-        if (sa == 0.0 && sb == 0.0) continue;
-        const double ca = rc[ia], cb = rc[ib];
-        int pa, qa, pb, qb;
-        js_pair(full, st, ia, &pa, &qa);
-        js_pair(full, st, ib, &pb, &qb);
-        const double g00 = G[pa * P + pb], g01 = G[pa * P + qb], g10 = G[qa * P + pb], g11 = G[qa * P + qb];
-        const double r00 = cb * g00 - sb * g01, r01 = sb * g00 + cb * g01;
-        const double r10 = cb * g10 - sb * g11, r11 = sb * g10 + cb * g11;
-        G[pa * P + pb] = ca * r00 - sa * r10;
-        G[qa * P + pb] = sa * r00 + ca * r10;
-        G[pa * P + qb] = ca * r01 - sa * r11;
-        G[qa * P + qb] = sa * r01 + ca * r11;
+        const int ia = (l >> 4) + 4 * k;
+        js_pair(full, st, ia, &pg[k], &qg[k]);
+        cg[k] = rc[ia];
+        sg[k] = rsn[ia];
+        g[k][0] = G[pg[k] * P + pb];
+        g[k][1] = G[pg[k] * P + qb];
+        g[k][2] = G[qg[k] * P + pb];
+        g[k][3] = G[qg[k] * P + qb];
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int ia = (l >> 5) + 2 * k, i = l & 31;
-        const double sa = rsn[ia];
-        if (sa == 0.0) continue;
-        const double ca = rc[ia];
-        int pa, qa;
-        js_pair(full, st, ia, &pa, &qa);
-        const double zp = Z[i * P + pa], zq = Z[i * P + qa];
-        Z[i * P + pa] = ca * zp - sa * zq;
-        Z[i * P + qa] = sa * zp + ca * zq;
+        const int iz = (l >> 4) + 4 * k;
+        zv[k][0] = Z[iz * ZS + pb];
+        zv[k][1] = Z[iz * ZS + qb];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double ca = cg[k], sa = sg[k];
+        const double r00 = cb * g[k][0] - sb * g[k][1], r01 = sb * g[k][0] + cb * g[k][1];
+        const double r10 = cb * g[k][2] - sb * g[k][3], r11 = sb * g[k][2] + cb * g[k][3];
+        G[pg[k] * P + pb] = ca * r00 - sa * r10;
+        G[qg[k] * P + pb] = sa * r00 + ca * r10;
+        G[pg[k] * P + qb] = ca * r01 - sa * r11;
+        G[qg[k] * P + qb] = sa * r01 + ca * r11;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int iz = (l >> 4) + 4 * k;
+        Z[iz * ZS + pb] = cb * zv[k][0] - sb * zv[k][1];
+        Z[iz * ZS + qb] = sb * zv[k][0] + cb * zv[k][1];
       }
       wave_sync();
     }
@@ -870,8 +893,8 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
   double za[2][8];
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) {
-    za[0][kk] = Z[(4 * kk + (l >> 4)) * P + (l & 15)];
-    za[1][kk] = Z[(4 * kk + (l >> 4)) * P + 16 + (l & 15)];
+    za[0][kk] = Z[(4 * kk + (l >> 4)) * ZS + (l & 15)];
+    za[1][kk] = Z[(4 * kk + (l >> 4)) * ZS + 16 + (l & 15)];
   }
   int co[8], oo[8];  // source column offsets (k = 4 kk + l/16), destination (16 c + l/16 + 4 v)
 #pragma unroll
@@ -882,20 +905,17 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
     oo[kk] = (c < BW ? I * BW + c : J * BW + c - BW) * Np;
   }
   const int njobs = 2 * Ns;  // (matrix, 16-row block)
-  double xb[8], yb[8];
+  double xb[8], yb[8], zb[8];  // the job's panel rows and the next two jobs'
+  auto fetch = [&](int jb, double* x) {
+    const double* src = (jb < Ns ? Bm : Vm) + (jb < Ns ? jb : jb - Ns) * 16 + (l & 15);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) x[kk] = src[co[kk]];
+  };
   int job = w;
-  if (job < njobs) {
-    const double* src = (job < Ns ? Bm : Vm) + (job < Ns ? job : job - Ns) * 16 + (l & 15);
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) xb[kk] = src[co[kk]];
-  }
+  if (job < njobs) fetch(job, xb);
+  if (job + NW < njobs) fetch(job + NW, yb);
   for (; job < njobs; job += NW) {
-    const int nx = job + NW;
-    if (nx < njobs) {
-      const double* src = (nx < Ns ? Bm : Vm) + (nx < Ns ? nx : nx - Ns) * 16 + (l & 15);
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) yb[kk] = src[co[kk]];
-    }
+    if (job + 2 * NW < njobs) fetch(job + 2 * NW, zb);
     jac_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
@@ -909,7 +929,10 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
       dst[oo[4 + v]] = acc1[v];
     }
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) xb[kk] = yb[kk];
+    for (int kk = 0; kk < 8; ++kk) {
+      xb[kk] = yb[kk];
+      yb[kk] = zb[kk];
+    }
   }
   if (t == 0) atomicAdd(&cnt[sweep], nrot);
 }
@@ -927,7 +950,7 @@ int jacobi_block_fits(int N, int elem_bytes, int cfg) {
   const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
   const size_t P = 2 * (size_t)bw;
   const size_t ldp = (size_t)Np + 16 / elem_bytes;
-  if ((size_t)Np * P * elem_bytes <= (size_t)JAC_LDS_BYTES && (ldp * P + 2 * P * P + P) * elem_bytes <= (size_t)JAC_LDS_MAX)
+  if ((size_t)Np * P * elem_bytes <= (size_t)JAC_LDS_BYTES && (ldp * P + 2 * P * P + 2 * P) * elem_bytes <= (size_t)JAC_LDS_MAX)
     return Np;
   return 0;
 }
@@ -941,7 +964,7 @@ int jacobi_pick_block(int N, int elem_bytes, int* Np_out) {
     const size_t P = 2 * (size_t)bw;
     const size_t ldp = (size_t)Np + 16 / elem_bytes;
     if ((size_t)Np * P * elem_bytes <= (size_t)JAC_LDS_BYTES &&
-        (ldp * P + 2 * P * P + P) * elem_bytes <= (size_t)JAC_LDS_MAX) {
+        (ldp * P + 2 * P * P + 2 * P) * elem_bytes <= (size_t)JAC_LDS_MAX) {
       *Np_out = Np;
       return bw;
     }
@@ -954,7 +977,7 @@ static hipError_t jac_launch(const Rec* recs, int nrec, const JacArgs& a, int sw
                              hipStream_t s) {
   constexpr int P = 2 * BW;
   const int nb = a.Np / BW;
-  const size_t lds = ((size_t)(a.Np + 16 / sizeof(T)) * P + 2 * P * P + P) * sizeof(T);
+  const size_t lds = ((size_t)(a.Np + 16 / sizeof(T)) * P + 2 * P * P + 2 * P) * sizeof(T);
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)jacobi_kernel<T, BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -975,7 +998,7 @@ hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, 
       return hipGetLastError();
     }
     static bool attr = false;
-    const size_t lds = 2 * 64 * 64 * sizeof(double);
+    const size_t lds = (64 * 64 + 64 * 65) * sizeof(double);
     if (!attr) {
       (void)hipFuncSetAttribute((const void*)jacobi_g_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       attr = true;
