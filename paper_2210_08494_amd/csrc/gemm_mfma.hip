@@ -24,17 +24,6 @@ template <typename T> __device__ __forceinline__ float to_f(T x);
 template <> __device__ __forceinline__ float to_f<float>(float x) { return x; }
 template <> __device__ __forceinline__ float to_f<bf16>(bf16 x) { return __bfloat162float(x); }
 
-__device__ __forceinline__ __bf16 rne_bf16(float x) {
-  // round to nearest even (NaN stays NaN)
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return __builtin_bit_cast(__bf16, (uint16_t)((u >> 16) | 0x40));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
-}
-__device__ __forceinline__ float bf_to_f(__bf16 h) {
-  return __uint_as_float(((uint32_t)__builtin_bit_cast(uint16_t, h)) << 16);
-}
-
 constexpr int MBM = 128, MBN = 128, MBK = 32, MNT = 256;
 constexpr int MLD = MBK + 8;  // padded LDS row (bf16 elements)
 
@@ -141,17 +130,17 @@ __device__ __forceinline__ void store_frag(const Frag& f, bool kc, int t, __bf16
   int rb, kb;
   frag_pos(kc, t, &rb, &kb);
   typedef __attribute__((__vector_size__(8))) __bf16 v4b;
+  typedef __attribute__((__vector_size__(16))) float v4f;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    v4b h, l2;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const __bf16 x = rne_bf16(f.v[r][c]);
-      h[c] = x;
-      if (LO) l2[c] = rne_bf16(f.v[r][c] - bf_to_f(x));
-    }
+    // hardware conversion (round to nearest even), two values per instruction
+    const v4f x = {f.v[r][0], f.v[r][1], f.v[r][2], f.v[r][3]};
+    const v4b h = __builtin_convertvector(x, v4b);
     *reinterpret_cast<v4b*>(&hi[(4 * rb + r) * MLD + 4 * kb]) = h;
-    if (LO) *reinterpret_cast<v4b*>(&lo[(4 * rb + r) * MLD + 4 * kb]) = l2;
+    if (LO) {
+      const v4f hb = __builtin_convertvector(h, v4f);
+      *reinterpret_cast<v4b*>(&lo[(4 * rb + r) * MLD + 4 * kb]) = __builtin_convertvector(x - hb, v4b);
+    }
   }
 }
 

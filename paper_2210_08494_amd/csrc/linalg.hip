@@ -26,6 +26,14 @@ template <> __device__ __forceinline__ float dev_rsqrt<float>(float x) {
   return y * (1.5f - 0.5f * x * y * y);
 }
 
+// Orders the LDS accesses of one wave (performed in program order) without a
+// workgroup barrier: keeps the compiler from moving them across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <typename T> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 template <> struct Eps<float> { static constexpr float v = 1.1920929e-07f; };
@@ -152,10 +160,251 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
   }
 }
 
+
+// Blocked form of the same factorisation and inverse (n <= 256), in 32-wide
+// blocks with the block row of R staged in LDS.  Per block column: one wave
+// factors the diagonal block; the block row right of it is solved column by
+// column (R_JJ^T Y = R_J,rest); the trailing upper triangle takes the rank-32
+// update in 4 x 4 register blocks.  The inverse runs over block rows
+// bottom-up: X_JJ = R_JJ^{-1}, X_J,rest = -X_JJ (R_J,rest X_rest,rest).  The
+// pivot rule, the shift and the zero rows are those of the column kernel;
+// only the order of the sums differs.
+constexpr int CB = 32, CHB_NT = 512, CHB_MAXN = 256;
+
+template <typename T>
+__global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restrict__ recs, CholArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char chb_smem[];
+  const Rec& rec = recs[blockIdx.x];
+  const int n = a.n;
+  const int LDW = ((n + 3) / 4) * 4 + 4;  // row stride of the staged block rows
+  T* Pn = reinterpret_cast<T*>(chb_smem);  // CB x LDW: block row of R
+  T* Tb = Pn + CB * LDW;                   // CB x LDW: R_J,rest X_rest,rest
+  __shared__ T Dg[CB][CB + 1], Di[CB][CB + 1];
+  __shared__ T red[CHB_NT / 64], redt[CHB_NT / 64];
+  __shared__ int okrow[CB];
+  __shared__ int deficient, nonfinite;
+  const T* Wg = at<const T>(rec, WS, a.off_gram);
+  T* R = at<T>(rec, WS, a.off_R);
+  T* X = at<T>(rec, WS, a.off_Rinv);
+  const int t = threadIdx.x;
+  if (t == 0) { deficient = 0; nonfinite = 0; }
+  __syncthreads();
+  T mx = T(0), tr = T(0);
+  for (int i = t; i < n; i += CHB_NT) {
+    const T v = Wg[i + (int64_t)i * n];
+    if (!(v - v == T(0))) nonfinite = 1;
+    mx = v > mx ? v : mx;
+    tr += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+    tr += __shfl_xor(tr, off);
+  }
+  if ((t & 63) == 0) { red[t >> 6] = mx; redt[t >> 6] = tr; }
+  for (int64_t e = t; e < (int64_t)n * n; e += CHB_NT) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    R[e] = (i <= j) ? Wg[e] : T(0);
+    X[e] = T(0);
+  }
+  __syncthreads();
+  if (t == 0) {
+    T m = red[0], tt = redt[0];
+    for (int w = 1; w < CHB_NT / 64; ++w) { m = red[w] > m ? red[w] : m; tt += redt[w]; }
+    red[0] = m;
+    redt[0] = tt;
+  }
+  __syncthreads();
+  const T dmax = red[0];
+  const T tau = T(a.tau_rel) * dmax;
+  if (a.shift_rel > 0.0) {
+    const T sh = T(a.shift_rel) * redt[0];
+    for (int i = t; i < n; i += CHB_NT) R[i + (int64_t)i * n] += sh;
+    __syncthreads();
+  }
+
+  // ---- factorisation, block column by block column
+  for (int kb = 0; kb < n; kb += CB) {
+    const int nbk = min(CB, n - kb), c0 = kb + nbk, m = n - c0;
+    for (int e = t; e < CB * CB; e += CHB_NT) {
+      const int i = e % CB, j = e / CB;
+      Dg[i][j] = (i <= j && j < nbk) ? R[(kb + i) + (int64_t)(kb + j) * n] : T(0);
+    }
+    const int mq = ((m + 3) / 4) * 4;  // columns read by the 4-wide blocks (zero beyond m)
+    for (int e = t; e < CB * mq; e += CHB_NT) {
+      const int i = e % CB, c = e / CB;
+      Pn[i * LDW + c] = (i < nbk && c < m) ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
+    }
+    __syncthreads();
+    if (t < 64) {  // diagonal block, one wave
+      for (int j = 0; j < nbk; ++j) {
+        const T p = Dg[j][j];
+        const bool ok = p > tau && dmax > T(0);
+        const T sp = ok ? dev_sqrt(p) : T(0);
+        const T inv = ok ? T(1) / sp : T(0);
+        wave_sync();
+        if (t >= j && t < nbk) Dg[j][t] = (t == j) ? sp : Dg[j][t] * inv;
+        if (t == 0) {
+          okrow[j] = ok;
+          if (!ok) deficient = 1;
+        }
+        wave_sync();
+        const int mm = nbk - j - 1;
+        if (ok)
+          for (int e = t; e < mm * mm; e += 64) {
+            const int ii = e % mm, kk = e / mm;
+            if (ii <= kk) Dg[j + 1 + ii][j + 1 + kk] -= Dg[j][j + 1 + ii] * Dg[j][j + 1 + kk];
+          }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < nbk * nbk; e += CHB_NT) {
+      const int i = e % nbk, j = e / nbk;
+      if (i <= j) R[(kb + i) + (int64_t)(kb + j) * n] = Dg[i][j];
+    }
+    // block row: for each column, forward substitution with Dg^T
+    for (int c = t; c < m; c += CHB_NT) {
+      T y[CB];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) y[i] = Pn[i * LDW + c];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        if (j < nbk) {
+          T sum = y[j];
+#pragma unroll
+          for (int i = 0; i < j; ++i) sum -= Dg[i][j] * y[i];
+          y[j] = okrow[j] ? sum * (T(1) / Dg[j][j]) : T(0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+        if (i < nbk) {
+          Pn[i * LDW + c] = y[i];
+          R[(kb + i) + (int64_t)(c0 + c) * n] = y[i];
+        }
+    }
+    __syncthreads();
+    // trailing upper triangle, 4 x 4 blocks (bi <= bk) in column-major triangular order
+    const int nq = mq / 4;
+    const int nblk = nq * (nq + 1) / 2;
+    for (int b = t; b < nblk; b += CHB_NT) {
+      int bk = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+      while ((bk + 1) * (bk + 2) / 2 <= b) ++bk;
+      while (bk * (bk + 1) / 2 > b) --bk;
+      const int bi = b - bk * (bk + 1) / 2;
+      T acc[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = T(0);
+      for (int j = 0; j < nbk; ++j) {
+        const T* pr = Pn + j * LDW;
+        T x[4], z[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[q] = pr[4 * bi + q];
+          z[q] = pr[4 * bk + q];
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], z[q], acc[p][q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 4 * bk + q;
+        if (k >= m) continue;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int i = 4 * bi + p;
+          if (i <= k) R[(c0 + i) + (int64_t)(c0 + k) * n] -= acc[p][q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- inverse, block rows bottom-up
+  for (int kb = ((n - 1) / CB) * CB; kb >= 0; kb -= CB) {
+    const int nbk = min(CB, n - kb), c0 = kb + nbk, m = n - c0;
+    for (int e = t; e < CB * CB; e += CHB_NT) {
+      const int i = e % CB, j = e / CB;
+      Dg[i][j] = (i <= j && j < nbk) ? R[(kb + i) + (int64_t)(kb + j) * n] : T(0);
+      Di[i][j] = T(0);
+    }
+    for (int e = t; e < CB * m; e += CHB_NT) {
+      const int i = e % CB, c = e / CB;
+      Pn[i * LDW + c] = i < nbk ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
+    }
+    __syncthreads();
+    if (t < 64) {  // Di = Dg^{-1}: rows bottom-up, lane j owns column j
+      for (int i = nbk - 1; i >= 0; --i) {
+        const T rii = Dg[i][i];
+        const T dinv = rii > T(0) ? T(1) / rii : T(0);
+        const int j = t;
+        if (j < nbk && j >= i) {
+          T sum = T(0);
+          for (int k = i + 1; k <= j; ++k) sum += Dg[i][k] * Di[k][j];
+          Di[i][j] = (j == i) ? dinv : -sum * dinv;
+        }
+        wave_sync();
+      }
+    }
+    // T = R_J,rest X_rest,rest: item (column c, half h) sums 16 rows over k <= c
+    const int c = t >> 1, h = t & 1;
+    T acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = T(0);
+    if (c < m) {
+      const T* xc = X + c0 + (int64_t)(c0 + c) * n;
+      for (int k = 0; k <= c; ++k) {
+        const T xk = xc[k];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = fma(Pn[(16 * h + r) * LDW + k], xk, acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Tb[(16 * h + r) * LDW + c] = acc[r];
+    }
+    __syncthreads();
+    for (int e = t; e < nbk * nbk; e += CHB_NT) {
+      const int i = e % nbk, j = e / nbk;
+      if (i <= j) X[(kb + i) + (int64_t)(kb + j) * n] = Di[i][j];
+    }
+    if (c < m) {  // X_J,c = -Di T_c, rows 16 h .. 16 h + 15
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 16 * h + r;
+        if (i >= nbk) continue;
+        T sum = T(0);
+        for (int s2 = i; s2 < nbk; ++s2) sum = fma(Di[i][s2], Tb[s2 * LDW + c], sum);
+        X[(kb + i) + (int64_t)(c0 + c) * n] = -sum;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    uint32_t ev = (deficient ? KFB_EV_CHOL_DEFICIENT : 0u) | (nonfinite ? KFB_EV_NONFINITE : 0u);
+    if (ev) atomicOr(at<uint32_t>(rec, STATUS, 0), ev);
+  }
+}
+
 template <typename T>
 hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s) {
   if (a.n <= 0 || nrec <= 0) return hipSuccess;
   if (a.n > CHOL_MAXN) return hipErrorInvalidValue;
+  if (a.n <= CHB_MAXN) {
+    const int ldw = ((a.n + 3) / 4) * 4 + 4;
+    const size_t lds = 2 * (size_t)CB * ldw * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)chol_blocked_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(2 * CB * (CHB_MAXN + 4) * sizeof(T)));
+      attr = true;
+    }
+    hipLaunchKernelGGL((chol_blocked_kernel<T>), dim3(nrec), dim3(CHB_NT), lds, s, recs, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((chol_inv_kernel<T>), dim3(nrec), dim3(CHOL_NT), 0, s, recs, a);
   return hipGetLastError();
 }
@@ -720,11 +969,6 @@ __global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restric
 // operands in registers and prefetch the next 16-row block of the panel.
 constexpr int JS_NT = 256, JS_P = 32, JS_BW = 16;
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  asm volatile("" ::: "memory");
-}
 
 __device__ __forceinline__ void js_pair(bool full, int st, int ia, int* p, int* q) {
   if (full) tour_pair(JS_P, st, ia, p, q);
