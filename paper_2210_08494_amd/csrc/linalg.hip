@@ -181,6 +181,7 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
   T* Tb = Pn + CB * LDW;                   // CB x LDW: R_J,rest X_rest,rest
   __shared__ T Dg[CB][CB + 1], Di[CB][CB + 1];
   __shared__ T red[CHB_NT / 64], redt[CHB_NT / 64];
+  __shared__ T rowb[CB], invrow[CB], pvt[2];
   __shared__ int okrow[CB];
   __shared__ int deficient, nonfinite;
   const T* Wg = at<const T>(rec, WS, a.off_gram);
@@ -202,10 +203,21 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
     tr += __shfl_xor(tr, off);
   }
   if ((t & 63) == 0) { red[t >> 6] = mx; redt[t >> 6] = tr; }
-  for (int64_t e = t; e < (int64_t)n * n; e += CHB_NT) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    R[e] = (i <= j) ? Wg[e] : T(0);
-    X[e] = T(0);
+  {  // R = upper triangle of W, X = 0; eight consecutive elements per thread, loads first
+    const int nn = n * n;
+    for (int e0 = 8 * t; e0 < nn; e0 += 8 * CHB_NT) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = e0 + q < nn ? Wg[e0 + q] : T(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q;
+        if (e < nn) {
+          R[e] = (e % n) <= (e / n) ? v[q] : T(0);
+          X[e] = T(0);
+        }
+      }
+    }
   }
   __syncthreads();
   if (t == 0) {
@@ -231,32 +243,46 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
       Dg[i][j] = (i <= j && j < nbk) ? R[(kb + i) + (int64_t)(kb + j) * n] : T(0);
     }
     const int mq = ((m + 3) / 4) * 4;  // columns read by the 4-wide blocks (zero beyond m)
+#pragma unroll 4
     for (int e = t; e < CB * mq; e += CHB_NT) {
       const int i = e % CB, c = e / CB;
       Pn[i * LDW + c] = (i < nbk && c < m) ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
     }
     __syncthreads();
-    if (t < 64) {  // diagonal block, one wave
-      for (int j = 0; j < nbk; ++j) {
-        const T p = Dg[j][j];
-        const bool ok = p > tau && dmax > T(0);
-        const T sp = ok ? dev_sqrt(p) : T(0);
-        const T inv = ok ? T(1) / sp : T(0);
-        wave_sync();
-        if (t >= j && t < nbk) Dg[j][t] = (t == j) ? sp : Dg[j][t] * inv;
-        if (t == 0) {
-          okrow[j] = ok;
-          if (!ok) deficient = 1;
-        }
-        wave_sync();
-        const int mm = nbk - j - 1;
-        if (ok)
-          for (int e = t; e < mm * mm; e += 64) {
-            const int ii = e % mm, kk = e / mm;
-            if (ii <= kk) Dg[j + 1 + ii][j + 1 + kk] -= Dg[j][j + 1 + ii] * Dg[j][j + 1 + kk];
+    if (t < CB) {  // diagonal block in registers: lane k holds column k; row j shared through LDS
+      const int k = t;
+      T d[CB];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) d[i] = Dg[i][k];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        if (j < nbk) {
+          if (k == j) {
+            const T p = d[j];
+            const bool ok = p > tau && dmax > T(0);
+            const T sp = ok ? dev_sqrt(p) : T(0);
+            pvt[0] = sp;
+            pvt[1] = ok ? T(1) / sp : T(0);
+            okrow[j] = ok;
+            invrow[j] = pvt[1];
+            if (!ok) deficient = 1;
           }
-        wave_sync();
+          wave_sync();
+          const T sp = pvt[0], inv = pvt[1];
+          const bool ok = okrow[j];
+          if (k >= j) d[j] = (k == j) ? sp : d[j] * inv;  // row j of R
+          rowb[k] = d[j];
+          wave_sync();
+#pragma unroll
+          for (int i = j + 1; i < CB; ++i) {
+            const T rji = rowb[i];  // R[j][i]
+            if (ok && i < nbk && k >= i) d[i] -= rji * d[j];
+          }
+          wave_sync();
+        }
       }
+#pragma unroll
+      for (int i = 0; i < CB; ++i) Dg[i][k] = d[i];
     }
     __syncthreads();
     for (int e = t; e < nbk * nbk; e += CHB_NT) {
@@ -271,10 +297,13 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         if (j < nbk) {
-          T sum = y[j];
+          T s0 = y[j], s1 = T(0);  // two partial sums shorten the dependent chain
 #pragma unroll
-          for (int i = 0; i < j; ++i) sum -= Dg[i][j] * y[i];
-          y[j] = okrow[j] ? sum * (T(1) / Dg[j][j]) : T(0);
+          for (int i = 0; i < j; ++i) {
+            if (i & 1) s1 = fma(Dg[i][j], y[i], s1);
+            else s0 = fma(-Dg[i][j], y[i], s0);
+          }
+          y[j] = okrow[j] ? (s0 - s1) * invrow[j] : T(0);
         }
       }
 #pragma unroll
@@ -333,35 +362,61 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
       Dg[i][j] = (i <= j && j < nbk) ? R[(kb + i) + (int64_t)(kb + j) * n] : T(0);
       Di[i][j] = T(0);
     }
-    for (int e = t; e < CB * m; e += CHB_NT) {
+    const int m8 = ((m + 7) / 8) * 8;  // columns read by the 8-wide chunks (zero beyond m)
+#pragma unroll 4
+    for (int e = t; e < CB * m8; e += CHB_NT) {
       const int i = e % CB, c = e / CB;
-      Pn[i * LDW + c] = i < nbk ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
+      Pn[i * LDW + c] = (i < nbk && c < m) ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
     }
     __syncthreads();
-    if (t < 64) {  // Di = Dg^{-1}: rows bottom-up, lane j owns column j
-      for (int i = nbk - 1; i >= 0; --i) {
-        const T rii = Dg[i][i];
-        const T dinv = rii > T(0) ? T(1) / rii : T(0);
-        const int j = t;
-        if (j < nbk && j >= i) {
-          T sum = T(0);
-          for (int k = i + 1; k <= j; ++k) sum += Dg[i][k] * Di[k][j];
-          Di[i][j] = (j == i) ? dinv : -sum * dinv;
-        }
-        wave_sync();
+    if (t < CB) {  // Di = Dg^{-1} in registers: rows bottom-up, lane j holds column j
+      const int j = t;
+      {
+        const T rjj = Dg[j][j];
+        invrow[j] = (j < nbk && rjj > T(0)) ? T(1) / rjj : T(0);
       }
+      wave_sync();
+      T x[CB];
+#pragma unroll
+      for (int i = CB - 1; i >= 0; --i) {
+        x[i] = T(0);
+        if (i < nbk) {
+          const T dinv = invrow[i];
+          T s0 = T(0), s1 = T(0);
+#pragma unroll
+          for (int k = i + 1; k < CB; ++k)
+            if (k <= j && k < nbk) {
+              if (k & 1) s1 = fma(Dg[i][k], x[k], s1);
+              else s0 = fma(Dg[i][k], x[k], s0);
+            }
+          x[i] = (j == i) ? dinv : (j > i ? -(s0 + s1) * dinv : T(0));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CB; ++i) Di[i][j] = j < nbk ? x[i] : T(0);
     }
-    // T = R_J,rest X_rest,rest: item (column c, half h) sums 16 rows over k <= c
-    const int c = t >> 1, h = t & 1;
+    // T = R_J,rest X_rest,rest: item (column c, half h) sums 16 rows over k <= c;
+    // columns interleave over the waves so each wave gets short and long ones
+    const int c = 8 * ((t & 63) >> 1) + (t >> 6), h = t & 1;
     T acc[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = T(0);
     if (c < m) {
+      // column c of X below the block row, 8 rows per chunk, the next chunk in flight
       const T* xc = X + c0 + (int64_t)(c0 + c) * n;
-      for (int k = 0; k <= c; ++k) {
-        const T xk = xc[k];
+      const int kend = c + 1;
+      T xa[8], xn[8];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = fma(Pn[(16 * h + r) * LDW + k], xk, acc[r]);
+      for (int q = 0; q < 8; ++q) xa[q] = q < kend ? xc[q] : T(0);
+      for (int k0 = 0; k0 < kend; k0 += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xn[q] = (k0 + 8 + q < kend) ? xc[k0 + 8 + q] : T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] = fma(Pn[(16 * h + r) * LDW + k0 + q], xa[q], acc[r]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xa[q] = xn[q];
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) Tb[(16 * h + r) * LDW + c] = acc[r];
@@ -800,28 +855,81 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
 // Gram, panel and V times the accumulated rotation), but the panel is not
 // staged in LDS: the Gram and the products read B and V straight from global
 // memory as MFMA operands.  LDS holds only the 64 x 64 Gram and rotation
-// (64 KB), so two workgroups share a CU and hide each other's latency, and
-// the wider panel halves the number of visits per sweep relative to 32
-// columns.  For the Gram, each lane feeds four consecutive rows of its column
-// to four MFMA steps (the row order of a sum does not matter), so every load
-// is a full 32-byte segment.
+// (65 KB), so two workgroups share a CU, and the wider panel halves the
+// number of visits per sweep (and the panel traffic) relative to 32 columns.
+//
+// Gram: waves (row quarter q = w % 4, tile group g = w / 4) read each of
+// their column blocks once per 16-row step (each lane four consecutive rows
+// of its column, fed to four MFMA steps); group 0 holds the upper 16 x 16
+// tiles (0,0) (0,1) (0,2) (0,3) (1,1), group 1 (1,2) (1,3) (2,2) (2,3) (3,3).
+// The four row quarters are summed in a fixed order through LDS.
 // ---------------------------------------------------------------------------
 constexpr int JG_NT = 512;
 constexpr int JG_P = 64, JG_BW = 32;
+constexpr int JG_LDS = (64 * 64 + 64 * 65) * 8;  // G and Z
 
-__global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
+__device__ __forceinline__ void jg_pair(bool full, int st, int ia, int* p, int* q) {
+  // full: circle method over 64 columns (st < 63); otherwise cross pairs (st < 32)
+  if (full) {
+    if (ia == 0) { *p = st; *q = 63; }
+    else {
+      int x = st + ia, y = st - ia;
+      x -= x >= 63 ? 63 : 0;
+      y += y < 0 ? 63 : 0;
+      *p = x;
+      *q = y;
+    }
+  } else {
+    *p = ia;
+    *q = JG_BW + ((ia + st) & (JG_BW - 1));
+  }
+}
+
+// tile u of group g: (block a, block b) of 16 panel columns each
+__device__ __forceinline__ constexpr int jg_tile_a(int g, int u) { return g ? (u < 2 ? 1 : u < 4 ? 2 : 3) : (u < 4 ? 0 : 1); }
+__device__ __forceinline__ constexpr int jg_tile_b(int g, int u) {
+  return g ? (u == 0 || u == 2 ? 2 : 3) : (u < 4 ? u : 1);
+}
+
+// Partial Gram tiles of group GRP over the 16-row steps q, q + 4, ... of the
+// panel (cp[i]: this lane's rows in column block i), the next step in flight.
+template <int GRP>
+__device__ __forceinline__ void jg_gram_part(const double* const* cp, int Ns, int q, jac_d4* acc) {
+  constexpr int B0 = GRP;  // group 1 never reads column block 0
+#pragma unroll
+  for (int u = 0; u < 5; ++u) acc[u] = jac_d4{0.0, 0.0, 0.0, 0.0};
+  jac_d4 x[4], y[4];
+  int st = q;
+  if (st < Ns)
+#pragma unroll
+    for (int i = B0; i < 4; ++i) x[i] = *reinterpret_cast<const jac_d4*>(cp[i] + 16 * st);
+  for (; st < Ns; st += 4) {
+    if (st + 4 < Ns)
+#pragma unroll
+      for (int i = B0; i < 4; ++i) y[i] = *reinterpret_cast<const jac_d4*>(cp[i] + 16 * (st + 4));
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int u = 0; u < 5; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[jg_tile_a(GRP, u)][e], x[jg_tile_b(GRP, u)][e], acc[u], 0, 0, 0);
+#pragma unroll
+    for (int i = B0; i < 4; ++i) x[i] = y[i];
+  }
+}
+
+__global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
                                                             int round) {
   extern __shared__ __attribute__((aligned(16))) unsigned char jg_smem[];
   constexpr int P = JG_P, BW = JG_BW, NP2 = P / 2;
   constexpr int ZP = P + 1;  // row stride of Z
   double* G = reinterpret_cast<double*>(jg_smem);  // G[i*P + j]
-  double* Z = G + P * P;                           // Z[i*ZP + j]; also Gram scratch (P x P)
+  double* Z = G + P * P;                           // Z[i*ZP + j]
+  double* slot = G;                                // Gram partials (5 tiles x 256 per slot), before G is formed
   __shared__ double rc[NP2], rsn[NP2];
-  __shared__ int pp[NP2], qq[NP2];
   __shared__ int pass_rot, any_off;
   const Rec& rec = recs[blockIdx.y];
   int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
-  const int Np = a.Np;
+  const int Np = a.Np, Ns = Np / 16;
   const int nb = Np / BW;  // >= 4
   if (sweep > 0 && cnt[sweep - 1] == 0) return;
   double* Bm = at<double>(rec, WS, a.off_B);
@@ -831,134 +939,172 @@ __global__ __launch_bounds__(JG_NT, 2) void jacobi_g_kernel(const Rec* __restric
   auto gcol = [&](int c) { return c < BW ? I * BW + c : J * BW + (c - BW); };
   const int t = threadIdx.x, w = t / 64, l = t % 64;
   const double tol = a.tol;
-  typedef __attribute__((__vector_size__(4 * sizeof(double)))) double dv4;
+  const bool full = round == 0;
+
+  // ---- 1. Gram
   {
-    if (t == 0) pass_rot = 0;
+    const int q = w & 3, grp = w >> 2;
+    const double* cp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cp[i] = Bm + (int64_t)gcol(16 * i + (l & 15)) * Np + 4 * (l >> 4);
+    jac_d4 acc[5];
+    if (grp == 0) jg_gram_part<0>(cp, Ns, q, acc);
+    else jg_gram_part<1>(cp, Ns, q, acc);
+    // fixed-order sum over the row quarters: (q0 + q2) + (q1 + q3)
+    auto put = [&](int sl) {
+      double* d = slot + sl * 1280;
+#pragma unroll
+      for (int u = 0; u < 5; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[u * 256 + v * 64 + l] = acc[u][v];
+    };
+    auto add = [&](int sl) {
+      const double* d = slot + sl * 1280;
+#pragma unroll
+      for (int u = 0; u < 5; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += d[u * 256 + v * 64 + l];
+    };
+    if (q >= 2) put(grp * 2 + (q - 2));
     __syncthreads();
-    // ---- 1. Gram: 10 upper 16x16 tiles x 2 row halves over 8 waves
-    for (int item = w; item < 20; item += JG_NT / 64) {
-      const int tile = item % 10, kh = item / 10;
-      int ti = 0, rem = tile;
-      while (rem >= 4 - ti) { rem -= 4 - ti; ++ti; }
-      const int tj = ti + rem;
-      const double* ca = Bm + (int64_t)gcol(ti * 16 + (l % 16)) * Np + 4 * (l / 16);
-      const double* cb = Bm + (int64_t)gcol(tj * 16 + (l % 16)) * Np + 4 * (l / 16);
-      jac_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-      const int kb = kh * (Np / 2), ke = kb + Np / 2;
-      for (int k0 = kb; k0 < ke; k0 += 16) {
-        const dv4 xa = *reinterpret_cast<const dv4*>(ca + k0);
-        const dv4 xb = *reinterpret_cast<const dv4*>(cb + k0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[0], xb[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[1], xb[1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[2], xb[2], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[3], xb[3], acc1, 0, 0, 0);
-      }
-      double* dst = kh == 0 ? G : Z;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = ti * 16 + l / 16 + 4 * v, j = tj * 16 + l % 16;
-        dst[i * P + j] = acc0[v] + acc1[v];
-      }
-    }
-    if (t == 0) any_off = 0;
+    if (q < 2) add(grp * 2 + q);
     __syncthreads();
-    for (int e = t; e < P * P; e += JG_NT) {
-      const int i = e / P, j = e % P;
-      if ((i / 16) <= (j / 16)) {  // upper tiles: add the two row halves, mirror below
-        const double x = G[e] + Z[e];
-        G[e] = x;
-        if ((i / 16) < (j / 16)) G[j * P + i] = x;
-      }
-    }
+    if (q == 1) put(grp);
     __syncthreads();
-    for (int e = t; e < P * P; e += JG_NT) {
-      const int i = e / P, j = e % P;
-      Z[i * ZP + j] = (i == j) ? 1.0 : 0.0;
-      if (i < j && (round == 0 || (i < BW && j >= BW))) {
-        const double gij = G[e];
-        if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
-      }
-    }
+    if (q == 0) add(grp);
     __syncthreads();
-    // ---- 2. plane rotations on G, accumulating Z (as in the LDS-panel kernel)
-    const bool full = round == 0;
-    const int nsteps = any_off ? (full ? P - 1 : BW) : 0;
-    for (int st = 0; st < nsteps; ++st) {
-      if (t < NP2) {
-        int p, q;
-        if (full) tour_pair(P, st, t, &p, &q);
-        else { p = t; q = BW + (t + st) % BW; }
-        const double gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
-        double c = 1.0, s = 0.0;
-        if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
-          const double aa = gqq - gpp, bb = 2.0 * gpq;
-          const double ir = dev_rsqrt(aa * aa + bb * bb);
-          const double y = 0.5 * (1.0 + fabs(aa) * ir);
-          const double ry = dev_rsqrt(y);
-          c = y * ry;
-          s = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
-          atomicAdd(&pass_rot, 1);
-        }
-        rc[t] = c;
-        rsn[t] = s;
-        pp[t] = p;
-        qq[t] = q;
-      }
-      __syncthreads();
-      for (int e = t; e < NP2 * NP2; e += JG_NT) {
-        const int ia = e / NP2, ib = e % NP2;
-        const double sa = rsn[ia], sb = rsn[ib];
-        if (sa == 0.0 && sb == 0.0) continue;
-        const double ca = rc[ia], cb = rc[ib];
-        const int pa = pp[ia], qa = qq[ia], pbb = pp[ib], qb = qq[ib];
-        const double g00 = G[pa * P + pbb], g01 = G[pa * P + qb], g10 = G[qa * P + pbb], g11 = G[qa * P + qb];
-        const double r00 = cb * g00 - sb * g01, r01 = sb * g00 + cb * g01;
-        const double r10 = cb * g10 - sb * g11, r11 = sb * g10 + cb * g11;
-        G[pa * P + pbb] = ca * r00 - sa * r10;
-        G[qa * P + pbb] = sa * r00 + ca * r10;
-        G[pa * P + qb] = ca * r01 - sa * r11;
-        G[qa * P + qb] = sa * r01 + ca * r11;
-      }
-      for (int e = t; e < NP2 * P; e += JG_NT) {
-        const int ia = e / P, i = e % P;
-        const double sa = rsn[ia];
-        if (sa == 0.0) continue;
-        const double ca = rc[ia];
-        const int pa = pp[ia], qa = qq[ia];
-        const double zp = Z[i * ZP + pa], zq = Z[i * ZP + qa];
-        Z[i * ZP + pa] = ca * zp - sa * zq;
-        Z[i * ZP + qa] = sa * zp + ca * zq;
-      }
-      __syncthreads();
-    }
-    const int nrot = pass_rot;
-    if (nrot > 0) {
-      // ---- 3. X <- X Z for X = panel of B, then of V, in global memory, as (Z^T X^T)
-      for (int pass = 0; pass < 2; ++pass) {
-        double* X = pass == 0 ? Bm : Vm;
-        for (int rb = w; rb < Np / 16; rb += JG_NT / 64) {
-          jac_d4 acc[4];
+    if (q == 0) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[c] = jac_d4{0.0, 0.0, 0.0, 0.0};
-          const int row = rb * 16 + (l % 16);
-#pragma unroll 4
-          for (int k0 = 0; k0 < P; k0 += 4) {
-            const double xb = X[row + (int64_t)gcol(k0 + l / 16) * Np];
+      for (int u = 0; u < 5; ++u) {
+        const int ta = jg_tile_a(grp, u), tb = jg_tile_b(grp, u);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const double za = Z[(k0 + l / 16) * ZP + c * 16 + (l % 16)];
-              acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb, acc[c], 0, 0, 0);
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) X[row + (int64_t)gcol(c * 16 + l / 16 + 4 * v) * Np] = acc[c][v];
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ta + (l >> 4) + 4 * v, j = 16 * tb + (l & 15);
+          G[i * P + j] = acc[u][v];
+          if (ta != tb) G[j * P + i] = acc[u][v];
         }
       }
     }
-    if (t == 0 && nrot > 0) atomicAdd(&cnt[sweep], nrot);
   }
+  if (t == 0) { any_off = 0; pass_rot = 0; }
+  __syncthreads();
+  for (int e = t; e < P * P; e += JG_NT) {
+    const int i = e / P, j = e % P;
+    Z[i * ZP + j] = (i == j) ? 1.0 : 0.0;
+    if (i < j && (full || (i < BW && j >= BW))) {
+      const double gij = G[e];
+      if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. plane rotations on G, accumulating Z
+  const int nsteps = any_off ? (full ? P - 1 : BW) : 0;
+  int nrot = 0;
+  for (int st = 0; st < nsteps; ++st) {
+    if (t < NP2) {
+      int p, q;
+      jg_pair(full, st, t, &p, &q);
+      const double gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
+      double c = 1.0, sn = 0.0;
+      if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
+        const double aa = gqq - gpp, bb = 2.0 * gpq;
+        const double ir = dev_rsqrt(aa * aa + bb * bb);
+        const double yy = 0.5 * (1.0 + fabs(aa) * ir);
+        const double ry = dev_rsqrt(yy);
+        c = yy * ry;
+        sn = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
+        ++nrot;
+      }
+      rc[t] = c;
+      rsn[t] = sn;
+    }
+    __syncthreads();
+    {
+      // thread: pair ib = t % 32 (columns) with pairs t/32 and t/32 + 16 (rows) of G,
+      // and rows t/32 + 16k (k < 4) of Z in the columns of pair ib; every read first
+      const int ib = t & 31, r0 = t >> 5;
+      int pb, qb, pa[2], qa[2];
+      jg_pair(full, st, ib, &pb, &qb);
+      const double cb = rc[ib], sb = rsn[ib];
+      double ca[2], sa[2], g[2][4], zv[4][2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int ia = r0 + 16 * k;
+        jg_pair(full, st, ia, &pa[k], &qa[k]);
+        ca[k] = rc[ia];
+        sa[k] = rsn[ia];
+        g[k][0] = G[pa[k] * P + pb];
+        g[k][1] = G[pa[k] * P + qb];
+        g[k][2] = G[qa[k] * P + pb];
+        g[k][3] = G[qa[k] * P + qb];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int iz = r0 + 16 * k;
+        zv[k][0] = Z[iz * ZP + pb];
+        zv[k][1] = Z[iz * ZP + qb];
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double r00 = cb * g[k][0] - sb * g[k][1], r01 = sb * g[k][0] + cb * g[k][1];
+        const double r10 = cb * g[k][2] - sb * g[k][3], r11 = sb * g[k][2] + cb * g[k][3];
+        G[pa[k] * P + pb] = ca[k] * r00 - sa[k] * r10;
+        G[qa[k] * P + pb] = sa[k] * r00 + ca[k] * r10;
+        G[pa[k] * P + qb] = ca[k] * r01 - sa[k] * r11;
+        G[qa[k] * P + qb] = sa[k] * r01 + ca[k] * r11;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int iz = r0 + 16 * k;
+        Z[iz * ZP + pb] = cb * zv[k][0] - sb * zv[k][1];
+        Z[iz * ZP + qb] = sb * zv[k][0] + cb * zv[k][1];
+      }
+    }
+    __syncthreads();
+  }
+  if (t < 64) {  // rotations counted by the lanes that chose them (wave 0)
+    int tot = nrot;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if (t == 0) pass_rot = tot;
+  }
+  __syncthreads();
+  const int nrt = pass_rot;
+  if (nrt == 0) return;
+
+  // ---- 3. [B_I B_J] <- [B_I B_J] Z and [V_I V_J] <- [V_I V_J] Z, as (Z^T X^T) on MFMA
+  int co[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) co[kk] = gcol(4 * kk + (l >> 4)) * Np;
+  const int njobs = 2 * Ns;  // (matrix, 16-row block)
+  for (int job = w; job < njobs; job += JG_NT / 64) {
+    const int64_t rofs = (job < Ns ? job : job - Ns) * 16 + (l & 15);
+    double* X = (job < Ns ? Bm : Vm) + rofs;
+    jac_d4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = jac_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {  // k in two halves of 32 panel columns
+      double xb[8];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) xb[kk] = X[co[8 * half + kk]];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = 4 * (8 * half + kk) + (l >> 4);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double za = Z[k * ZP + 16 * c + (l & 15)];
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb[kk], acc[c], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(int64_t)gcol(16 * c + (l >> 4) + 4 * v) * Np] = acc[c][v];
+  }
+  if (t == 0) atomicAdd(&cnt[sweep], nrt);
 }
 
 // P = 32 (two 16-column blocks), four waves, several workgroups per CU.  The
@@ -1242,7 +1388,7 @@ hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, 
       return hipGetLastError();
     }
     static bool attr = false;
-    const size_t lds = (64 * 64 + 64 * 65) * sizeof(double);
+    const size_t lds = JG_LDS;
     if (!attr) {
       (void)hipFuncSetAttribute((const void*)jacobi_g_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       attr = true;
