@@ -207,7 +207,13 @@ def main():
     flops_per_call = S * 9.0 * Ncore ** 3  # textbook symmetric EVD count per core
     flops_per_launch = flops_per_call / launches_per_call
     achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
-    roofline = {"kernel": "jacobi_kernel<double,16> (block one-sided Jacobi round, FP64)",
+    cfg = kfb.tune_get_jacobi(MIX, Ncore)[0]
+    if cfg & kfb.KFB_JAC_STREAMED:
+        kname = {16: "jacobi_s_kernel", 32: "jacobi_g_kernel"}[cfg & 0xFF]
+        kdesc = f"{kname} (block one-sided Jacobi round, FP64, {2 * (cfg & 0xFF)}-column panels streamed from HBM)"
+    else:
+        kdesc = f"jacobi_kernel<double,{cfg}> (block one-sided Jacobi round, FP64, panel in LDS)"
+    roofline = {"kernel": kdesc,
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
                 "per_launch": {"algorithmic_flops": flops_per_launch, "avg_ms": avg_launch_ms,
@@ -277,7 +283,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32+fp64",
+        "dtype": "bf16+fp64",
         "data": "synthetic (seeded decaying-spectrum batches and N(0,1) gradients generated on the device)",
         "config": {"workload": f"{L}-layer stack, 2 K-factors per layer ({S} states) at d={D}, r={R}, "
                                f"n={N_BATCH}, rho={RHO}, lambda={LAM}; step = grouped Brand update of all "

@@ -335,6 +335,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
 // ---------------------------------------------------------------------------
 struct PrePlan {
   int64_t dG, dA, lduG, lduA, ldg, lds;
+  int aligned16;  // every G and S pointer 16-byte aligned and ldg, lds multiples of 4
   int NG, NA, ks3;
   int64_t oT1, oT2, oT3, oPart, ocG, ocA, oBeta;
   size_t per_problem;
@@ -376,12 +377,12 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   // T1 = U_G^T G   (NG x dA, row-major)
   GemmArgs g1;
   g1.A = op(PU_G, 0, p.lduG, 1); g1.B = op(P_G, 0, p.ldg, 1); g1.C = op(PWS, p.oT1, dA, 1);
-  g1.m = NG; g1.n = (int)dA; g1.k = (int)dG;
+  g1.m = NG; g1.n = (int)dA; g1.k = (int)dG; g1.aligned16 = p.aligned16;
   KFB_TRY((mm<PR, 0, TU, TGrad, TA, TA, TA>(drecs, nrec, g1, s)));
   // T2 = G U_A     (dG x NA, column-major)
   GemmArgs g2;
   g2.A = op(P_G, 0, p.ldg, 1); g2.B = op(PU_A, 0, 1, p.lduA); g2.C = op(PWS, p.oT2, 1, dG);
-  g2.m = (int)dG; g2.n = NA; g2.k = (int)dA;
+  g2.m = (int)dG; g2.n = NA; g2.k = (int)dA; g2.aligned16 = p.aligned16;
   KFB_TRY((mm<PR, 0, TGrad, TU, TA, TA, TA>(drecs, nrec, g2, s)));
   // T3 = T1 U_A    (NG x NA)
   GemmArgs g3;
@@ -418,7 +419,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g5.B.slot2 = PU_A; g5.B.off2 = 0; g5.B.rs2 = p.lduA; g5.B.cs2 = 1; g5.B.split = NG;
   g5.C0 = op(P_G, 0, p.ldg, 1); g5.beta_slot = PWS; g5.beta_off = p.oBeta;
   g5.C = op(P_S, 0, p.lds, 1);
-  g5.m = (int)dG; g5.n = (int)dA; g5.k = NG + NA;
+  g5.m = (int)dG; g5.n = (int)dA; g5.k = NG + NA; g5.aligned16 = p.aligned16;
   KFB_TRY((mm<PR, 0, TU, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
   return KFB_OK;
 }
@@ -527,8 +528,10 @@ int dispatch_precond(int count, kfb_state_t const* stG, kfb_state_t const* stA, 
   if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
   Rec* host = (Rec*)malloc(sizeof(Rec) * (size_t)count);
   if (!host) return KFB_EINVAL;
+  p.aligned16 = (ldg % 4 == 0) && (lds % 4 == 0);
   for (int i = 0; i < count; ++i) {
     if (!G[i] || !S[i] || G[i] == S[i] || !(lamG[i] > 0.0) || !(lamA[i] > 0.0)) { free(host); return KFB_EINVAL; }
+    if ((((uintptr_t)G[i]) | ((uintptr_t)S[i])) & 15) p.aligned16 = 0;
     kfb_state_t g = stG[i], a = stA[i];
     Rec* rc = &host[i];
     memset(rc, 0, sizeof(Rec));

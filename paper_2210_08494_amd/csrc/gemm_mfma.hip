@@ -282,6 +282,218 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_kernel(const Rec* __restrict__ 
       }
 }
 
+// ---------------------------------------------------------------------------
+// Streamlined variant for large single-term FP32 products (the two-sided
+// apply): every operand 16-byte aligned with a unit stride along rows (MN)
+// or along k (KC), k and segment splits multiples of 32, m and n multiples
+// of 4.  The orientation of each operand is a template parameter and every
+// per-thread address is formed once, so a k tile costs four vector loads,
+// eight packed conversions and four LDS stores per operand.  LDS rows of
+// MN-staged operands permute their four 16-byte k chunks by bits 4-5 of the
+// row index, which spreads the transposed stores of a wave (rows 4 apart)
+// over the banks while 16 consecutive rows still read conflict-free.
+// ---------------------------------------------------------------------------
+template <bool KC>
+__device__ __forceinline__ int fast_lds_off(int row, int kb16) {  // kb16: bf16 offset in the row, multiple of 4
+  return KC ? row * MLD + kb16 : row * MLD + 8 * ((kb16 >> 3) ^ ((row >> 4) & 3)) + (kb16 & 7);
+}
+
+typedef const float __attribute__((address_space(1)))* gfptr;  // global-memory float pointer
+
+template <bool KC>
+struct FastSrc {
+  gfptr p0;
+  gfptr p1;             // this thread's base per segment (row offset applied, k offset not)
+  int64_t k0s, k1s;     // stride along k per segment
+  int64_t r0s, r1s;     // stride along rows per segment (KC: between the thread's four rows)
+  int split;
+  int nr;               // KC: rows of the thread's four in range; MN: 4 or 0
+  __device__ void init(const Rec& rec, const OpRef& o, bool isa, int row0, int nrows, int t) {
+    const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
+    const int left = nrows - (row0 + 4 * rb);
+    nr = KC ? (left < 0 ? 0 : left > 4 ? 4 : left) : (left > 0 ? 4 : 0);
+    // rows outside the matrix read row 0 (always valid) and are zeroed afterwards
+    const int gr = nr ? row0 + 4 * rb : 0;
+    split = o.slot2 >= 0 ? o.split : 0x7fffffff;
+    // A(i, k) = base[i*rs + k*cs];  B(k, j) = base[k*rs + j*cs]
+    {
+      const float* base = at<const float>(rec, o.slot, o.off);
+      r0s = isa ? o.rs : o.cs;
+      k0s = isa ? o.cs : o.rs;
+      p0 = (gfptr)(base + (int64_t)gr * r0s + (int64_t)(4 * kb) * k0s);
+    }
+    if (o.slot2 >= 0) {
+      const float* base = at<const float>(rec, o.slot2, o.off2);
+      r1s = isa ? o.rs2 : o.cs2;
+      k1s = isa ? o.cs2 : o.rs2;
+      p1 = (gfptr)(base + (int64_t)gr * r1s + (int64_t)(4 * kb) * k1s);
+    } else {
+      p1 = p0; r1s = r0s; k1s = k0s;
+    }
+  }
+  // the 4 x 4 sub-block (rows x k) of k tile k0 into f; no branches around the loads
+  __device__ __forceinline__ void load(int k0, Frag& f) const {
+    const bool sg = k0 >= split;
+    const int64_t kk = sg ? k0 - split : k0;
+    const int64_t ks = sg ? k1s : k0s, rs = sg ? r1s : r0s;
+    const gfptr b = (sg ? p1 : p0) + kk * ks;
+    typedef __attribute__((__vector_size__(16))) float v4;
+    if (KC) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const v4 x = *reinterpret_cast<const __attribute__((address_space(1))) v4*>(b + (r < nr ? r : 0) * rs);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) f.v[r][c] = r < nr ? x[c] : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const v4 x = *reinterpret_cast<const __attribute__((address_space(1))) v4*>(b + c * ks);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f.v[r][c] = nr ? x[r] : 0.f;
+      }
+    }
+  }
+};
+
+template <bool KC>
+__device__ __forceinline__ void fast_store(const Frag& f, int t, __bf16* dst) {
+  const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
+  typedef __attribute__((__vector_size__(8))) __bf16 v4b;
+  typedef __attribute__((__vector_size__(16))) float v4f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const v4f x = {f.v[r][0], f.v[r][1], f.v[r][2], f.v[r][3]};
+    *reinterpret_cast<v4b*>(&dst[fast_lds_off<KC>(4 * rb + r, 4 * kb)]) = __builtin_convertvector(x, v4b);
+  }
+}
+
+template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP>
+__global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restrict__ recs, GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][128 * MLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][128 * MLD];
+  const Rec& rec = recs[blockIdx.z];
+  const int tm = blockIdx.x, tn = blockIdx.y;
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  constexpr bool swp = SWP;  // output column-major: issue (B^T A^T) so stores coalesce
+  FastSrc<AKC> A;
+  FastSrc<BKC> B;
+  A.init(rec, g.A, true, tm * 128, g.m, t);
+  B.init(rec, g.B, false, tn * 128, g.n, t);
+  // fragment read offsets (bf16 elements) into a stage
+  const int kq = 8 * (l / 16);
+  int offA[4], offB[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    offA[i] = fast_lds_off<AKC>(wm + i * 16 + (l % 16), kq);
+    offB[i] = fast_lds_off<BKC>(wn + i * 16 + (l % 16), kq);
+  }
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  Frag fa, fb;
+  A.load(0, fa);
+  B.load(0, fb);
+  fast_store<AKC>(fa, t, sA[0]);
+  fast_store<BKC>(fb, t, sB[0]);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < g.k; k0 += MBK) {
+    const bool more = k0 + MBK < g.k;
+    if (more) {
+      A.load(k0 + MBK, fa);
+      B.load(k0 + MBK, fb);
+    }
+    bf16x8 af[4], bfr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      af[i] = *reinterpret_cast<const bf16x8*>(&sA[cur][offA[i]]);
+      bfr[i] = *reinterpret_cast<const bf16x8*>(&sB[cur][offB[i]]);
+    }
+    if constexpr (!swp) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      fast_store<AKC>(fa, t, sA[cur ^ 1]);
+      fast_store<BKC>(fb, t, sB[cur ^ 1]);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  TC* C = at<TC>(rec, g.C.slot, g.C.off);
+  const bool use_c0 = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
+  const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
+  const float alpha = (float)g.alpha;
+  const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+  const int gm0 = tm * 128 + wm, gn0 = tn * 128 + wn;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi, gj;
+        if (swp) { gi = gm0 + 16 * i + (l % 16); gj = gn0 + 16 * j + 4 * (l / 16) + v; }
+        else { gi = gm0 + 16 * i + 4 * (l / 16) + v; gj = gn0 + 16 * j + (l % 16); }
+        if (gi < g.m && gj < g.n) {
+          float val = alpha * acc[i][j][v];
+          if (C0) val += beta * to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+          C[gi * g.C.rs + gj * g.C.cs] = TC(val);
+        }
+      }
+}
+
+// orientation of an operand for the streamlined kernel: 1 = unit stride along
+// k, 0 = unit stride along rows, -1 = not eligible
+static int fast_orient(const OpRef& o, bool isa) {
+  auto one = [&](int64_t rs, int64_t cs) -> int {
+    const int64_t r_st = isa ? rs : cs, k_st = isa ? cs : rs;
+    if (k_st == 1 && r_st % 4 == 0) return 1;
+    if (r_st == 1 && k_st % 4 == 0) return 0;
+    return -1;
+  };
+  const int a = one(o.rs, o.cs);
+  if (o.slot2 < 0) return a;
+  if (o.split % MBK) return -1;
+  return one(o.rs2, o.cs2) == a ? a : -1;
+}
+
+template <typename TC, typename TC0>
+static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s, hipError_t* err) {
+  if (!g.aligned16 || g.ksplit > 1 || g.k <= 0 || g.k % MBK || g.m % 4 || g.n % 4) return false;
+  const int ao = fast_orient(g.A, true), bo = fast_orient(g.B, false);
+  if (ao < 0 || bo < 0) return false;
+  dim3 grid((g.m + 127) / 128, (g.n + 127) / 128, nrec);
+  const bool swp = g.C.rs == 1;
+#define KFB_FAST(AK, BK, SW) \
+  hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW>), grid, dim3(MNT), 0, s, recs, g)
+  if (swp) {
+    if (ao && bo) KFB_FAST(true, true, true);
+    else if (ao) KFB_FAST(true, false, true);
+    else if (bo) KFB_FAST(false, true, true);
+    else KFB_FAST(false, false, true);
+  } else {
+    if (ao && bo) KFB_FAST(true, true, false);
+    else if (ao) KFB_FAST(true, false, false);
+    else if (bo) KFB_FAST(false, true, false);
+    else KFB_FAST(false, false, false);
+  }
+#undef KFB_FAST
+  *err = hipGetLastError();
+  return true;
+}
+
 // fixed-order sum of split-K partials (FP32), then alpha / beta epilogue
 template <typename TC, typename TC0>
 __global__ __launch_bounds__(256) void mfma_splitk_reduce(const Rec* __restrict__ recs, GemmArgs g) {
@@ -306,6 +518,10 @@ __global__ __launch_bounds__(256) void mfma_splitk_reduce(const Rec* __restrict_
 template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
 hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t s) {
   if (g0.m <= 0 || g0.n <= 0 || nrec <= 0) return hipSuccess;
+  if constexpr (SPLIT == 0 && sizeof(TA) == 4 && sizeof(TB) == 4 && sizeof(TC) == 4) {
+    hipError_t e;
+    if (gemm_bf16_fast<TC, TC0>(recs, nrec, g0, s, &e)) return e;
+  }
   GemmArgs g = g0;
   if (g.k < 0) g.k = 0;
   const int tiles_m = (g.m + MBM - 1) / MBM, tiles_n = (g.n + MBN - 1) / MBN;

@@ -49,6 +49,8 @@ struct GemmArgs {
   // when beta_slot >= 0; lets a launch use per-problem values computed on the GPU
   int32_t beta_slot = -1;
   int64_t beta_off = 0;
+  // caller's promise: every pointer of A, B, C0 and C is 16-byte aligned
+  int32_t aligned16 = 0;
 };
 
 template <typename T>

@@ -926,7 +926,7 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
   double* Z = G + P * P;                           // Z[i*ZP + j]
   double* slot = G;                                // Gram partials (5 tiles x 256 per slot), before G is formed
   __shared__ double rc[NP2], rsn[NP2];
-  __shared__ int pass_rot, any_off;
+  __shared__ int pass_rot, any_off, step_any[2];
   const Rec& rec = recs[blockIdx.y];
   int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
   const int Np = a.Np, Ns = Np / 16;
@@ -986,7 +986,7 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
       }
     }
   }
-  if (t == 0) { any_off = 0; pass_rot = 0; }
+  if (t == 0) { any_off = 0; pass_rot = 0; step_any[0] = 0; }
   __syncthreads();
   for (int e = t; e < P * P; e += JG_NT) {
     const int i = e / P, j = e % P;
@@ -1015,12 +1015,17 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
         c = yy * ry;
         sn = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
         ++nrot;
+        step_any[st & 1] = 1;
       }
       rc[t] = c;
       rsn[t] = sn;
     }
     __syncthreads();
-    {
+    // a step in which no pair rotates leaves G and Z as they are: skip its update
+    // (the flag of the next step is cleared here, after everyone has read its last use)
+    const bool upd = step_any[st & 1] != 0;
+    if (t == 0) step_any[(st + 1) & 1] = 0;
+    if (upd) {
       // thread: pair ib = t % 32 (columns) with pairs t/32 and t/32 + 16 (rows) of G,
       // and rows t/32 + 16k (k < 4) of Z in the columns of pair ib; every read first
       const int ib = t & 31, r0 = t >> 5;
@@ -1060,9 +1065,10 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
         Z[iz * ZP + pb] = cb * zv[k][0] - sb * zv[k][1];
         Z[iz * ZP + qb] = sb * zv[k][0] + cb * zv[k][1];
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (t < 64) {  // rotations counted by the lanes that chose them (wave 0)
     int tot = nrot;
 #pragma unroll
@@ -1226,8 +1232,10 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
         rc[l] = c;
         rsn[l] = sn;
       }
-      nrot += __popcll(__ballot(rot));
+      const int nr = __popcll(__ballot(rot));
+      nrot += nr;
       wave_sync();
+      if (nr == 0) continue;  // nothing rotates in this step: G and Z stay as they are
       // lane l: 2x2 blocks (pair l/16 + 4k, pair l%16) of G, k < 4, and rows
       // l/16 + 4k, k < 8, of Z in the columns of pair l%16.  All operands are
       // read before any result is written (the blocks and Z entries of one
