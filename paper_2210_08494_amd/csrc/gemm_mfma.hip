@@ -312,7 +312,8 @@ struct FastSrc {
     const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
     const int left = nrows - (row0 + 4 * rb);
     nr = KC ? (left < 0 ? 0 : left > 4 ? 4 : left) : (left > 0 ? 4 : 0);
-    // rows outside the matrix read row 0 (always valid) and are zeroed afterwards
+    // rows outside the matrix read row 0 instead (always valid); they only feed
+    // output rows / columns outside C, which the epilogue never stores
     const int gr = nr ? row0 + 4 * rb : 0;
     split = o.slot2 >= 0 ? o.split : 0x7fffffff;
     // A(i, k) = base[i*rs + k*cs];  B(k, j) = base[k*rs + j*cs]
@@ -331,40 +332,30 @@ struct FastSrc {
       p1 = p0; r1s = r0s; k1s = k0s;
     }
   }
-  // the 4 x 4 sub-block (rows x k) of k tile k0 into f; no branches around the loads
-  __device__ __forceinline__ void load(int k0, Frag& f) const {
+  // the 4 x 4 sub-block (rows x k) of k tile k0 as four raw vectors (KC: x[r] =
+  // row r, MN: x[c] = k column c); no branches around the loads (values of rows
+  // outside the matrix are arbitrary: they never reach C)
+  __device__ __forceinline__ void load(int k0, f32x4* x) const {
     const bool sg = k0 >= split;
     const int64_t kk = sg ? k0 - split : k0;
     const int64_t ks = sg ? k1s : k0s, rs = sg ? r1s : r0s;
     const gfptr b = (sg ? p1 : p0) + kk * ks;
-    typedef __attribute__((__vector_size__(16))) float v4;
-    if (KC) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const v4 x = *reinterpret_cast<const __attribute__((address_space(1))) v4*>(b + (r < nr ? r : 0) * rs);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) f.v[r][c] = r < nr ? x[c] : 0.f;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const v4 x = *reinterpret_cast<const __attribute__((address_space(1))) v4*>(b + c * ks);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) f.v[r][c] = nr ? x[r] : 0.f;
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int64_t o = KC ? (q < nr ? q : 0) * rs : q * ks;
+      x[q] = *reinterpret_cast<const __attribute__((address_space(1))) f32x4*>(b + o);
     }
   }
 };
 
 template <bool KC>
-__device__ __forceinline__ void fast_store(const Frag& f, int t, __bf16* dst) {
+__device__ __forceinline__ void fast_store(const f32x4* x, int t, __bf16* dst) {
   const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
   typedef __attribute__((__vector_size__(8))) __bf16 v4b;
-  typedef __attribute__((__vector_size__(16))) float v4f;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const v4f x = {f.v[r][0], f.v[r][1], f.v[r][2], f.v[r][3]};
-    *reinterpret_cast<v4b*>(&dst[fast_lds_off<KC>(4 * rb + r, 4 * kb)]) = __builtin_convertvector(x, v4b);
+    const f32x4 v = KC ? x[r] : f32x4{x[0][r], x[1][r], x[2][r], x[3][r]};  // row r, k = 4kb .. 4kb+3
+    *reinterpret_cast<v4b*>(&dst[fast_lds_off<KC>(4 * rb + r, 4 * kb)]) = __builtin_convertvector(v, v4b);
   }
 }
 
@@ -394,7 +385,7 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  Frag fa, fb;
+  f32x4 fa[4], fb[4];
   A.load(0, fa);
   B.load(0, fb);
   fast_store<AKC>(fa, t, sA[0]);
