@@ -255,10 +255,24 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   int64_t srcZ = p.oZ, dstZ = p.oZb;
   const int64_t oR[3] = {p.oR1, p.oR2, p.oR3}, oX[2] = {p.oX1, p.oX2};
   for (int pass = 0; pass < passes; ++pass) {
-    GemmArgs gg;
-    gg.A = op(WS, srcZ, d, 1); gg.B = op(WS, srcZ, 1, d); gg.C = op(WS, p.oGram, 1, n);
-    gg.m = n; gg.n = n; gg.k = (int)d; gg.ksplit = p.ksG; gg.Part = op(WS, p.oPart, 1, n);
-    KFB_TRY((gemm<TZ, TZ, TG, TG, TG>(drecs, nrec, gg, s)));
+    if constexpr (sizeof(TG) == 8) {
+      if (d % 16 == 0) {  // upper blocks on FP64 MFMA
+        GramArgs ga;
+        ga.n = n; ga.ks = p.ksG; ga.kchunk = 0; ga.d = d;
+        ga.off_Z = srcZ; ga.off_part = p.oPart; ga.off_gram = p.oGram;
+        KFB_TRY(gram_f64<TZ>(drecs, nrec, ga, s));
+      } else {
+        GemmArgs gg;
+        gg.A = op(WS, srcZ, d, 1); gg.B = op(WS, srcZ, 1, d); gg.C = op(WS, p.oGram, 1, n);
+        gg.m = n; gg.n = n; gg.k = (int)d; gg.ksplit = p.ksG; gg.Part = op(WS, p.oPart, 1, n);
+        KFB_TRY((gemm<TZ, TZ, TG, TG, TG>(drecs, nrec, gg, s)));
+      }
+    } else {
+      GemmArgs gg;
+      gg.A = op(WS, srcZ, d, 1); gg.B = op(WS, srcZ, 1, d); gg.C = op(WS, p.oGram, 1, n);
+      gg.m = n; gg.n = n; gg.k = (int)d; gg.ksplit = p.ksG; gg.Part = op(WS, p.oPart, 1, n);
+      KFB_TRY((gemm<TZ, TZ, TG, TG, TG>(drecs, nrec, gg, s)));
+    }
     CholArgs ca;
     ca.n = n; ca.off_gram = p.oGram; ca.off_R = oR[pass]; ca.off_Rinv = oX[pass & 1]; ca.off_rowbuf = 0;
     ca.tau_rel = tau;

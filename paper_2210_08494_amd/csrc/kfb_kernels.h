@@ -28,6 +28,16 @@ hipError_t copy2d(const Rec* recs, int nrec, OpRef dst, OpRef src, int m, int n,
 hipError_t zero_words(const Rec* recs, int nrec, int slot, int64_t off, int nwords, hipStream_t s);
 
 // ---- Brand-update stages ---------------------------------------------------
+// Upper blocks of the FP64 Gram W = Z^T Z (Z: d x n column-major, ld = d,
+// d a multiple of 16), split over ks row chunks with fixed-order summation.
+struct GramArgs {
+  int n, ks, kchunk;
+  int64_t d;
+  int64_t off_Z, off_part, off_gram;  // in WS: Z, ks x n x n partials, n x n result
+};
+template <typename TZ>
+hipError_t gram_f64(const Rec* recs, int nrec, const GramArgs& a, hipStream_t s);
+
 struct CholArgs {
   int n;
   int64_t off_gram, off_R, off_Rinv;  // n x n column-major in WS

@@ -34,6 +34,9 @@ __device__ __forceinline__ void wave_sync() {
   asm volatile("" ::: "memory");
 }
 
+// four doubles: an FP64 MFMA 16x16x4 accumulator fragment
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double jac_d4;
+
 template <typename T> struct Eps;
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 template <> struct Eps<float> { static constexpr float v = 1.1920929e-07f; };
@@ -465,6 +468,119 @@ hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
+// Gram matrix of the residual in FP64 for CholeskyQR (Algorithm 3's thin QR):
+// W = Z^T Z for Z d x n (column-major, ld = d, FP32 or FP64 entries; FP32
+// products are exact in FP64).  Only the blocks on and above the diagonal are
+// formed (the Cholesky reads the upper triangle): a workgroup takes a 64 x 64
+// block over a chunk of rows of Z, four waves 32 x 32 each on
+// v_mfma_f64_16x16x4f64, each lane feeding four consecutive rows of its column
+// to four MFMA steps; the result is issued transposed so partial stores
+// coalesce.  Chunks are summed in a fixed order by gram_reduce_kernel.
+// ---------------------------------------------------------------------------
+template <typename TZ>
+__device__ __forceinline__ jac_d4 gram_ld4(const TZ* p) {
+  if constexpr (sizeof(TZ) == 8) {
+    return *reinterpret_cast<const jac_d4*>(p);
+  } else {
+    typedef __attribute__((__vector_size__(16))) float f4;
+    const f4 x = *reinterpret_cast<const f4*>(p);
+    return jac_d4{(double)x[0], (double)x[1], (double)x[2], (double)x[3]};
+  }
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(256) void gram_f64_kernel(const Rec* __restrict__ recs, GramArgs a) {
+  const Rec& rec = recs[blockIdx.z];
+  const int n = a.n, nb = (n + 63) / 64;
+  // upper block index -> (bi, bj), bi <= bj, column-major triangular order
+  int b = blockIdx.x, bj = 0;
+  while (b > bj) { b -= bj + 1; ++bj; }
+  const int bi = b;
+  const int64_t d = a.d;
+  const int64_t k0 = (int64_t)blockIdx.y * a.kchunk;
+  const int64_t k1 = min(d, k0 + a.kchunk);
+  const TZ* Z = at<const TZ>(rec, WS, a.off_Z);
+  double* part = at<double>(rec, WS, a.off_part) + (int64_t)blockIdx.y * n * n;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int ci0 = 64 * bi + 32 * (w & 1), cj0 = 64 * bj + 32 * (w >> 1);
+  // this lane's columns (clamped into range; columns >= n are never stored)
+  const TZ* pa[2];
+  const TZ* pb[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int ca = min(ci0 + 16 * u + (l & 15), n - 1), cb = min(cj0 + 16 * u + (l & 15), n - 1);
+    pa[u] = Z + (int64_t)ca * d + 4 * (l >> 4);
+    pb[u] = Z + (int64_t)cb * d + 4 * (l >> 4);
+  }
+  jac_d4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = jac_d4{0.0, 0.0, 0.0, 0.0};
+  (void)nb;
+  for (int64_t k = k0; k < k1; k += 16) {
+    jac_d4 xa[2], xb[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      xa[u] = gram_ld4<TZ>(pa[u] + k);
+      xb[u] = gram_ld4<TZ>(pb[u] + k);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)  // transposed issue: D[p][q] = W[ci_q][cj_p]
+          acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[v][e], xa[u][e], acc[u][v], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ci0 + 16 * u + (l & 15), j = cj0 + 16 * v + (l >> 4) + 4 * q;
+        if (i < n && j < n) part[i + (int64_t)j * n] = acc[u][v][q];
+      }
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const Rec* __restrict__ recs, GramArgs a) {
+  const Rec& rec = recs[blockIdx.z];
+  const int n = a.n;
+  int b = blockIdx.x, bj = 0;
+  while (b > bj) { b -= bj + 1; ++bj; }
+  const int bi = b;
+  const double* part = at<const double>(rec, WS, a.off_part);
+  double* W = at<double>(rec, WS, a.off_gram);
+  const int64_t nn = (int64_t)n * n;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = 64 * bi + (e & 63), j = 64 * bj + (e >> 6);
+    if (i >= n || j >= n) continue;
+    const int64_t o = i + (int64_t)j * n;
+    double s = 0.0;
+    for (int kz = 0; kz < a.ks; ++kz) s += part[kz * nn + o];
+    W[o] = s;
+  }
+}
+
+template <typename TZ>
+hipError_t gram_f64(const Rec* recs, int nrec, const GramArgs& a0, hipStream_t s) {
+  if (a0.n <= 0 || nrec <= 0) return hipSuccess;
+  GramArgs a = a0;
+  const int nb = (a.n + 63) / 64, nblk = nb * (nb + 1) / 2;
+  if (a.ks < 1) a.ks = 1;
+  a.kchunk = (int)(((a.d + a.ks - 1) / a.ks + 15) / 16 * 16);
+  a.ks = (int)((a.d + a.kchunk - 1) / a.kchunk);
+  hipLaunchKernelGGL((gram_f64_kernel<TZ>), dim3(nblk, a.ks, nrec), dim3(256), 0, s, recs, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(nblk, 1, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+template hipError_t gram_f64<float>(const Rec*, int, const GramArgs&, hipStream_t);
+template hipError_t gram_f64<double>(const Rec*, int, const GramArgs&, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Core assembly.  With L = [[diag(sqrt(rho D)), sqrt(w) P], [0, sqrt(w) R]]
 // (N x N, P = U^T M including the re-projection, R the residual's triangular
 // factor), the Brand core is M_S = L L^T.  The Jacobi iteration orthogonalises
@@ -557,7 +673,6 @@ __device__ __forceinline__ void tour_pair(int P, int st, int q, int* x, int* y) 
   else { *x = (st + q) % R; *y = (st - q + R) % R; }
 }
 
-typedef __attribute__((__vector_size__(4 * sizeof(double)))) double jac_d4;
 
 // G = C^T C for the panel C (Np x P, column stride LDP) into G (row-major P x P).
 // FP64 with P >= 16: 16x16 tiles on MFMA (upper triangle, one wave per tile

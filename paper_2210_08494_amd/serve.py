@@ -16,6 +16,10 @@ Scheduling (host side; all arithmetic runs in the HIP library):
 * same-phase admitted requests are fused by shape bucket into one grouped
   launch sequence (``kfb_brand_update_batched`` / ``kfb_precondition_batched``,
   whose per-problem results equal single calls bit for bit);
+* at most ``max_inflight`` groups are on the device at once: while the slots
+  are taken, arriving requests wait and are fused into larger groups when a
+  slot frees (this is what lets throughput approach the grouped closed loop
+  under load instead of flooding the device with groups of one);
 * groups go round-robin onto several default-priority HIP streams, each first
   waiting on the completion events of the last operations on its states, so
   work on different states overlaps on the device while per-state order holds;
@@ -82,7 +86,8 @@ class ServerStats:
 
 class Server:
     def __init__(self, layers, n_max: int, rho: float = 0.95, prec: int = kfb.KFB_BF16_MIXED,
-                 streams: int = 4, byte_budget: int = 8 << 30, max_group: int = 64, device="cuda"):
+                 streams: int = 4, byte_budget: int = 8 << 30, max_group: int = 64, device="cuda",
+                 max_inflight: int | None = None):
         """layers: list of (d_in, d_out, r_A, r_G)."""
         import torch
         self.torch = torch
@@ -96,6 +101,7 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.byte_budget = int(byte_budget)
         self.max_group = int(max_group)
+        self.max_inflight = int(max_inflight) if max_inflight else len(self.streams)
         self.pending = collections.deque()
         self.inflight: list[_Group] = []
         self.inflight_bytes = 0
@@ -143,14 +149,24 @@ class Server:
         return done
 
     def step(self) -> int:
-        """One scheduler tick: retire, admit, group, issue.  Returns groups issued."""
+        """One scheduler tick: retire, admit, group, issue into the free slots.
+        Returns the number of groups issued."""
         self.poll()
+        free = self.max_inflight - len(self.inflight)
+        if free <= 0 or not self.pending:
+            return 0
         admitted = self._admit()
         issued = 0
+        leftover = []
         for key, reqs in admitted.items():
             for i in range(0, len(reqs), self.max_group):
-                if self._issue(key, reqs[i:i + self.max_group]):
+                chunk = reqs[i:i + self.max_group]
+                if issued < free and self._issue(key, chunk):
                     issued += 1
+                else:
+                    leftover.extend(chunk)
+        if leftover:  # back into the queue in arrival order (keeps per-state FIFO)
+            self.pending = collections.deque(sorted(list(self.pending) + leftover, key=lambda r: r.rid))
         return issued
 
     def drain(self, timeout_s: float = 120.0):
