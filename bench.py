@@ -82,6 +82,25 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"n={N_BATCH} on the host, median {med:.3f} s each"}
 
 
+def _measured_traffic(kfb, kname):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, only when it was taken on this exact library build."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"{kname}_d4096_r256_n256_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    build = kfb.load().kfb_build_info().decode()
+    if vals.get("library") != build or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def serve_leg(torch, kfb, dev, args):
     """Open-loop Poisson serving at the headline shape: 70% updates (uniform over
     layer and factor), 30% preconditionings (uniform layer), continuous batching."""
@@ -138,6 +157,8 @@ def main():
     ap.add_argument("--fp32-updates", type=int, default=6)
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--serve-rates", default="400,2000")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (factor states "
@@ -213,9 +234,10 @@ def main():
         kdesc = f"{kname} (block one-sided Jacobi round, FP64, {2 * (cfg & 0xFF)}-column panels streamed from HBM)"
     else:
         kdesc = f"jacobi_kernel<double,{cfg}> (block one-sided Jacobi round, FP64, panel in LDS)"
+    traffic = _measured_traffic(kfb, kname if cfg & kfb.KFB_JAC_STREAMED else "jacobi_kernel")
     roofline = {"kernel": kdesc,
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic,
                 "per_launch": {"algorithmic_flops": flops_per_launch, "avg_ms": avg_launch_ms,
                                "launches_per_update_call": launches_per_call,
                                "unit_work": "9*(r+n)^3 FP64 flops per core eigensolve, 48 cores per call"}}
@@ -256,9 +278,11 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         lat32.append(e0.elapsed_time(e1))
-    fp32_plain = {"value": round(1e3 / (sum(lat32) / len(lat32)), 2), "unit": "B-updates/s",
-                  "ms_per_update_p50": round(_percentile(lat32, 50), 3), "states": 2,
-                  "mode": "one update at a time, no grouping"}
+    fp32_plain = None
+    if lat32:
+        fp32_plain = {"value": round(1e3 / (sum(lat32) / len(lat32)), 2), "unit": "B-updates/s",
+                      "ms_per_update_p50": round(_percentile(lat32, 50), 3), "states": 2,
+                      "mode": "one update at a time, no grouping"}
 
     # ---- single mixed update latency (no grouping), for the latency columns
     lat1 = []
@@ -303,9 +327,15 @@ def main():
         "autotune": {"jacobi_config": tune.config_name(best_bw) if best_bw else None,
                      "candidates_ms": {tune.config_name(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},
     }
+    out["library"] = kfb.load().kfb_build_info().decode()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        a = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

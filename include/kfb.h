@@ -182,7 +182,9 @@ int kfb_profile_report(char* buf, size_t len, int reset);
 
 const char* kfb_strerror(int code);
 
-/* Library build identification (compiled target, e.g. "gfx950"). */
+/* Library build identification: "kfb gfx950 hip src=<digest>", the digest a
+ * SHA-1 prefix over the library's sources, so a measurement can be tied to the
+ * exact code it was taken on. */
 const char* kfb_build_info(void);
 
 #ifdef __cplusplus

@@ -28,15 +28,30 @@ def _hipcc():
     return "hipcc"
 
 
+def source_digest() -> str:
+    """SHA-1 (12 hex digits) over the library's sources and headers: names the
+    build in kfb_build_info, so measurements can be matched to the code."""
+    import hashlib
+    h = hashlib.sha1()
+    files = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hip", ".h"))]
+    files.append(os.path.join(INCLUDE, "kfb.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libkfb.so; returns the library path."""
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    digest = source_digest()
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, f"-DKFB_SRC_DIGEST=\"{digest}\"", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

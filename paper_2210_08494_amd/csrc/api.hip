@@ -804,6 +804,9 @@ const char* kfb_strerror(int code) {
   }
 }
 
-const char* kfb_build_info(void) { return "kfb gfx950 hip"; }
+#ifndef KFB_SRC_DIGEST
+#define KFB_SRC_DIGEST "unknown"
+#endif
+const char* kfb_build_info(void) { return "kfb gfx950 hip src=" KFB_SRC_DIGEST; }
 
 }  // extern "C"

@@ -64,5 +64,9 @@ def test_create_rejects_bad_arguments_without_touching_memory(lib):
 def test_strerror_and_build_info(lib):
     assert lib.kfb_strerror(0) == b"ok"
     assert lib.kfb_strerror(2).startswith(b"buffer")
-    assert b"gfx950" in lib.kfb_build_info()
+    info = lib.kfb_build_info()
+    assert b"gfx950" in info
+    # the digest names the exact sources the library was built from
+    from paper_2210_08494_amd import build as kbuild
+    assert info.endswith(b"src=" + kbuild.source_digest().encode())
     assert lib.kfb_destroy(None) == 1
