@@ -1032,6 +1032,33 @@ __device__ __forceinline__ void jg_gram_part(const double* const* cp, int Ns, in
   }
 }
 
+// rotation (c, s) zeroing the (p, q) entry of a Gram, or false when the pair is
+// already orthogonal to tolerance (c = 1, s = 0)
+__device__ __forceinline__ bool jg_rot(double gpp, double gqq, double gpq, double tol, double* c, double* s) {
+  *c = 1.0;
+  *s = 0.0;
+  if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
+    const double aa = gqq - gpp, bb = 2.0 * gpq;
+    const double ir = dev_rsqrt(aa * aa + bb * bb);
+    const double yy = 0.5 * (1.0 + fabs(aa) * ir);
+    const double ry = dev_rsqrt(yy);
+    *c = yy * ry;
+    *s = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
+    return true;
+  }
+  return false;
+}
+
+// J_A^T g J_B for the 2 x 2 block g = {(pa, pb), (pa, qb), (qa, pb), (qa, qb)}
+__device__ __forceinline__ void jg_rot_block(double ca, double sa, double cb, double sb, double* g) {
+  const double r00 = cb * g[0] - sb * g[1], r01 = sb * g[0] + cb * g[1];
+  const double r10 = cb * g[2] - sb * g[3], r11 = sb * g[2] + cb * g[3];
+  g[0] = ca * r00 - sa * r10;
+  g[2] = sa * r00 + ca * r10;
+  g[1] = ca * r01 - sa * r11;
+  g[3] = sa * r01 + ca * r11;
+}
+
 __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
                                                             int round) {
   extern __shared__ __attribute__((aligned(16))) unsigned char jg_smem[];
@@ -1041,6 +1068,7 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
   double* Z = G + P * P;                           // Z[i*ZP + j]
   double* slot = G;                                // Gram partials (5 tiles x 256 per slot), before G is formed
   __shared__ double rc[NP2], rsn[NP2];
+  __shared__ double hc[2][NP2], hs[2][NP2];  // cross rounds: rotations of the current and next step
   __shared__ int pass_rot, any_off, step_any[2];
   const Rec& rec = recs[blockIdx.y];
   int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
@@ -1116,71 +1144,178 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
   // ---- 2. plane rotations on G, accumulating Z
   const int nsteps = any_off ? (full ? P - 1 : BW) : 0;
   int nrot = 0;
-  for (int st = 0; st < nsteps; ++st) {
-    if (t < NP2) {
-      int p, q;
-      jg_pair(full, st, t, &p, &q);
-      const double gpp = G[p * P + p], gqq = G[q * P + q], gpq = G[p * P + q];
-      double c = 1.0, sn = 0.0;
-      if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
-        const double aa = gqq - gpp, bb = 2.0 * gpq;
-        const double ir = dev_rsqrt(aa * aa + bb * bb);
-        const double yy = 0.5 * (1.0 + fabs(aa) * ir);
-        const double ry = dev_rsqrt(yy);
-        c = yy * ry;
-        sn = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
-        ++nrot;
-        step_any[st & 1] = 1;
-      }
-      rc[t] = c;
-      rsn[t] = sn;
-    }
-    __syncthreads();
-    // a step in which no pair rotates leaves G and Z as they are: skip its update
-    // (the flag of the next step is cleared here, after everyone has read its last use)
-    const bool upd = step_any[st & 1] != 0;
-    if (t == 0) step_any[(st + 1) & 1] = 0;
-    if (upd) {
-      // thread: pair ib = t % 32 (columns) with pairs t/32 and t/32 + 16 (rows) of G,
-      // and rows t/32 + 16k (k < 4) of Z in the columns of pair ib; every read first
-      const int ib = t & 31, r0 = t >> 5;
-      int pb, qb, pa[2], qa[2];
-      jg_pair(full, st, ib, &pb, &qb);
-      const double cb = rc[ib], sb = rsn[ib];
-      double ca[2], sa[2], g[2][4], zv[4][2];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int ia = r0 + 16 * k;
-        jg_pair(full, st, ia, &pa[k], &qa[k]);
-        ca[k] = rc[ia];
-        sa[k] = rsn[ia];
-        g[k][0] = G[pa[k] * P + pb];
-        g[k][1] = G[pa[k] * P + qb];
-        g[k][2] = G[qa[k] * P + pb];
-        g[k][3] = G[qa[k] * P + qb];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int iz = r0 + 16 * k;
-        zv[k][0] = Z[iz * ZP + pb];
-        zv[k][1] = Z[iz * ZP + qb];
-      }
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const double r00 = cb * g[k][0] - sb * g[k][1], r01 = sb * g[k][0] + cb * g[k][1];
-        const double r10 = cb * g[k][2] - sb * g[k][3], r11 = sb * g[k][2] + cb * g[k][3];
-        G[pa[k] * P + pb] = ca[k] * r00 - sa[k] * r10;
-        G[qa[k] * P + pb] = sa[k] * r00 + ca[k] * r10;
-        G[pa[k] * P + qb] = ca[k] * r01 - sa[k] * r11;
-        G[qa[k] * P + qb] = sa[k] * r01 + ca[k] * r11;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int iz = r0 + 16 * k;
-        Z[iz * ZP + pb] = cb * zv[k][0] - sb * zv[k][1];
-        Z[iz * ZP + qb] = sb * zv[k][0] + cb * zv[k][1];
+  if (full) {
+    // first round of a sweep: all pairs of the panel (circle method), Z in LDS
+    for (int st = 0; st < nsteps; ++st) {
+      if (t < NP2) {
+        int p, q;
+        jg_pair(true, st, t, &p, &q);
+        double c, sn;
+        if (jg_rot(G[p * P + p], G[q * P + q], G[p * P + q], tol, &c, &sn)) {
+          ++nrot;
+          step_any[st & 1] = 1;
+        }
+        rc[t] = c;
+        rsn[t] = sn;
       }
       __syncthreads();
+      // a step in which no pair rotates leaves G and Z as they are: skip its update
+      // (the flag of the next step is cleared here, after everyone has read its last use)
+      const bool upd = step_any[st & 1] != 0;
+      if (t == 0) step_any[(st + 1) & 1] = 0;
+      if (upd) {
+        // thread: pair ib = t % 32 (columns) with pairs t/32 and t/32 + 16 (rows) of G,
+        // and rows t/32 + 16k (k < 4) of Z in the columns of pair ib; every read first
+        const int ib = t & 31, r0 = t >> 5;
+        int pb, qb, pa[2], qa[2];
+        jg_pair(true, st, ib, &pb, &qb);
+        const double cb = rc[ib], sb = rsn[ib];
+        double ca[2], sa[2], g[2][4], zv[4][2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int ia = r0 + 16 * k;
+          jg_pair(true, st, ia, &pa[k], &qa[k]);
+          ca[k] = rc[ia];
+          sa[k] = rsn[ia];
+          g[k][0] = G[pa[k] * P + pb];
+          g[k][1] = G[pa[k] * P + qb];
+          g[k][2] = G[qa[k] * P + pb];
+          g[k][3] = G[qa[k] * P + qb];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int iz = r0 + 16 * k;
+          zv[k][0] = Z[iz * ZP + pb];
+          zv[k][1] = Z[iz * ZP + qb];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          jg_rot_block(ca[k], sa[k], cb, sb, g[k]);
+          G[pa[k] * P + pb] = g[k][0];
+          G[pa[k] * P + qb] = g[k][1];
+          G[qa[k] * P + pb] = g[k][2];
+          G[qa[k] * P + qb] = g[k][3];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int iz = r0 + 16 * k;
+          Z[iz * ZP + pb] = cb * zv[k][0] - sb * zv[k][1];
+          Z[iz * ZP + qb] = sb * zv[k][0] + cb * zv[k][1];
+        }
+        __syncthreads();
+      }
+    }
+  } else if (nsteps > 0) {
+    // Later rounds: the BW x BW cross pairs, pair i = (i, BW + (i + st) % BW) at
+    // step st.  G is symmetric and is only read again through its upper half,
+    // so a step updates the 2 x 2 blocks (a, b) with a <= b only (528 of 1024)
+    // and keeps the entries on and above the diagonal of the two diagonal
+    // quadrants and the whole upper-right quadrant.  One barrier per step:
+    // lanes i < 32 of wave 0 rotate the blocks (i, i) and {i, i + 1}, which
+    // hold every entry the pair i of the next step needs (the third one comes
+    // from lane i + 1), and compute that rotation at once; 464 other threads
+    // rotate one block each.
+    // Z stays in registers: thread t owns rows t/32 + 16k (k < 4) in column t%32
+    // (zp) and in the column paired with it at the current step (zq); the
+    // pairing advances by one column per step, a rotation of zq across the 32
+    // lanes that share the rows.
+    const int zib = t & 31, zr0 = t >> 5;
+    double zp[4], zq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int iz = zr0 + 16 * k;
+      zp[k] = iz == zib ? 1.0 : 0.0;
+      zq[k] = iz == BW + zib ? 1.0 : 0.0;
+    }
+    const int zsrc = (l & 32) | ((l + 1) & 31);  // lane holding the next step's column
+    // storage of the block (a, b), a <= b: (a, b), (a, qb), (b, qa) [= (qa, b)], (min, max of qa, qb)
+    auto blk_off = [&](int a, int b, int qa, int qb, int* o) {
+      o[0] = a * P + b;
+      o[1] = a * P + qb;
+      o[2] = b * P + qa;
+      o[3] = qa <= qb ? qa * P + qb : qb * P + qa;
+    };
+    // this thread's block besides wave 0's: e < 448 -> distance 2 + e / 32, e < 464 -> distance 16
+    int oa = -1, ob = -1;
+    if (t >= NP2) {
+      const int e = t - NP2;
+      if (e < 448) {
+        const int x = e & (BW - 1), y = (x + 2 + (e >> 5)) & (BW - 1);
+        oa = min(x, y);
+        ob = max(x, y);
+      } else if (e < 464) {
+        oa = e - 448;
+        ob = oa + 16;
+      }
+    }
+    if (t < NP2) {  // step 0 from the Gram
+      double c, sn;
+      if (jg_rot(G[t * P + t], G[(BW + t) * P + BW + t], G[t * P + BW + t], tol, &c, &sn)) ++nrot;
+      hc[0][t] = c;
+      hs[0][t] = sn;
+    }
+    __syncthreads();
+    for (int st = 0; st < BW; ++st) {
+      const int cur = st & 1;
+      if (t < NP2) {
+        const int i = t, j = (t + 1) & (BW - 1);
+        const int qi = BW + ((i + st) & (BW - 1)), qj = BW + ((j + st) & (BW - 1));
+        const int a2 = min(i, j), b2 = max(i, j);
+        const int qa2 = a2 == i ? qi : qj, qb2 = a2 == i ? qj : qi;
+        int od[4], oe[4];
+        blk_off(i, i, qi, qi, od);
+        blk_off(a2, b2, qa2, qb2, oe);
+        const double ci = hc[cur][i], si = hs[cur][i], ca2 = hc[cur][a2], sa2 = hs[cur][a2];
+        const double cb2 = hc[cur][b2], sb2 = hs[cur][b2];
+        double gd[4] = {G[od[0]], G[od[1]], G[od[1]], G[od[3]]};
+        double ge[4] = {G[oe[0]], G[oe[1]], G[oe[2]], G[oe[3]]};
+        jg_rot_block(ci, si, ci, si, gd);
+        jg_rot_block(ca2, sa2, cb2, sb2, ge);
+        G[od[0]] = gd[0];
+        G[od[1]] = gd[1];
+        G[od[3]] = gd[3];
+        G[oe[0]] = ge[0];
+        G[oe[1]] = ge[1];
+        G[oe[2]] = ge[2];
+        G[oe[3]] = ge[3];
+        // pair i of step st + 1 is (i, qj): G[i][i], G[i][qj] (in the block {i, j}), G[qj][qj] from lane j
+        const double gqq = __shfl(gd[3], j);
+        const double gpq = a2 == i ? ge[1] : ge[2];
+        if (st + 1 < BW) {
+          double c, sn;
+          if (jg_rot(gd[0], gqq, gpq, tol, &c, &sn)) ++nrot;
+          hc[cur ^ 1][i] = c;
+          hs[cur ^ 1][i] = sn;
+        }
+      } else if (oa >= 0) {
+        const int qa = BW + ((oa + st) & (BW - 1)), qb = BW + ((ob + st) & (BW - 1));
+        int o[4];
+        blk_off(oa, ob, qa, qb, o);
+        double g[4] = {G[o[0]], G[o[1]], G[o[2]], G[o[3]]};
+        jg_rot_block(hc[cur][oa], hs[cur][oa], hc[cur][ob], hs[cur][ob], g);
+        G[o[0]] = g[0];
+        G[o[1]] = g[1];
+        G[o[2]] = g[2];
+        G[o[3]] = g[3];
+      }
+      const double cz = hc[cur][zib], sz = hs[cur][zib];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double x = zp[k], y = zq[k];
+        zp[k] = cz * x - sz * y;
+        zq[k] = sz * x + cz * y;
+      }
+      if (st + 1 < BW)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zq[k] = __shfl(zq[k], zsrc);
+      __syncthreads();
+    }
+    // Z back to LDS for the panel products (the last step paired zib with BW + (zib + BW - 1) % BW)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int iz = zr0 + 16 * k;
+      Z[iz * ZP + zib] = zp[k];
+      Z[iz * ZP + BW + ((zib + BW - 1) & (BW - 1))] = zq[k];
     }
   }
   __syncthreads();
