@@ -1219,11 +1219,14 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
     // (zp) and in the column paired with it at the current step (zq); the
     // pairing advances by one column per step, a rotation of zq across the 32
     // lanes that share the rows.
-    const int zib = t & 31, zr0 = t >> 5;
-    double zp[4], zq[4];
+    // Z and the other blocks live in waves 1..7 only, so wave 0 runs nothing but
+    // the step's critical path.  Z: half-wave h = t/32 - 2 (0..13) owns rows
+    // h + 14k (k < 5, rows < 64) in column t%32 and in its current partner.
+    const int zib = t & 31, zh = (t >> 5) - 2;
+    double zp[5], zq[5];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int iz = zr0 + 16 * k;
+    for (int k = 0; k < 5; ++k) {
+      const int iz = zh + 14 * k;
       zp[k] = iz == zib ? 1.0 : 0.0;
       zq[k] = iz == BW + zib ? 1.0 : 0.0;
     }
@@ -1235,24 +1238,42 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
       o[2] = b * P + qa;
       o[3] = qa <= qb ? qa * P + qb : qb * P + qa;
     };
-    // this thread's block besides wave 0's: e < 448 -> distance 2 + e / 32, e < 464 -> distance 16
-    int oa = -1, ob = -1;
-    if (t >= NP2) {
-      const int e = t - NP2;
-      if (e < 448) {
-        const int x = e & (BW - 1), y = (x + 2 + (e >> 5)) & (BW - 1);
-        oa = min(x, y);
-        ob = max(x, y);
-      } else if (e < 464) {
-        oa = e - 448;
-        ob = oa + 16;
+    // the blocks besides wave 0's, on waves 1..7 (448 threads; 16 take two):
+    // e < 448 -> distance 2 + e / 32, e < 464 -> distance 16
+    int oa[2] = {-1, -1}, ob[2] = {-1, -1};
+    if (t >= 64) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = (t - 64) + 448 * h;
+        if (e < 448) {
+          const int x = e & (BW - 1), y = (x + 2 + (e >> 5)) & (BW - 1);
+          oa[h] = min(x, y);
+          ob[h] = max(x, y);
+        } else if (e < 464) {
+          oa[h] = e - 448;
+          ob[h] = oa[h] + 16;
+        }
       }
     }
-    if (t < NP2) {  // step 0 from the Gram
-      double c, sn;
-      if (jg_rot(G[t * P + t], G[(BW + t) * P + BW + t], G[t * P + BW + t], tol, &c, &sn)) ++nrot;
-      hc[0][t] = c;
-      hs[0][t] = sn;
+    // lanes i < 32 of wave 0 carry their blocks (i, i) = {d0 d1; d1 d3} and
+    // (i, i + 1) = {e00 e01; e10 e11} (rows of pair i, columns of pair i + 1)
+    // from step to step in registers: after a step, pair i moves to the second-
+    // block column of pair i + 1, so the new blocks consist of the lane's own
+    // results, three results of lane i + 1, and one entry rotated by the owner
+    // of the block (i, i + 2), read back from LDS.
+    double d0 = 0.0, d1 = 0.0, d3 = 0.0, e00 = 0.0, e01 = 0.0, e10 = 0.0, e11 = 0.0, ci = 1.0, si = 0.0;
+    if (t < NP2) {  // step 0 from the Gram (still complete)
+      const int i = t, j = (i + 1) & (BW - 1), qi = BW + i, qj = BW + j;
+      d0 = G[i * P + i];
+      d1 = G[i * P + qi];
+      d3 = G[qi * P + qi];
+      e00 = G[i * P + j];
+      e01 = G[i * P + qj];
+      e10 = G[qi * P + j];
+      e11 = G[qi * P + qj];
+      if (jg_rot(d0, d3, d1, tol, &ci, &si)) ++nrot;
+      hc[0][t] = ci;
+      hs[0][t] = si;
     }
     __syncthreads();
     for (int st = 0; st < BW; ++st) {
@@ -1260,63 +1281,68 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
       if (t < NP2) {
         const int i = t, j = (t + 1) & (BW - 1);
         const int qi = BW + ((i + st) & (BW - 1)), qj = BW + ((j + st) & (BW - 1));
-        const int a2 = min(i, j), b2 = max(i, j);
-        const int qa2 = a2 == i ? qi : qj, qb2 = a2 == i ? qj : qi;
-        int od[4], oe[4];
-        blk_off(i, i, qi, qi, od);
-        blk_off(a2, b2, qa2, qb2, oe);
-        const double ci = hc[cur][i], si = hs[cur][i], ca2 = hc[cur][a2], sa2 = hs[cur][a2];
-        const double cb2 = hc[cur][b2], sb2 = hs[cur][b2];
-        double gd[4] = {G[od[0]], G[od[1]], G[od[1]], G[od[3]]};
-        double ge[4] = {G[oe[0]], G[oe[1]], G[oe[2]], G[oe[3]]};
+        if (st > 0) e01 = G[i * P + qj];  // rotated last step by the owner of the block (i, i + 2)
+        const double cj = __shfl(ci, j), sj = __shfl(si, j);
+        double gd[4] = {d0, d1, d1, d3};
+        double ge[4] = {e00, e01, e10, e11};
         jg_rot_block(ci, si, ci, si, gd);
-        jg_rot_block(ca2, sa2, cb2, sb2, ge);
-        G[od[0]] = gd[0];
-        G[od[1]] = gd[1];
-        G[od[3]] = gd[3];
-        G[oe[0]] = ge[0];
-        G[oe[1]] = ge[1];
-        G[oe[2]] = ge[2];
-        G[oe[3]] = ge[3];
-        // pair i of step st + 1 is (i, qj): G[i][i], G[i][qj] (in the block {i, j}), G[qj][qj] from lane j
-        const double gqq = __shfl(gd[3], j);
-        const double gpq = a2 == i ? ge[1] : ge[2];
+        jg_rot_block(ci, si, cj, sj, ge);
+        G[i * P + i] = gd[0];
+        G[i * P + qi] = gd[1];
+        G[qi * P + qi] = gd[3];
+        G[min(i, j) * P + max(i, j)] = ge[0];
+        G[i * P + qj] = ge[1];
+        G[j * P + qi] = ge[2];
+        G[min(qi, qj) * P + max(qi, qj)] = ge[3];
+        // step st + 1: pair i = (i, qj); blocks {i, qj} x {i, qj} and {i, qj} x {j, qk}
+        d0 = gd[0];
+        d1 = ge[1];
+        e00 = ge[0];
+        d3 = __shfl(gd[3], j);
+        e10 = __shfl(gd[1], j);
+        e11 = __shfl(ge[3], j);
         if (st + 1 < BW) {
-          double c, sn;
-          if (jg_rot(gd[0], gqq, gpq, tol, &c, &sn)) ++nrot;
-          hc[cur ^ 1][i] = c;
-          hs[cur ^ 1][i] = sn;
+          if (jg_rot(d0, d3, d1, tol, &ci, &si)) ++nrot;
+          hc[cur ^ 1][i] = ci;
+          hs[cur ^ 1][i] = si;
         }
-      } else if (oa >= 0) {
-        const int qa = BW + ((oa + st) & (BW - 1)), qb = BW + ((ob + st) & (BW - 1));
-        int o[4];
-        blk_off(oa, ob, qa, qb, o);
-        double g[4] = {G[o[0]], G[o[1]], G[o[2]], G[o[3]]};
-        jg_rot_block(hc[cur][oa], hs[cur][oa], hc[cur][ob], hs[cur][ob], g);
-        G[o[0]] = g[0];
-        G[o[1]] = g[1];
-        G[o[2]] = g[2];
-        G[o[3]] = g[3];
-      }
-      const double cz = hc[cur][zib], sz = hs[cur][zib];
+      } else if (t >= 64) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double x = zp[k], y = zq[k];
-        zp[k] = cz * x - sz * y;
-        zq[k] = sz * x + cz * y;
-      }
-      if (st + 1 < BW)
+        for (int h = 0; h < 2; ++h) {
+          if (oa[h] < 0) continue;
+          const int a = oa[h], b = ob[h];
+          const int qa = BW + ((a + st) & (BW - 1)), qb = BW + ((b + st) & (BW - 1));
+          int o[4];
+          blk_off(a, b, qa, qb, o);
+          double g[4] = {G[o[0]], G[o[1]], G[o[2]], G[o[3]]};
+          jg_rot_block(hc[cur][a], hs[cur][a], hc[cur][b], hs[cur][b], g);
+          G[o[0]] = g[0];
+          G[o[1]] = g[1];
+          G[o[2]] = g[2];
+          G[o[3]] = g[3];
+        }
+        const double cz = hc[cur][zib], sz = hs[cur][zib];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) zq[k] = __shfl(zq[k], zsrc);
+        for (int k = 0; k < 5; ++k) {
+          const double x = zp[k], y = zq[k];
+          zp[k] = cz * x - sz * y;
+          zq[k] = sz * x + cz * y;
+        }
+        if (st + 1 < BW)
+#pragma unroll
+          for (int k = 0; k < 5; ++k) zq[k] = __shfl(zq[k], zsrc);
+      }
       __syncthreads();
     }
     // Z back to LDS for the panel products (the last step paired zib with BW + (zib + BW - 1) % BW)
+    if (t >= 64)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int iz = zr0 + 16 * k;
-      Z[iz * ZP + zib] = zp[k];
-      Z[iz * ZP + BW + ((zib + BW - 1) & (BW - 1))] = zq[k];
-    }
+      for (int k = 0; k < 5; ++k) {
+        const int iz = zh + 14 * k;
+        if (iz >= P) continue;
+        Z[iz * ZP + zib] = zp[k];
+        Z[iz * ZP + BW + ((zib + BW - 1) & (BW - 1))] = zq[k];
+      }
   }
   __syncthreads();
   if (t < 64) {  // rotations counted by the lanes that chose them (wave 0)
