@@ -284,6 +284,32 @@ def main():
                       "ms_per_update_p50": round(_percentile(lat32, 50), 3), "states": 2,
                       "mode": "one update at a time, no grouping"}
 
+    # ---- factored (linear-cost) application, Algorithm 8: the gradient of each
+    # layer given as G_k A_k^T by the step's own batches (grouped over the layers)
+    Gks = [batches[0][2 * l + 1] for l in range(L)]
+    Aks = [batches[0][2 * l] for l in range(L)]
+    ws_f = kfb.Workspace(dev)
+    kfb.precondition_factored_batched(fg, fa, Gks, Aks, Ss, lam, lam, 0, ws_f)
+    torch.cuda.synchronize()
+    fac_ms = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        kfb.precondition_factored_batched(fg, fa, Gks, Aks, Ss, lam, lam, 0, ws_f)
+        e1.record()
+        torch.cuda.synchronize()
+        fac_ms.append(e0.elapsed_time(e1))
+    fac_call = _percentile(fac_ms, 50)
+    two_sided = sum(v["ms_per_call"] for k, v in stages.items() if k.startswith("pre_") and v)
+    fac_flops = L * (2 * 4.0 * N * D * n + 2.0 * D * D * n)
+    factored = {"ms_per_call": round(fac_call, 3), "layers": L,
+                "ms_per_layer": round(fac_call / L, 4),
+                "two_sided_ms_per_layer": round(two_sided / L, 4),
+                "speedup_vs_two_sided": round(two_sided / fac_call, 2),
+                "tflops": round(fac_flops / (fac_call * 1e-3) / 1e12, 2),
+                "s_write_gbs": round(L * 4.0 * D * D / (fac_call * 1e-3) / 1e9, 1),
+                "unit_work": "per layer 8*N*d*n (both sides) + 2*d^2*n (S = Y_G Y_A^T) flops; S written once (FP32)"}
+
     # ---- single mixed update latency (no grouping), for the latency columns
     lat1 = []
     for i in range(6):
@@ -323,6 +349,7 @@ def main():
         "serving": serving,
         "roofline": roofline,
         "stages": stages,
+        "factored_apply": factored,
         "status_events": sorted(set(status)),
         "autotune": {"jacobi_config": tune.config_name(best_bw) if best_bw else None,
                      "candidates_ms": {tune.config_name(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},

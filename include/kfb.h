@@ -129,6 +129,48 @@ int kfb_precondition_batched(int32_t count, kfb_state_t const* st_gamma, kfb_sta
                              const double* lam_gamma, const double* lam_a, uint32_t flags,
                              void* workspace, size_t ws_bytes, kfb_stream_t stream);
 
+/* Workspace bytes for kfb_precondition_factored on this pair of states and
+ * factor width n (0 if n < 1). */
+size_t kfb_precondition_factored_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a, int32_t n);
+
+/* Linear-cost application to a factored layer gradient (Section 5,
+ * Algorithm 8).  When the gradient is the product G_k A_k^T of the layer's
+ * per-sample output-gradient and activation matrices (the same matrices the
+ * factors are built from), each side's regularised inverse is applied to its
+ * own thin factor and the step is formed from the two results:
+ *   Y_G = (U_G D_G U_G^T + lam_gamma I)^{-1} G_k = U_G c_G U_G^T G_k + G_k / lam_gamma,
+ *   Y_A = (U_A D_A U_A^T + lam_a I)^{-1} A_k     = U_A c_A U_A^T A_k + A_k / lam_a,
+ *   S   = Y_G Y_A^T,        c = diag(1/(D + lam) - 1/lam),
+ * which equals kfb_precondition with G = G_k A_k^T, at O(N d n) cost per side
+ * instead of O(N d_out d_in), plus the d_out x d_in x n product for S.
+ * G_k: d_out x n and A_k: d_in x n, column-major (element (i, j) at
+ * X[i + j*ld], ld >= the side's d: a PyTorch [n, d] row-major tensor), in the
+ * element type of the state's batches (FP64: double, FP32: float, mixed:
+ * bf16); n >= 1.  S: row-major d_out x d_in, lds >= d_in (double in the FP64
+ * form, float otherwise); it may not alias G_k or A_k.  lam > 0 absolute,
+ * flags as for kfb_precondition.  In the mixed form the per-side products run
+ * on BF16 MFMA with U and the coefficients split into two BF16 terms, the
+ * product for S on single-term BF16 MFMA, all with FP32 accumulation.
+ * Errors: KFB_EINVAL (null pointer, n < 1, ld too small, lam <= 0),
+ * KFB_ESTATE (precision or handle mismatch), KFB_EEMPTY (a state without
+ * modes), KFB_EWORKSPACE. */
+int kfb_precondition_factored(kfb_state_t st_gamma, kfb_state_t st_a, const void* G_k, int64_t ldgk,
+                              const void* A_k, int64_t ldak, int32_t n, void* S, int64_t lds,
+                              double lam_gamma, double lam_a, uint32_t flags, void* workspace,
+                              size_t ws_bytes, kfb_stream_t stream);
+
+/* Grouped form: `count` layers sharing (d_out, d_in, modes per side, n,
+ * precision, flags); lambdas per layer.  Results equal the single calls bit
+ * for bit. */
+size_t kfb_precondition_factored_batched_workspace_bytes(int32_t count, kfb_state_t const* st_gamma,
+                                                         kfb_state_t const* st_a, int32_t n);
+int kfb_precondition_factored_batched(int32_t count, kfb_state_t const* st_gamma,
+                                      kfb_state_t const* st_a, const void* const* G_k, int64_t ldgk,
+                                      const void* const* A_k, int64_t ldak, int32_t n, void* const* S,
+                                      int64_t lds, const double* lam_gamma, const double* lam_a,
+                                      uint32_t flags, void* workspace, size_t ws_bytes,
+                                      kfb_stream_t stream);
+
 /* Host-side metadata: modes held, updates applied, sizes. Any pointer may be NULL. */
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,
                    int32_t* n_max, int32_t* prec);

@@ -372,7 +372,7 @@ void make_pre_plan(int64_t dG, int64_t dA, int64_t lduG, int64_t lduA, int NG, i
   p->oT3 = take((size_t)NG * NA * sizeof(TA));
   p->oPart = take((size_t)ks * NG * NA * sizeof(TA));
   p->ocG = take((size_t)2 * NG * sizeof(TA));
-  p->ocA = take((size_t)2 * NA * sizeof(TA) + 16);
+  p->ocA = take((size_t)2 * NA * sizeof(TA) + 32);  // + the three doubles of precond_coefs
   p->oBeta = ((p->ocA + (int64_t)2 * NA * (int64_t)sizeof(TA)) + 7) & ~int64_t(7);
   p->per_problem = o;
 }
@@ -435,6 +435,87 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g5.C = op(P_S, 0, p.lds, 1);
   g5.m = (int)dG; g5.n = (int)dA; g5.k = NG + NA; g5.aligned16 = p.aligned16;
   KFB_TRY((mm<PR, 0, TU, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
+  return KFB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Factored preconditioner (Algorithm 8): per-side inverse applied to the thin
+// factors G_k (dG x n) and A_k (dA x n), then S = Y_G Y_A^T.
+// ---------------------------------------------------------------------------
+struct FacPlan {
+  int64_t dG, dA, lduG, lduA, ldgk, ldak, lds;
+  int NG, NA, n, ksG, ksA, aligned16;
+  int64_t ocG, ocA, oBeta, oTG, oTA, oPart, oYG, oYA;
+  size_t per_problem;
+};
+
+template <int PR>
+void make_fac_plan(int64_t dG, int64_t dA, int64_t lduG, int64_t lduA, int NG, int NA, int n, FacPlan* p) {
+  typedef typename Ty<PR>::Acc TA;
+  p->dG = dG; p->dA = dA; p->lduG = lduG; p->lduA = lduA; p->NG = NG; p->NA = NA; p->n = n;
+  auto ks_for = [&](int m, int nn, int64_t k) {  // the problem's own shape only
+    const int tiles = ((m + 63) / 64) * ((nn + 63) / 64);
+    int ks = 1;
+    while (tiles * ks < 512 && (k / (ks * 2)) >= 256) ks *= 2;
+    return ks;
+  };
+  p->ksG = ks_for(NG, n, dG);
+  p->ksA = ks_for(NA, n, dA);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at_ = o; o = align256(o + bytes); return (int64_t)at_; };
+  p->ocG = take((size_t)2 * NG * sizeof(TA));
+  p->ocA = take((size_t)2 * NA * sizeof(TA) + 32);
+  p->oBeta = ((p->ocA + (int64_t)2 * NA * (int64_t)sizeof(TA)) + 7) & ~int64_t(7);
+  p->oTG = take((size_t)NG * n * sizeof(TA));
+  p->oTA = take((size_t)NA * n * sizeof(TA));
+  const size_t pg = (size_t)p->ksG * NG * n, pa = (size_t)p->ksA * NA * n;
+  p->oPart = take((pg > pa ? pg : pa) * sizeof(TA));
+  p->oYG = take((size_t)dG * n * sizeof(TA));
+  p->oYA = take((size_t)dA * n * sizeof(TA));
+  p->per_problem = o;
+}
+
+template <int PR>
+int run_fac(const Rec* drecs, int nrec, const FacPlan& p, uint32_t flags, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::M TM; typedef typename T::D TD; typedef typename T::Acc TA;
+  typedef TA TGrad;  // S element type
+  const int n = p.n;
+  {
+    StageTimer st_side("fac_sides", s, 7 + (p.ksG > 1 ? 1 : 0) + (p.ksA > 1 ? 1 : 0));
+    CoefArgs ca;
+    ca.kG = p.NG; ca.kA = p.NA; ca.off_cG = p.ocG; ca.off_cA = p.ocA; ca.flags = flags;
+    KFB_TRY((precond_coefs<TD, TA>(drecs, nrec, ca, s)));
+    for (int side = 0; side < 2; ++side) {
+      const int slotU = side ? PU_A : PU_G, slotX = side ? P_AK : P_G;
+      const int64_t d = side ? p.dA : p.dG, ldu = side ? p.lduA : p.lduG, ldx = side ? p.ldak : p.ldgk;
+      const int N = side ? p.NA : p.NG, ks = side ? p.ksA : p.ksG;
+      const int64_t oT = side ? p.oTA : p.oTG, oY = side ? p.oYA : p.oYG;
+      const int64_t oc = side ? p.ocA : p.ocG;
+      // T = U^T X   (N x n)
+      GemmArgs g;
+      g.A = op(slotU, 0, ldu, 1); g.B = op(slotX, 0, 1, ldx); g.C = op(PWS, oT, 1, N);
+      g.m = N; g.n = n; g.k = (int)d; g.ksplit = ks; g.Part = op(PWS, p.oPart, 1, N);
+      KFB_TRY((mm<PR, 1, TU, TM, TA, TA, TA>(drecs, nrec, g, s)));
+      // T <- diag(c) T
+      ScaleArgs sc;
+      sc.m = N; sc.n = n; sc.X = op(PWS, oT, 1, N); sc.row_slot = PWS; sc.row_off = oc + (int64_t)N * sizeof(TA);
+      sc.col_slot = -1; sc.col_off = 0; sc.extra_mode = 0;
+      KFB_TRY((scale2d<TA, TA>(drecs, nrec, sc, s)));
+      // Y = X / lam + U T
+      GemmArgs y;
+      y.A = op(slotU, 0, 1, ldu); y.B = op(PWS, oT, 1, N); y.C0 = op(slotX, 0, 1, ldx);
+      y.beta_slot = PWS; y.beta_off = p.oBeta + (side ? 16 : 8);
+      y.C = op(PWS, oY, 1, d); y.m = (int)d; y.n = n; y.k = N;
+      KFB_TRY((mm<PR, 1, TU, TA, TA, TM, TA>(drecs, nrec, y, s)));
+    }
+  }
+  StageTimer st_s("fac_S", s, 1);
+  // S = Y_G Y_A^T   (dG x dA row-major, inner dimension n)
+  GemmArgs g5;
+  g5.A = op(PWS, p.oYG, 1, p.dG); g5.B = op(PWS, p.oYA, p.dA, 1); g5.C = op(P_S, 0, p.lds, 1);
+  g5.m = (int)p.dG; g5.n = (int)p.dA; g5.k = n; g5.aligned16 = p.aligned16;
+  KFB_TRY((mm<PR, 0, TA, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
   return KFB_OK;
 }
 
@@ -568,6 +649,78 @@ int dispatch_precond(int count, kfb_state_t const* stG, kfb_state_t const* stA, 
   return run_precond<KFB_BF16_MIXED>(dev, count, p, flags, s);
 }
 
+int dispatch_fac(int count, kfb_state_t const* stG, kfb_state_t const* stA, const void* const* Gk, int64_t ldgk,
+                 const void* const* Ak, int64_t ldak, int n, void* const* S, int64_t lds, const double* lamG,
+                 const double* lamA, uint32_t flags, void* workspace, size_t ws_bytes, hipStream_t s,
+                 size_t* need_only) {
+  if (count <= 0 || !stG || !stA || n < 1) return KFB_EINVAL;
+  kfb_state_t g0 = stG[0], a0 = stA[0];
+  if (!g0 || !a0) return KFB_EINVAL;
+  const int prec = g0->prec;
+  const int NG = pre_modes(g0, flags), NA = pre_modes(a0, flags);
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t g = stG[i], a = stA[i];
+    if (!g || !a) return KFB_EINVAL;
+    if (g == a) return KFB_ESTATE;
+    if (g->prec != prec || a->prec != prec || g->d != g0->d || a->d != a0->d ||
+        pre_modes(g, flags) != NG || pre_modes(a, flags) != NA || g->ldu != g0->ldu || a->ldu != a0->ldu)
+      return KFB_ESTATE;
+  }
+  if (NG <= 0 || NA <= 0) return KFB_EEMPTY;
+  if (ldgk < g0->d || ldak < a0->d || lds < a0->d) return KFB_EINVAL;
+  FacPlan p;
+  if (prec == KFB_FP64) make_fac_plan<KFB_FP64>(g0->d, a0->d, g0->ldu, a0->ldu, NG, NA, n, &p);
+  else if (prec == KFB_FP32) make_fac_plan<KFB_FP32>(g0->d, a0->d, g0->ldu, a0->ldu, NG, NA, n, &p);
+  else make_fac_plan<KFB_BF16_MIXED>(g0->d, a0->d, g0->ldu, a0->ldu, NG, NA, n, &p);
+  p.ldgk = ldgk; p.ldak = ldak; p.lds = lds;
+  const size_t head = align256(sizeof(Rec) * (size_t)count);
+  const size_t need = head + p.per_problem * (size_t)count;
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!Gk || !Ak || !S || !workspace || !lamG || !lamA) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  // Y_G and Y_A columns start 16-byte aligned when d_out and d_in are multiples of 4
+  p.aligned16 = (lds % 4 == 0) && (g0->d % 4 == 0) && (a0->d % 4 == 0);
+  Rec* host = (Rec*)malloc(sizeof(Rec) * (size_t)count);
+  if (!host) return KFB_EINVAL;
+  const size_t selem = prec == KFB_FP64 ? 8 : 4;
+  const size_t sbytes = (size_t)((g0->d - 1) * lds + a0->d) * selem;
+  for (int i = 0; i < count; ++i) {
+    if (!Gk[i] || !Ak[i] || !S[i] || !(lamG[i] > 0.0) || !(lamA[i] > 0.0)) { free(host); return KFB_EINVAL; }
+    const char* sb = (const char*)S[i];
+    auto overlaps = [&](const void* x, size_t xb) {
+      const char* xc = (const char*)x;
+      return sb < xc + xb && xc < sb + sbytes;
+    };
+    const size_t mel = m_elem(prec);
+    if (overlaps(Gk[i], (size_t)((n - 1) * ldgk + g0->d) * mel) || overlaps(Ak[i], (size_t)((n - 1) * ldak + a0->d) * mel)) {
+      free(host);
+      return KFB_EINVAL;
+    }
+    if (((uintptr_t)S[i]) & 15) p.aligned16 = 0;
+    kfb_state_t g = stG[i], a = stA[i];
+    Rec* rc = &host[i];
+    memset(rc, 0, sizeof(Rec));
+    rc->p[PU_G] = g->buf + g->off_U[g->front];
+    rc->p[PD_G] = g->buf + g->off_D[g->front];
+    rc->p[PU_A] = a->buf + a->off_U[a->front];
+    rc->p[PD_A] = a->buf + a->off_D[a->front];
+    rc->p[P_G] = const_cast<void*>(Gk[i]);
+    rc->p[P_AK] = const_cast<void*>(Ak[i]);
+    rc->p[P_S] = S[i];
+    rc->p[PWS] = (char*)workspace + head + p.per_problem * (size_t)i;
+    rc->s[0] = lamG[i];
+    rc->s[1] = lamA[i];
+  }
+  Rec* dev = (Rec*)workspace;
+  hipError_t he = upload_recs(host, count, dev, s);
+  free(host);
+  if (he != hipSuccess) return KFB_EHIP;
+  if (prec == KFB_FP64) return run_fac<KFB_FP64>(dev, count, p, flags, s);
+  if (prec == KFB_FP32) return run_fac<KFB_FP32>(dev, count, p, flags, s);
+  return run_fac<KFB_BF16_MIXED>(dev, count, p, flags, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -679,6 +832,44 @@ int kfb_precondition_batched(int32_t count, kfb_state_t const* st_gamma, kfb_sta
                              void* workspace, size_t ws_bytes, kfb_stream_t stream) {
   return dispatch_precond(count, st_gamma, st_a, G, ldg, S, lds, lam_gamma, lam_a, flags, workspace,
                           ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_precondition_factored_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a, int32_t n) {
+  return kfb_precondition_factored_batched_workspace_bytes(1, &st_gamma, &st_a, n);
+}
+
+int kfb_precondition_factored(kfb_state_t st_gamma, kfb_state_t st_a, const void* G_k, int64_t ldgk,
+                              const void* A_k, int64_t ldak, int32_t n, void* S, int64_t lds,
+                              double lam_gamma, double lam_a, uint32_t flags, void* workspace,
+                              size_t ws_bytes, kfb_stream_t stream) {
+  const void* Gs[1] = {G_k};
+  const void* As[1] = {A_k};
+  void* Ss[1] = {S};
+  return dispatch_fac(1, &st_gamma, &st_a, Gs, ldgk, As, ldak, n, Ss, lds, &lam_gamma, &lam_a, flags,
+                      workspace, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_precondition_factored_batched_workspace_bytes(int32_t count, kfb_state_t const* st_gamma,
+                                                         kfb_state_t const* st_a, int32_t n) {
+  size_t need = 0;
+  if (count <= 0 || !st_gamma || !st_a || !st_gamma[0] || !st_a[0]) return 0;
+  double* l = (double*)malloc(sizeof(double) * (size_t)count);
+  if (!l) return 0;
+  for (int i = 0; i < count; ++i) l[i] = 1.0;
+  const int rc = dispatch_fac(count, st_gamma, st_a, nullptr, st_gamma[0]->d, nullptr, st_a[0]->d, n, nullptr,
+                              st_a[0]->d, l, l, 0, nullptr, 0, nullptr, &need);
+  free(l);
+  return rc == KFB_OK ? need : 0;
+}
+
+int kfb_precondition_factored_batched(int32_t count, kfb_state_t const* st_gamma,
+                                      kfb_state_t const* st_a, const void* const* G_k, int64_t ldgk,
+                                      const void* const* A_k, int64_t ldak, int32_t n, void* const* S,
+                                      int64_t lds, const double* lam_gamma, const double* lam_a,
+                                      uint32_t flags, void* workspace, size_t ws_bytes,
+                                      kfb_stream_t stream) {
+  return dispatch_fac(count, st_gamma, st_a, G_k, ldgk, A_k, ldak, n, S, lds, lam_gamma, lam_a, flags,
+                      workspace, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,

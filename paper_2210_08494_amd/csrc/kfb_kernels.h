@@ -83,6 +83,10 @@ template <typename TCore, typename TW, typename TD>
 hipError_t finalize_core(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s);
 
 // ---- preconditioner helpers -------------------------------------------------
+// Per side: c_i = 1/(D_i + lam) - 1/lam for the modes used, stored as
+// [c_G / lam_A..., c_G...] at off_cG and [c_A / lam_G..., c_A...] at off_cA
+// (TAcc), followed (8-byte aligned) by three doubles: 1/(lam_G lam_A),
+// 1/lam_G, 1/lam_A (lam after spectrum continuation when that flag is set).
 struct CoefArgs {
   int kG, kA;              // modes used per side
   int64_t off_cG, off_cA;  // coefficient vectors (TAcc) in PWS

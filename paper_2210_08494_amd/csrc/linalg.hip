@@ -1828,6 +1828,8 @@ __global__ __launch_bounds__(256) void precond_coefs_kernel(const Rec* __restric
   if (threadIdx.x == 0) {
     const int64_t boff = ((a.off_cA + (int64_t)2 * a.kA * (int64_t)sizeof(TAcc)) + 7) & ~int64_t(7);
     *at<double>(rec, PWS, boff) = 1.0 / (lG * lA);
+    *at<double>(rec, PWS, boff + 8) = 1.0 / lG;
+    *at<double>(rec, PWS, boff + 16) = 1.0 / lA;
   }
 }
 

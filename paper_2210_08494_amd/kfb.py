@@ -40,6 +40,15 @@ _SIGS = {
                                                 ctypes.POINTER(_vp), _i64, ctypes.POINTER(_vp), _i64,
                                                 ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _u32, _vp, _sz,
                                                 _vp]),
+    "kfb_precondition_factored_workspace_bytes": (_sz, [_vp, _vp, _i32]),
+    "kfb_precondition_factored": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, _vp, _i64, _dbl, _dbl,
+                                                 _u32, _vp, _sz, _vp]),
+    "kfb_precondition_factored_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                                _i32]),
+    "kfb_precondition_factored_batched": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                         ctypes.POINTER(_vp), _i64, ctypes.POINTER(_vp), _i64,
+                                                         _i32, ctypes.POINTER(_vp), _i64, ctypes.POINTER(_dbl),
+                                                         ctypes.POINTER(_dbl), _u32, _vp, _sz, _vp]),
     "kfb_state_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
@@ -253,6 +262,51 @@ def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):
     _check(lib.kfb_precondition_batched(cnt, hg, ha, gp, int(Gs[0].stride(0)), sp, int(Ss[0].stride(0)), lg, la,
                                         int(flags), _ptr(w), int(w.numel()), _stream()),
            "kfb_precondition_batched")
+
+
+def _factor_arg(X, f: "Factor"):
+    assert X.is_cuda and X.dim() == 2 and X.shape[1] == f.d and X.dtype == f.mdtype and X.stride(1) == 1
+    return int(X.shape[0]), int(X.stride(0))
+
+
+def precondition_factored(fg: Factor, fa: Factor, Gk, Ak, S, lam_g: float, lam_a: float, flags: int = 0,
+                          ws: Workspace | None = None):
+    """S = [(Gamma~ + lam_g I)^{-1} G_k] [(A~ + lam_a I)^{-1} A_k]^T (Algorithm 8).
+
+    Gk: (n, d_out) and Ak: (n, d_in) device tensors (= d x n column-major), the
+    state's batch dtype; S row-major (d_out, d_in)."""
+    lib = load()
+    n, ldgk = _factor_arg(Gk, fg)
+    n2, ldak = _factor_arg(Ak, fa)
+    assert n == n2 and S.shape == (fg.d, fa.d) and S.stride(1) == 1
+    need = lib.kfb_precondition_factored_workspace_bytes(fg.handle, fa.handle, n)
+    if need == 0:
+        raise KfbError("kfb_precondition_factored_workspace_bytes rejected the states")
+    w = (ws or fg.ws).get(need)
+    _check(lib.kfb_precondition_factored(fg.handle, fa.handle, _ptr(Gk), ldgk, _ptr(Ak), ldak, n, _ptr(S),
+                                         int(S.stride(0)), float(lam_g), float(lam_a), int(flags), _ptr(w),
+                                         int(w.numel()), _stream()), "kfb_precondition_factored")
+
+
+def precondition_factored_batched(fgs, fas, Gks, Aks, Ss, lam_g, lam_a, flags, ws: Workspace):
+    lib = load()
+    cnt = len(fgs)
+    n, ldgk = _factor_arg(Gks[0], fgs[0])
+    _, ldak = _factor_arg(Aks[0], fas[0])
+    hg = (_vp * cnt)(*[f.handle.value for f in fgs])
+    ha = (_vp * cnt)(*[f.handle.value for f in fas])
+    gp = (_vp * cnt)(*[g.data_ptr() for g in Gks])
+    ap = (_vp * cnt)(*[a.data_ptr() for a in Aks])
+    sp = (_vp * cnt)(*[s.data_ptr() for s in Ss])
+    lg = (_dbl * cnt)(*[float(x) for x in lam_g])
+    la = (_dbl * cnt)(*[float(x) for x in lam_a])
+    need = lib.kfb_precondition_factored_batched_workspace_bytes(cnt, hg, ha, n)
+    if need == 0:
+        raise KfbError("kfb_precondition_factored_batched_workspace_bytes rejected the bucket")
+    w = ws.get(need)
+    _check(lib.kfb_precondition_factored_batched(cnt, hg, ha, gp, ldgk, ap, ldak, n, sp, int(Ss[0].stride(0)),
+                                                 lg, la, int(flags), _ptr(w), int(w.numel()), _stream()),
+           "kfb_precondition_factored_batched")
 
 
 def profile_enable(on: bool = True):
