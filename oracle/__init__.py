@@ -19,6 +19,9 @@ precond   The regularised inverse applied on both sides of a layer gradient:
           dense Cholesky solves (definition), the low-rank spectral form of
           Algorithm 1 (its inverse-application lines), the factored form of
           Algorithm 8, and spectrum continuation (Section 3.5).
+rsvd      B-R-KFAC (Algorithm 5): the dense EA factor and the randomized SVD
+          (range finder with re-orthonormalised power iterations) whose
+          rank-r result overwrites a factor's representation.
 metrics   Basis-invariant comparisons (reconstruction, eigenvalues,
           orthonormality, preconditioned-gradient error).
 """
@@ -26,4 +29,5 @@ from .bprocess import DenseFactor, truncate_rank, sorted_eigh  # noqa: F401
 from .brand import BrandFactor, symmetric_brand  # noqa: F401
 from .precond import (precondition_dense, lowrank_inverse_apply, precondition_lowrank,  # noqa: F401
                       precondition_factored, spectrum_continuation)
+from .rsvd import ea_update, range_basis, rsvd, rsvd_overwrite  # noqa: F401
 from .metrics import e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S  # noqa: F401

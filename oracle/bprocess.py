@@ -79,6 +79,12 @@ class DenseFactor:
             self.kept = min(r_eff + n, d)
         self.k += 1
 
+    def overwrite(self, U: np.ndarray, D: np.ndarray) -> None:
+        """B-R-KFAC (Algorithm 5): the current iterate is replaced by U diag(D) U^T
+        (the RSVD of the previous EA factor) in place of the usual truncation."""
+        self.X = (U * D[None, :]) @ U.T
+        self.kept = U.shape[1]
+
     def modes(self):
         """(V, lam): the kept eigenpairs of X_k, eigenvalues descending, clipped >= 0."""
         lam, V = sorted_eigh(self.X)

@@ -58,6 +58,12 @@ class BrandFactor:
         self.D = np.zeros(0)
         self.k = 0
 
+    def overwrite(self, U: np.ndarray, D: np.ndarray) -> None:
+        """B-R-KFAC (Algorithm 5): replace the representation by (U, D) (an RSVD of
+        the previous EA factor); the next update truncates it as usual."""
+        self.U = np.asarray(U, dtype=np.float64).copy()
+        self.D = np.asarray(D, dtype=np.float64).copy()
+
     def update(self, M: np.ndarray) -> None:
         """Algorithm 4 for one factor; M: (d, n) float64 columns are samples."""
         M = np.asarray(M, dtype=np.float64)

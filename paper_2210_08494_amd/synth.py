@@ -15,6 +15,8 @@ fully-connected layer fed batches of n samples):
 * output grads g = Z' . diag(k^-beta), Z' ~ N(0,1)^{n x d}, beta = 0.7, no ReLU.
   The K-factor input is M_G = g^T.
 * layer gradient G ~ N(0,1)^{d_out x d_in}, a fresh draw every step.
+* the Gaussian test matrix of a randomized SVD, iid N(0,1), d x l (stream 4);
+  the method's random draws are inputs, so both sides get the same ones.
 
 Every array is generated in float64 by numpy's PCG64, seeded from
 SeedSequence(entropy=20221015, spawn_key=(config_id, step, stream)), and
@@ -74,6 +76,17 @@ def batch_for(config_id: int, step: int, side: str, n: int, d: int, *, bias: boo
 
 def grad_for(config_id: int, step: int, d_out: int, d_in: int) -> np.ndarray:
     return gradient(rng_for(config_id, step, STREAM_GRAD), d_out, d_in)
+
+
+STREAM_SKETCH = 4
+
+
+def sketch_for(config_id: int, step: int, d: int, l: int) -> np.ndarray:
+    """The Gaussian test matrix of a randomized SVD: (l, d) iid N(0,1) rows.
+
+    As a d x l column-major matrix (the layout the C-ABI takes) it is the
+    row-major numpy array of shape (l, d)."""
+    return rng_for(config_id, step, STREAM_SKETCH).standard_normal((l, d))
 
 
 def to_bf16_values(x: np.ndarray) -> np.ndarray:

@@ -321,3 +321,128 @@ def test_generator_recipe():
     x = np.array([1.0, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, -3.14159])
     y = synth.to_bf16_values(x)
     assert y[0] == 1.0 and y[1] == 1.0 and y[2] == 1.0 + 2 ** -7 and abs(y[3] + 3.140625) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# B-R-KFAC (Algorithm 5): the dense EA factor and its randomized SVD
+# ----------------------------------------------------------------------------
+from oracle import ea_update, range_basis, rsvd, rsvd_overwrite, sorted_eigh  # noqa: E402
+
+
+def _psd(d, rank, seed, decay=1.0):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((d, rank)) * (np.arange(1, rank + 1) ** -decay)[None, :]
+    return G @ G.T
+
+
+def test_ea_update_closed_form():
+    # E_k = sum_i kappa(i) rho^(k-i) w_i M_i M_i^T with w_0 = 1/n, w_i = (1 - rho)/n
+    d, n, rho = 12, 3, 0.8
+    Ms = _batches(d, n, 5, seed=31)
+    E = None
+    for M in Ms:
+        E = ea_update(E, M, rho)
+    ref = sum((rho ** (4 - i)) * ((1.0 if i == 0 else (1 - rho)) / n) * (M @ M.T) for i, M in enumerate(Ms))
+    assert np.linalg.norm(E - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_rsvd_exact_on_low_rank(q):
+    # a factor of rank <= l is recovered exactly: the leading r eigenpairs (library eigh)
+    d, rank, r, p = 50, 14, 9, 6
+    X = _psd(d, rank, seed=32)
+    Om = np.random.default_rng(33).standard_normal((d, r + p))
+    U, s = rsvd_overwrite(X, Om, r, q)
+    lam, V = sorted_eigh(X)
+    assert np.max(np.abs(s - lam[:r])) <= 1e-12 * lam[0]
+    assert e_rec_lowrank(U, s, V[:, :r], lam[:r]) <= 1e-12
+    assert e_orth(U) <= 1e-13
+
+
+def test_range_basis_spans_power_sketch():
+    # q power iterations: span(Q) = span(X^(2q+1) Omega) (explicit matrix power)
+    d, l, q = 30, 6, 2
+    rng = np.random.default_rng(34)
+    lam = 1.0 + 0.3 * np.arange(d)[::-1] / d      # mild decay keeps X^5 Omega well conditioned
+    V, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    X = (V * lam) @ V.T
+    Om = rng.standard_normal((d, l))
+    Q = range_basis(X, Om, q)
+    Qr, _ = np.linalg.qr(np.linalg.matrix_power(X, 2 * q + 1) @ Om)
+    assert np.linalg.norm(Q @ Q.T - Qr @ Qr.T) <= 1e-10
+    # and a dropped power iteration gives a different span
+    Q1 = range_basis(X, Om, q - 1)
+    assert np.linalg.norm(Q1 @ Q1.T - Qr @ Qr.T) > 1e-6
+
+
+def test_rsvd_reconstructs_projection():
+    # with r = l the RSVD factors reproduce Q Q^T X exactly (B = Q^T X, SVD of B)
+    d, l, q = 40, 10, 1
+    X = _psd(d, d, seed=35)
+    Om = np.random.default_rng(36).standard_normal((d, l))
+    U, s, Vt = rsvd(X, Om, l, q)
+    Q = range_basis(X, Om, q)
+    assert np.linalg.norm((U * s) @ Vt - Q @ (Q.T @ X)) <= 1e-12 * np.linalg.norm(X)
+
+
+def test_rsvd_error_within_range_finder_bound():
+    # Halko, Martinsson & Tropp (2011), Corollary 10.10 and Section 9.4: with q power
+    # iterations E||X - Q Q^T X|| <= [(1 + sqrt(r/(p-1))) sigma_{r+1}^(2q+1)
+    #   + e sqrt(l)/p (sum_{j>r} sigma_j^(2(2q+1)))^(1/2)]^(1/(2q+1)), and truncating
+    # to rank r adds at most sigma_{r+1}.  A fixed seed, with a factor 3 of slack.
+    d, r, p = 300, 20, 16
+    X = _psd(d, d, seed=37, decay=1.0)
+    sig = np.linalg.svd(X, compute_uv=False)
+    Om = np.random.default_rng(38).standard_normal((d, r + p))
+    for q in (0, 1, 2):
+        U, s = rsvd_overwrite(X, Om, r, q)
+        e = np.linalg.norm(X - (U * s) @ U.T, 2)
+        k = 2 * q + 1
+        bound = ((1 + np.sqrt(r / (p - 1))) * sig[r] ** k
+                 + np.e * np.sqrt(r + p) / p * np.sqrt(np.sum(sig[r:] ** (2 * k)))) ** (1.0 / k)
+        assert e <= sig[r] + 3 * bound
+        assert e >= sig[r] * (1 - 1e-12)     # never better than the optimal truncation
+
+
+def test_overwrite_prop_3_2_and_3_1():
+    # When the RSVD is exact (rank E_i <= l), the overwrite is the optimal rank-r
+    # truncation of E_i: the next error is rho (E_i - M~_{R,i,r}) (Proposition 3.2)
+    # and no larger than the pure B-process error (Proposition 3.1).
+    d, r, n, rho, i = 40, 6, 3, 0.9, 5
+    Ms = _batches(d, n, i + 2, seed=39, decay=0.5)
+    pure, over = DenseFactor(d, r, rho), DenseFactor(d, r, rho)
+    E = None
+    for k in range(i + 1):
+        pure.update(Ms[k])
+        over.update(Ms[k])
+        E = ea_update(E, Ms[k], rho)
+    assert np.linalg.matrix_rank(E) <= (i + 1) * n
+    Om = np.random.default_rng(40).standard_normal((d, (i + 1) * n + 2))
+    U, s = rsvd_overwrite(E, Om, r, 1)
+    MR = (U * s) @ U.T
+    assert np.linalg.norm(MR - truncate_rank(E, r)) <= 1e-10 * np.linalg.norm(E)
+    over.overwrite(U, s)
+    pure.update(Ms[i + 1])
+    over.update(Ms[i + 1])
+    E1 = ea_update(E, Ms[i + 1], rho)
+    assert np.linalg.norm((E1 - over.X) - rho * (E - MR)) <= 1e-12 * np.linalg.norm(E1)
+    for ord_ in ("fro", 2):
+        assert np.linalg.norm(E1 - pure.X, ord_) >= np.linalg.norm(E1 - over.X, ord_) * (1 - 1e-12)
+
+
+def test_structured_overwrite_matches_dense():
+    # Oracle-B with an overwrite tracks Oracle-D with the same overwrite
+    d, r, n, rho = 48, 6, 4, 0.9
+    Ms = _batches(d, n, 6, seed=41, decay=0.5)
+    b, D = BrandFactor(d, r, rho), DenseFactor(d, r, rho)
+    E = None
+    for k, M in enumerate(Ms):
+        if k == 3:
+            Om = np.random.default_rng(42).standard_normal((d, r + 4))
+            U, s = rsvd_overwrite(E, Om, r, 2)
+            b.overwrite(U, s)
+            D.overwrite(U, s)
+        b.update(M)
+        D.update(M)
+        E = ea_update(E, M, rho)
+        assert e_rec_dense(b.U, b.D, D.X) <= 1e-12
