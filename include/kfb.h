@@ -171,6 +171,46 @@ int kfb_precondition_factored_batched(int32_t count, kfb_state_t const* st_gamma
                                       uint32_t flags, void* workspace, size_t ws_bytes,
                                       kfb_stream_t stream);
 
+/* ---- B-R-KFAC (Section 3.4, Algorithm 5) ------------------------------------
+ * Every T_RSVD steps B-R-KFAC replaces a factor's representation by a
+ * randomized SVD of the dense EA factor of the previous step, in place of the
+ * usual truncation, and then performs the B-update as usual.  The dense factor
+ * X (d x d, column-major, ld ldx >= d; double in the FP64 form, float
+ * otherwise) is caller memory, kept beside the state.
+ *
+ * kfb_dense_bytes: bytes of such a factor (0 on invalid sizes).
+ * kfb_dense_update: one step of the EA definition (Section 2.1) for the
+ * state's rho and batch convention:  X <- rho X + (1 - rho)/n M M^T, or, with
+ * first != 0, X <- M M^T / n (X is not read).  M as for kfb_brand_update.
+ * The workspace (kfb_dense_update_workspace_bytes, 256-byte aligned) holds the
+ * call's record.  Mixed form: BF16 M on MFMA with FP32 accumulation.  X may not
+ * overlap M.  Errors: KFB_EINVAL, KFB_EWORKSPACE. */
+size_t kfb_dense_bytes(int64_t d, int64_t ldx, int32_t prec);
+size_t kfb_dense_update_workspace_bytes(void);
+int kfb_dense_update(kfb_state_t st, void* X, int64_t ldx, const void* M, int64_t ldm, int32_t n,
+                     int32_t first, void* workspace, size_t ws_bytes, kfb_stream_t stream);
+
+/* kfb_rsvd_overwrite: (U, D) <- the rank-r randomized SVD of X (r = the
+ * state's truncation rank), with l = r + oversample sketch columns and
+ * power_its re-orthonormalised power iterations (each a product with X^T and
+ * one with X):
+ *   Q = orth(X Omega); power_its times { Q = orth(X^T Q); Q = orth(X Q) };
+ *   B = Q^T X = U_B S V_B^T;  U = Q U_B[:, :r],  D = S[:r]
+ * (the paper writes the result as U~ D~ U~^T: the left singular vectors and
+ * the singular values).  Omega: the d x l Gaussian test matrix (column-major,
+ * ld ldo >= d, the element type of X) drawn by the caller.  Orthonormalisation
+ * is CholeskyQR as in the B-update; the small SVD is the B-update's core
+ * eigensolver on the triangular factor of X^T Q.  Writes the back buffers and
+ * swaps (a preconditioning enqueued earlier still reads the old modes); the
+ * state then holds r modes.  Requires 1 <= r, l <= min(d, r + n_max, 2048),
+ * 0 <= power_its <= 16.  A sketch whose range has fewer than l directions
+ * (X of low rank) sets KFB_EV_CHOL_DEFICIENT and yields zero singular values
+ * for the missing directions.  Errors: KFB_EINVAL, KFB_EWORKSPACE. */
+size_t kfb_rsvd_workspace_bytes(kfb_state_t st, int32_t oversample);
+int kfb_rsvd_overwrite(kfb_state_t st, const void* X, int64_t ldx, const void* Omega, int64_t ldo,
+                       int32_t oversample, int32_t power_its, void* workspace, size_t ws_bytes,
+                       kfb_stream_t stream);
+
 /* Host-side metadata: modes held, updates applied, sizes. Any pointer may be NULL. */
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,
                    int32_t* n_max, int32_t* prec);

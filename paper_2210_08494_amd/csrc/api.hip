@@ -211,48 +211,24 @@ hipError_t mm(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
   }
 }
 
+// Thin QR of the d x n matrix at srcZ (Algorithm 3's QR of the residual; the
+// re-orthonormalisation of the randomized range finder) by CholeskyQR: two
+// passes when the Gram is formed in FP64; in the FP32 form a shifted first pass
+// (shifted CholeskyQR3) keeps the factorisation stable for ill-conditioned
+// inputs.  Ping-pongs between srcZ and altZ; returns the offsets of Q and of R
+// (n x n upper triangular, the product of the passes' factors).
 template <int PR>
-int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
+int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t altZ, int64_t* oQ_out,
+            int64_t* oR_out, hipStream_t s) {
   typedef Ty<PR> T;
-  typedef typename T::U TU; typedef typename T::M TM; typedef typename T::Z TZ;
-  typedef typename T::P TP; typedef typename T::G TG; typedef typename T::Core TC;
-  typedef typename T::W TW; typedef typename T::D TD; typedef typename T::Acc TA;
-  const int64_t d = p.d, ldu = p.ldu, ldm = p.ldm;
-  const int r = p.r, n = p.n, N = p.N;
-
-  const int kl_P = p.ksP > 1 ? 2 : 1, kl_G = p.ksG > 1 ? 2 : 1;
-  if (r > 0) {
-    // P = U_r^T M   (Algorithm 3: projection)
-    StageTimer st_proj("proj", s, 2 * kl_P + 2);
-    GemmArgs g;
-    g.A = op(U_FRONT, 0, ldu, 1); g.B = op(M_IN, 0, 1, ldm); g.C = op(WS, p.oP, 1, r);
-    g.m = r; g.n = n; g.k = (int)d; g.ksplit = p.ksP; g.Part = op(WS, p.oPart, 1, r);
-    KFB_TRY((mm<PR, 1, TU, TM, TP, TP, TP>(drecs, nrec, g, s)));
-    // Z = M - U_r P   (component outside span(U))
-    GemmArgs z;
-    z.A = op(U_FRONT, 0, 1, ldu); z.B = op(WS, p.oP, 1, r); z.C0 = op(M_IN, 0, 1, ldm);
-    z.C = op(WS, p.oZ, 1, d); z.m = (int)d; z.n = n; z.k = r; z.alpha = -1.0; z.beta = 1.0;
-    KFB_TRY((mm<PR, 1, TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
-    // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
-    GemmArgs g2 = g;
-    g2.B = op(WS, p.oZ, 1, d); g2.C = op(WS, p.oP2, 1, r);
-    KFB_TRY((mm<PR, 1, TU, TZ, TP, TP, TP>(drecs, nrec, g2, s)));
-    GemmArgs z2 = z;
-    z2.B = op(WS, p.oP2, 1, r); z2.C0 = op(WS, p.oZ, 1, d);
-    KFB_TRY((mm<PR, 1, TU, TP, TZ, TZ, TA>(drecs, nrec, z2, s)));
-  } else {
-    StageTimer st_copy("proj", s, 1);
-    KFB_TRY((copy2d<TZ, TM>(drecs, nrec, op(WS, p.oZ, 1, d), op(M_IN, 0, 1, ldm), (int)d, n, s)));
-  }
-  // Thin QR of the residual (Algorithm 3) by CholeskyQR: two passes when the
-  // Gram is formed in FP64; in the FP32 form a shifted first pass (shifted
-  // CholeskyQR3) keeps the factorisation stable for ill-conditioned residuals.
+  typedef typename T::Z TZ; typedef typename T::G TG; typedef typename T::Acc TA;
+  const int64_t d = p.d;
+  const int n = p.n;
   const bool fp32_chol = sizeof(TG) == 4;
   const int passes = fp32_chol ? 3 : 2;
-  std::unique_ptr<StageTimer> st_qr(new StageTimer("cholqr", s, passes * (kl_G + 2) + passes - 1));
   const double ueps = fp32_chol ? 1.1920929e-07 : 2.220446049250313e-16;
   const double tau = 64.0 * ueps;
-  int64_t srcZ = p.oZ, dstZ = p.oZb;
+  int64_t dstZ = altZ;
   const int64_t oR[3] = {p.oR1, p.oR2, p.oR3}, oX[2] = {p.oX1, p.oX2};
   for (int pass = 0; pass < passes; ++pass) {
     if constexpr (sizeof(TG) == 8) {
@@ -284,7 +260,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
     const int64_t tmp = srcZ; srcZ = dstZ; dstZ = tmp;
   }
-  const int64_t oQ = srcZ;  // the orthonormal Q after the last pass
+  *oQ_out = srcZ;  // the orthonormal Q after the last pass
   // R = R_last ... R_1 (products of upper-triangular factors)
   {
     GemmArgs rr;
@@ -297,17 +273,23 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
       KFB_TRY((gemm<TG, TG, TG, TG, TG>(drecs, nrec, r3, s)));
     }
   }
-  const int64_t oRfin = passes == 3 ? p.oGram : p.oRt;
-  st_qr.reset();
-  // core square factor and Jacobi eigensolve (Algorithm 3: EVD of M_S)
-  CoreArgs co;
-  co.r = r; co.n = n; co.N = N; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = r > 0 ? p.oP2 : -1;
-  co.off_R = oRfin; co.off_B = p.oB; co.off_V = p.oV;
-  {
-    StageTimer st_core("core", s, 2);
-    KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, nrec, co, s)));
-    KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
-  }
+  *oR_out = passes == 3 ? p.oGram : p.oRt;
+  return KFB_OK;
+}
+
+// launches of one thin_qr (for the stage counters)
+inline int thin_qr_launches(int prec, int ksG) {
+  const int passes = prec == KFB_FP32 ? 3 : 2, kl = ksG > 1 ? 2 : 1;
+  return passes * (kl + 2) + passes - 1;
+}
+
+// Jacobi eigensolve of the assembled core (B, V in the plan's workspace) and
+// finalize: eigenvalues descending into D_BACK, eigenvectors into W.
+template <int PR>
+int core_evd(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::Core TC; typedef typename T::W TW; typedef typename T::D TD;
+  const int N = p.N;
   JacArgs ja;
   ja.Np = p.Np; ja.N = N; ja.b = p.bw; ja.max_sweeps = MAX_SWEEPS;
   ja.off_B = p.oB; ja.off_V = p.oV; ja.off_cnt = p.oCnt;
@@ -331,6 +313,62 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   {
     StageTimer st_fin("finalize", s, 2);
     KFB_TRY((finalize_core<TC, TW, TD>(drecs, nrec, fa, s)));
+  }
+  return KFB_OK;
+}
+
+template <int PR>
+int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::M TM; typedef typename T::Z TZ;
+  typedef typename T::P TP; typedef typename T::G TG; typedef typename T::Core TC;
+  typedef typename T::W TW; typedef typename T::D TD; typedef typename T::Acc TA;
+  const int64_t d = p.d, ldu = p.ldu, ldm = p.ldm;
+  const int r = p.r, n = p.n, N = p.N;
+
+  const int kl_P = p.ksP > 1 ? 2 : 1;
+  if (r > 0) {
+    // P = U_r^T M   (Algorithm 3: projection)
+    StageTimer st_proj("proj", s, 2 * kl_P + 2);
+    GemmArgs g;
+    g.A = op(U_FRONT, 0, ldu, 1); g.B = op(M_IN, 0, 1, ldm); g.C = op(WS, p.oP, 1, r);
+    g.m = r; g.n = n; g.k = (int)d; g.ksplit = p.ksP; g.Part = op(WS, p.oPart, 1, r);
+    KFB_TRY((mm<PR, 1, TU, TM, TP, TP, TP>(drecs, nrec, g, s)));
+    // Z = M - U_r P   (component outside span(U))
+    GemmArgs z;
+    z.A = op(U_FRONT, 0, 1, ldu); z.B = op(WS, p.oP, 1, r); z.C0 = op(M_IN, 0, 1, ldm);
+    z.C = op(WS, p.oZ, 1, d); z.m = (int)d; z.n = n; z.k = r; z.alpha = -1.0; z.beta = 1.0;
+    KFB_TRY((mm<PR, 1, TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
+    // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
+    GemmArgs g2 = g;
+    g2.B = op(WS, p.oZ, 1, d); g2.C = op(WS, p.oP2, 1, r);
+    KFB_TRY((mm<PR, 1, TU, TZ, TP, TP, TP>(drecs, nrec, g2, s)));
+    GemmArgs z2 = z;
+    z2.B = op(WS, p.oP2, 1, r); z2.C0 = op(WS, p.oZ, 1, d);
+    KFB_TRY((mm<PR, 1, TU, TP, TZ, TZ, TA>(drecs, nrec, z2, s)));
+  } else {
+    StageTimer st_copy("proj", s, 1);
+    KFB_TRY((copy2d<TZ, TM>(drecs, nrec, op(WS, p.oZ, 1, d), op(M_IN, 0, 1, ldm), (int)d, n, s)));
+  }
+  int64_t oQ, oRfin;
+  std::unique_ptr<StageTimer> st_qr(new StageTimer("cholqr", s, thin_qr_launches(PR, p.ksG)));
+  {
+    const int rc = thin_qr<PR>(drecs, nrec, p, p.oZ, p.oZb, &oQ, &oRfin, s);
+    if (rc != KFB_OK) return rc;
+  }
+  st_qr.reset();
+  // core square factor and Jacobi eigensolve (Algorithm 3: EVD of M_S)
+  CoreArgs co;
+  co.r = r; co.n = n; co.N = N; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = r > 0 ? p.oP2 : -1;
+  co.off_R = oRfin; co.off_B = p.oB; co.off_V = p.oV;
+  {
+    StageTimer st_core("core", s, 2);
+    KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, nrec, co, s)));
+    KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
+  }
+  {
+    const int rc = core_evd<PR>(drecs, nrec, p, s);
+    if (rc != KFB_OK) return rc;
   }
   // rotation: U' = [U_r Q] W  (Algorithm 3), into the back buffer
   GemmArgs ro;
@@ -516,6 +554,105 @@ int run_fac(const Rec* drecs, int nrec, const FacPlan& p, uint32_t flags, hipStr
   g5.A = op(PWS, p.oYG, 1, p.dG); g5.B = op(PWS, p.oYA, p.dA, 1); g5.C = op(P_S, 0, p.lds, 1);
   g5.m = (int)p.dG; g5.n = (int)p.dA; g5.k = n; g5.aligned16 = p.aligned16;
   KFB_TRY((mm<PR, 0, TA, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
+  return KFB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// B-R-KFAC (Algorithm 5): dense EA factor and the randomized-SVD overwrite
+// ---------------------------------------------------------------------------
+// X = beta X + alpha M M^T   (X: d x d column-major; M: d x n batch)
+template <int PR>
+int run_dense(const Rec* drecs, int64_t d, int64_t ldx, int64_t ldm, int n, double alpha, double beta,
+              hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TX; typedef typename T::M TM; typedef typename T::Acc TA;
+  GemmArgs g;
+  g.A = op(M_IN, 0, 1, ldm); g.B = op(M_IN, 0, ldm, 1);
+  g.C0 = op(B_X, 0, 1, ldx); g.C = op(B_X, 0, 1, ldx);
+  g.m = (int)d; g.n = (int)d; g.k = n; g.alpha = alpha; g.beta = beta;
+  StageTimer st("dense_ea", s, 1);
+  if constexpr (PR == KFB_BF16_MIXED) {
+    KFB_TRY((gemm_bf16<TM, TM, TX, TX, 0>(drecs, 1, g, s)));
+  } else {
+    KFB_TRY((gemm<TM, TM, TX, TX, TA>(drecs, 1, g, s)));
+  }
+  return KFB_OK;
+}
+
+// Randomized SVD of X truncated to r, written into the back buffers:
+//   Y = X Omega;  q times { Q = qr(Y); Y = X^T Q; Q = qr(Y); Y = X Q };  Q = qr(Y);
+//   B = Q^T X = Y'^T with Y' = X^T Q = Q' R';  the left singular vectors of B are
+//   the eigenvectors of R'^T R' (the Jacobi core with square factor R'), the
+//   singular values the square roots of its eigenvalues;  U = Q W[:, :r].
+template <int PR>
+int run_rsvd(const Rec* drecs, const UpdPlan& p, int64_t oZc, int r, int64_t ldx, int64_t ldo, int power_its,
+             hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::Z TZ; typedef typename T::P TP; typedef typename T::G TG;
+  typedef typename T::Core TC; typedef typename T::W TW; typedef typename T::D TD; typedef typename T::Acc TA;
+  const int64_t d = p.d;
+  const int l = p.n;
+  int64_t oQ = -1, oR = -1;
+  // the three d x l buffers: the product lands in one not holding Q
+  const int64_t bufs[3] = {p.oZ, p.oZb, oZc};
+  auto product = [&](bool transposed, int64_t src, int64_t dst, bool omega) -> int {
+    GemmArgs g;
+    g.A = transposed ? op(B_X, 0, ldx, 1) : op(B_X, 0, 1, ldx);
+    g.B = omega ? op(B_OMEGA, 0, 1, ldo) : op(WS, src, 1, d);
+    g.C = op(WS, dst, 1, d);
+    g.m = (int)d; g.n = l; g.k = (int)d;
+    KFB_TRY((mm<PR, 1, TU, TU, TZ, TZ, TA>(drecs, 1, g, s)));
+    return KFB_OK;
+  };
+  auto other = [&](int64_t a, int64_t b) {
+    for (int i = 0; i < 3; ++i)
+      if (bufs[i] != a && bufs[i] != b) return bufs[i];
+    return bufs[0];
+  };
+  auto qr = [&](int64_t y, int64_t keep) -> int {
+    // factor Y (at y) using the buffer not holding `keep` as the second one
+    return thin_qr<PR>(drecs, 1, p, y, other(y, keep), &oQ, &oR, s);
+  };
+  {
+    StageTimer st("rsvd_range", s, 1);
+    int rc = product(false, 0, p.oZ, true);
+    if (rc != KFB_OK) return rc;
+    if ((rc = qr(p.oZ, -1)) != KFB_OK) return rc;
+    for (int it = 0; it < power_its; ++it) {
+      for (int half = 0; half < 2; ++half) {
+        const int64_t y = other(oQ, -1);
+        if ((rc = product(half == 0, oQ, y, false)) != KFB_OK) return rc;
+        if ((rc = qr(y, -1)) != KFB_OK) return rc;
+      }
+    }
+    // Y' = X^T Q and its R' (Q kept)
+    const int64_t Qfin = oQ;
+    const int64_t y = other(Qfin, -1);
+    if ((rc = product(true, Qfin, y, false)) != KFB_OK) return rc;
+    if ((rc = qr(y, Qfin)) != KFB_OK) return rc;
+    oQ = Qfin;
+  }
+  // core: B_jac = R' (assemble_core forms the transpose of its square factor, so
+  // it is handed R'^T), V = I
+  CoreArgs co;
+  co.r = 0; co.n = l; co.N = l; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = -1;
+  co.off_R = p.oX1; co.off_B = p.oB; co.off_V = p.oV;
+  {
+    StageTimer st("core", s, 3);
+    KFB_TRY((copy2d<TG, TG>(drecs, 1, op(WS, p.oX1, 1, l), op(WS, oR, l, 1), l, l, s)));
+    KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, 1, co, s)));
+    KFB_TRY(zero_words(drecs, 1, WS, p.oCnt, MAX_SWEEPS, s));
+  }
+  {
+    const int rc = core_evd<PR>(drecs, 1, p, s);
+    if (rc != KFB_OK) return rc;
+  }
+  StageTimer st("rsvd_rotate", s, 2);
+  KFB_TRY(sqrt_prefix<TD>(drecs, 1, D_BACK, 0, r, s));
+  GemmArgs ro;
+  ro.A = op(WS, oQ, 1, d); ro.B = op(WS, p.oW, 1, l); ro.C = op(U_BACK, 0, 1, p.ldu);
+  ro.m = (int)d; ro.n = r; ro.k = l;
+  KFB_TRY((mm<PR, 1, TZ, TW, TU, TU, TA>(drecs, 1, ro, s)));
   return KFB_OK;
 }
 
@@ -721,6 +858,76 @@ int dispatch_fac(int count, kfb_state_t const* stG, kfb_state_t const* stA, cons
   return run_fac<KFB_BF16_MIXED>(dev, count, p, flags, s);
 }
 
+int dispatch_dense(kfb_state_t st, void* X, int64_t ldx, const void* M, int64_t ldm, int n, int first,
+                   void* workspace, size_t ws_bytes, hipStream_t s) {
+  if (!st || !X || !M || !workspace || n < 1 || ldx < st->d || ldm < st->d) return KFB_EINVAL;
+  if (ws_bytes < 256) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  const size_t xe = st->prec == KFB_FP64 ? 8 : 4;
+  const char* xb = (const char*)X;
+  const char* mb = (const char*)M;
+  const size_t xbytes = (size_t)((st->d - 1) * ldx + st->d) * xe;
+  const size_t mbytes = (size_t)((n - 1) * ldm + st->d) * m_elem(st->prec);
+  if (xb < mb + mbytes && mb < xb + xbytes) return KFB_EINVAL;
+  Rec host;
+  memset(&host, 0, sizeof(Rec));
+  host.p[M_IN] = const_cast<void*>(M);
+  host.p[B_X] = X;
+  Rec* dev = (Rec*)workspace;
+  if (upload_recs(&host, 1, dev, s) != hipSuccess) return KFB_EHIP;
+  const double alpha = first ? 1.0 / n : (1.0 - st->rho) / n;
+  const double beta = first ? 0.0 : st->rho;
+  if (st->prec == KFB_FP64) return run_dense<KFB_FP64>(dev, st->d, ldx, ldm, n, alpha, beta, s);
+  if (st->prec == KFB_FP32) return run_dense<KFB_FP32>(dev, st->d, ldx, ldm, n, alpha, beta, s);
+  return run_dense<KFB_BF16_MIXED>(dev, st->d, ldx, ldm, n, alpha, beta, s);
+}
+
+constexpr int RSVD_MAX_POWER_ITS = 16;
+
+int dispatch_rsvd(kfb_state_t st, const void* X, int64_t ldx, const void* Omega, int64_t ldo, int oversample,
+                  int power_its, void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only) {
+  if (!st || oversample < 0 || power_its < 0 || power_its > RSVD_MAX_POWER_ITS) return KFB_EINVAL;
+  const int r = st->r;
+  const int64_t l = (int64_t)r + oversample;
+  if (r < 1 || l > st->d || l > (int64_t)r + st->n_max || l > 2048) return KFB_EINVAL;
+  UpdPlan p;
+  bool ok = false;
+  if (st->prec == KFB_FP64) ok = make_upd_plan<KFB_FP64>(st->d, st->ldu, st->d, 0, (int)l, 1, &p);
+  else if (st->prec == KFB_FP32) ok = make_upd_plan<KFB_FP32>(st->d, st->ldu, st->d, 0, (int)l, 1, &p);
+  else ok = make_upd_plan<KFB_BF16_MIXED>(st->d, st->ldu, st->d, 0, (int)l, 1, &p);
+  if (!ok) return KFB_EINVAL;
+  const size_t ze = st->prec == KFB_FP64 ? 8 : 4;  // Y, Q element size
+  const int64_t oZc = (int64_t)p.per_problem;
+  const size_t head = align256(sizeof(Rec));
+  const size_t need = head + p.per_problem + align256((size_t)st->d * l * ze);
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!X || !Omega || !workspace || ldx < st->d || ldo < st->d) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  Rec host;
+  memset(&host, 0, sizeof(Rec));
+  host.p[U_FRONT] = st->buf + st->off_U[st->front];
+  host.p[U_BACK] = st->buf + st->off_U[1 - st->front];
+  host.p[WS] = (char*)workspace + head;
+  host.p[D_FRONT] = st->buf + st->off_D[st->front];
+  host.p[D_BACK] = st->buf + st->off_D[1 - st->front];
+  host.p[STATUS] = st->buf + st->off_status;
+  host.p[B_X] = const_cast<void*>(X);
+  host.p[B_OMEGA] = const_cast<void*>(Omega);
+  host.s[0] = 0.0;  // core of the square factor R' alone: no decayed modes,
+  host.s[1] = 1.0;  // unit weight
+  Rec* dev = (Rec*)workspace;
+  if (upload_recs(&host, 1, dev, s) != hipSuccess) return KFB_EHIP;
+  int rc;
+  if (st->prec == KFB_FP64) rc = run_rsvd<KFB_FP64>(dev, p, oZc, r, ldx, ldo, power_its, s);
+  else if (st->prec == KFB_FP32) rc = run_rsvd<KFB_FP32>(dev, p, oZc, r, ldx, ldo, power_its, s);
+  else rc = run_rsvd<KFB_BF16_MIXED>(dev, p, oZc, r, ldx, ldo, power_its, s);
+  if (rc != KFB_OK) return rc;
+  st->front = 1 - st->front;
+  st->k_valid = r;
+  return KFB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -870,6 +1077,31 @@ int kfb_precondition_factored_batched(int32_t count, kfb_state_t const* st_gamma
                                       kfb_stream_t stream) {
   return dispatch_fac(count, st_gamma, st_a, G_k, ldgk, A_k, ldak, n, S, lds, lam_gamma, lam_a, flags,
                       workspace, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_dense_bytes(int64_t d, int64_t ldx, int32_t prec) {
+  if (d <= 0 || ldx < d || prec < KFB_FP64 || prec > KFB_BF16_MIXED) return 0;
+  return (size_t)ldx * d * (prec == KFB_FP64 ? 8 : 4);
+}
+
+size_t kfb_dense_update_workspace_bytes(void) { return 256; }
+
+int kfb_dense_update(kfb_state_t st, void* X, int64_t ldx, const void* M, int64_t ldm, int32_t n,
+                     int32_t first, void* workspace, size_t ws_bytes, kfb_stream_t stream) {
+  return dispatch_dense(st, X, ldx, M, ldm, n, first, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+size_t kfb_rsvd_workspace_bytes(kfb_state_t st, int32_t oversample) {
+  size_t need = 0;
+  if (dispatch_rsvd(st, nullptr, 0, nullptr, 0, oversample, 0, nullptr, 0, nullptr, &need) != KFB_OK) return 0;
+  return need;
+}
+
+int kfb_rsvd_overwrite(kfb_state_t st, const void* X, int64_t ldx, const void* Omega, int64_t ldo,
+                       int32_t oversample, int32_t power_its, void* workspace, size_t ws_bytes,
+                       kfb_stream_t stream) {
+  return dispatch_rsvd(st, X, ldx, Omega, ldo, oversample, power_its, workspace, ws_bytes, (hipStream_t)stream,
+                       nullptr);
 }
 
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,

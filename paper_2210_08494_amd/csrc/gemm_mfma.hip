@@ -545,6 +545,8 @@ KFB_GEMM_BF16(float, float, float, bf16, 1)
 KFB_GEMM_BF16(float, float, float, float, 1)
 // mixed-form preconditioner (single BF16 terms)
 KFB_GEMM_BF16(float, float, float, float, 0)
+// mixed-form dense EA factor: X = rho X + w M M^T from BF16 batches (exact products)
+KFB_GEMM_BF16(bf16, bf16, float, float, 0)
 #undef KFB_GEMM_BF16
 
 }  // namespace kfb

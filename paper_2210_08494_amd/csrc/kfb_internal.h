@@ -29,6 +29,10 @@ enum UpdSlot { U_FRONT = 0, U_BACK = 1, M_IN = 2, WS = 3, D_FRONT = 4, D_BACK = 
 // (the factored form also reads A_k from P_AK; G_k comes in P_G)
 enum PreSlot { PU_G = 0, PD_G = 1, PU_A = 2, PD_A = 3, P_G = 4, P_S = 5, PWS = 6, P_AK = 7 };
 
+// Slots of the B-R-KFAC calls (with the update's slots): the dense EA factor
+// and the Gaussian sketch of the randomized SVD.
+enum DenseSlot { B_X = 7, B_OMEGA = 8 };
+
 // A matrix operand resolved per record: element (i, j) of the logical matrix
 // lives at base + i*rs + j*cs, with base = rec.p[slot] + off (bytes).  When
 // slot2 >= 0 the operand is split along its k-index (columns of A, rows of B)

@@ -106,4 +106,8 @@ struct ScaleArgs {
 template <typename T, typename TS>
 hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s);
 
+// x_i <- sqrt(max(x_i, 0)), i < count, for the vector at rec.p[slot] + off
+template <typename T>
+hipError_t sqrt_prefix(const Rec* recs, int nrec, int slot, int64_t off, int count, hipStream_t s);
+
 }  // namespace kfb

@@ -1786,7 +1786,8 @@ hipError_t finalize_core(const Rec* recs, int nrec, const FinArgs& a, hipStream_
 //     sA = c_A / lam_G   (cols of G U_A)        tA = c_A  (cols of the core)
 //     beta = 1 / (lam_G lam_A)                   (the G term), as a double.
 // Layout at off_cG: [sG (kG)][tG (kG)]; at off_cA: [sA (kA)][tA (kA)];
-// beta at off_cA + 2*kA*sizeof(TAcc) rounded to 8 bytes.
+// beta at off_cA + 2*kA*sizeof(TAcc) rounded to 8 bytes, then 1/lam_G and
+// 1/lam_A (the factored form's X / lam terms).
 // ---------------------------------------------------------------------------
 template <typename TD, typename TAcc>
 __global__ __launch_bounds__(256) void precond_coefs_kernel(const Rec* __restrict__ recs, CoefArgs a) {
@@ -1869,7 +1870,29 @@ hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
+// x_i <- sqrt(max(x_i, 0)) for the first `count` entries (singular values from
+// the eigenvalues of a Gram matrix)
+template <typename T>
+__global__ __launch_bounds__(256) void sqrt_prefix_kernel(const Rec* __restrict__ recs, int slot, int64_t off,
+                                                          int count) {
+  T* x = at<T>(recs[blockIdx.y], slot, off);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+    const double v = (double)x[i];
+    x[i] = T(v > 0.0 ? sqrt(v) : 0.0);
+  }
+}
+
+template <typename T>
+hipError_t sqrt_prefix(const Rec* recs, int nrec, int slot, int64_t off, int count, hipStream_t s) {
+  if (count <= 0 || nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL((sqrt_prefix_kernel<T>), dim3((count + 255) / 256, nrec), dim3(256), 0, s, recs, slot, off,
+                     count);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
+template hipError_t sqrt_prefix<double>(const Rec*, int, int, int64_t, int, hipStream_t);
+template hipError_t sqrt_prefix<float>(const Rec*, int, int, int64_t, int, hipStream_t);
 template hipError_t chol_inv<double>(const Rec*, int, const CholArgs&, hipStream_t);
 template hipError_t chol_inv<float>(const Rec*, int, const CholArgs&, hipStream_t);
 template hipError_t assemble_core<double, double, double, double>(const Rec*, int, const CoreArgs&, hipStream_t);

@@ -49,6 +49,11 @@ _SIGS = {
                                                          ctypes.POINTER(_vp), _i64, ctypes.POINTER(_vp), _i64,
                                                          _i32, ctypes.POINTER(_vp), _i64, ctypes.POINTER(_dbl),
                                                          ctypes.POINTER(_dbl), _u32, _vp, _sz, _vp]),
+    "kfb_dense_bytes": (_sz, [_i64, _i64, _i32]),
+    "kfb_dense_update_workspace_bytes": (_sz, []),
+    "kfb_dense_update": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, _sz, _vp]),
+    "kfb_rsvd_workspace_bytes": (_sz, [_vp, _i32]),
+    "kfb_rsvd_overwrite": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, _sz, _vp]),
     "kfb_state_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
@@ -307,6 +312,37 @@ def precondition_factored_batched(fgs, fas, Gks, Aks, Ss, lam_g, lam_a, flags, w
     _check(lib.kfb_precondition_factored_batched(cnt, hg, ha, gp, ldgk, ap, ldak, n, sp, int(Ss[0].stride(0)),
                                                  lg, la, int(flags), _ptr(w), int(w.numel()), _stream()),
            "kfb_precondition_factored_batched")
+
+
+def dense_factor(f: Factor, device="cuda"):
+    """A zeroed dense EA factor for the state f (d x d; row j of the tensor is column j)."""
+    import torch
+    return torch.zeros((f.d, f.d), dtype=_dtype_of(f.prec), device=device)
+
+
+def dense_update(f: Factor, X, M, first: bool, ws: Workspace | None = None):
+    """X <- rho X + (1 - rho)/n M M^T (first: M M^T / n), B-R-KFAC's dense EA factor of f."""
+    lib = load()
+    assert X.is_cuda and X.dim() == 2 and X.shape == (f.d, f.d) and X.stride(1) == 1 and X.dtype == _dtype_of(f.prec)
+    n, ldm = _factor_arg(M, f)
+    w = (ws or f.ws).get(lib.kfb_dense_update_workspace_bytes())
+    _check(lib.kfb_dense_update(f.handle, _ptr(X), int(X.stride(0)), _ptr(M), ldm, n, 1 if first else 0, _ptr(w),
+                                int(w.numel()), _stream()), "kfb_dense_update")
+
+
+def rsvd_overwrite(f: Factor, X, Omega, oversample: int, power_its: int, ws: Workspace | None = None):
+    """(U, D) of f <- the rank-r randomized SVD of X with the sketch Omega ((r + oversample, d) tensor)."""
+    lib = load()
+    assert X.is_cuda and X.shape == (f.d, f.d) and X.stride(1) == 1 and X.dtype == _dtype_of(f.prec)
+    assert Omega.is_cuda and Omega.dim() == 2 and Omega.shape[1] == f.d and Omega.stride(1) == 1
+    assert Omega.dtype == X.dtype and Omega.shape[0] == f.r + oversample
+    need = lib.kfb_rsvd_workspace_bytes(f.handle, int(oversample))
+    if need == 0:
+        raise KfbError("kfb_rsvd_workspace_bytes rejected the sizes")
+    w = (ws or f.ws).get(need)
+    _check(lib.kfb_rsvd_overwrite(f.handle, _ptr(X), int(X.stride(0)), _ptr(Omega), int(Omega.stride(0)),
+                                  int(oversample), int(power_its), _ptr(w), int(w.numel()), _stream()),
+           "kfb_rsvd_overwrite")
 
 
 def profile_enable(on: bool = True):

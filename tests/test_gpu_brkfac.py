@@ -1,0 +1,165 @@
+"""GPU parity of B-R-KFAC (Algorithm 5) through the C-ABI.
+
+Every T_RSVD steps the factor's representation is overwritten by the rank-r
+randomized SVD of the dense EA factor of the previous step (the same Gaussian
+sketch on both sides), then the B-update proceeds.  Checked against the FP64
+oracle (oracle/rsvd.py for the dense factor and the RSVD, Oracle-B for the
+updates): the state after every overwrite and every update (basis-invariant
+reconstruction error), the dense factor, and the orthonormality of U.
+Tolerances 1e-10 / 1e-5 / 2e-2 for the FP64 / FP32 / BF16-mixed forms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_08494_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-5, 2: 2e-2}
+XTOL = {0: 1e-13, 1: 1e-6, 2: 1e-6}
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _to_dev(x, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=_dev(), dtype=dtype)
+
+
+def _front_np(f):
+    import torch
+    torch.cuda.synchronize()
+    U, D = f.front()
+    return U.double().cpu().numpy(), D.double().cpu().numpy()
+
+
+def _batch(cfg, k, side, n, d, prec):
+    x = synth.batch_for(cfg, k, side, n, d)
+    if prec == 1:
+        x = x.astype(np.float32).astype(np.float64)
+    if prec == 2:
+        x = synth.to_bf16_values(x)
+    return x
+
+
+def _trajectory(kfb, prec, d, r, n, p, q, T, steps, cfg, side="A", rho=0.95, check_x=True):
+    import torch
+    mdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[prec]
+    xdt = torch.float64 if prec == 0 else torch.float32
+    f = kfb.Factor(d, r, n, rho, prec)
+    X = kfb.dense_factor(f)
+    ob = oracle.BrandFactor(d, r, rho)
+    E = None
+    worst = dict(over=0.0, upd=0.0, x=0.0, orth=0.0)
+    for k in range(steps):
+        if k > 0 and k % T == 0:
+            Om = synth.sketch_for(cfg, k, d, r + p)   # (l, d) rows = columns of Omega
+            if prec == 1:
+                Om = Om.astype(np.float32).astype(np.float64)
+            kfb.rsvd_overwrite(f, X, _to_dev(Om, xdt), p, q)
+            # the oracle works on the dense factor the GPU holds (rounded to the form's type)
+            Xh = X.double().cpu().numpy().T if prec else E
+            U, s = oracle.rsvd_overwrite(Xh, Om.T, r, q)
+            ob.overwrite(U, s)
+            Ug, Dg = _front_np(f)
+            assert Ug.shape[1] == r
+            worst["over"] = max(worst["over"], oracle.e_rec_lowrank(Ug, Dg, U, s))
+            worst["orth"] = max(worst["orth"], oracle.e_orth(Ug))
+        M = _batch(cfg, k, side, n, d, prec)
+        Md = _to_dev(M, mdt)
+        f.update(Md)
+        kfb.dense_update(f, X, Md, first=(k == 0))
+        ob.update(M.T)
+        E = oracle.ea_update(E, M.T, rho)
+        Ug, Dg = _front_np(f)
+        worst["upd"] = max(worst["upd"], oracle.e_rec_lowrank(Ug, Dg, ob.U, ob.D))
+        if check_x:
+            Xg = X.double().cpu().numpy()
+            worst["x"] = max(worst["x"], float(np.linalg.norm(Xg.T - E) / np.linalg.norm(E)))
+    print(f"  worst {worst}", flush=True)
+    return f, worst
+
+
+def test_fp64_brkfac_trajectory(kfb):
+    d, r, n, p, q, T, steps = 256, 32, 32, 16, 2, 5, 12
+    print(f"fp64 B-R-KFAC d={d} r={r} n={n} l={r + p} q={q} T={T}", flush=True)
+    f, w = _trajectory(kfb, kfb.KFB_FP64, d, r, n, p, q, T, steps, cfg=81)
+    assert w["over"] <= TOL[0] and w["upd"] <= TOL[0] and w["orth"] <= TOL[0] and w["x"] <= XTOL[0]
+    assert f.status() == 0
+
+
+def test_fp32_brkfac_trajectory(kfb):
+    d, r, n, p, q, T, steps = 1024, 64, 64, 16, 2, 3, 7
+    print(f"fp32 B-R-KFAC d={d} r={r} n={n}", flush=True)
+    f, w = _trajectory(kfb, kfb.KFB_FP32, d, r, n, p, q, T, steps, cfg=82, side="G")
+    assert w["over"] <= TOL[1] and w["upd"] <= TOL[1] and w["orth"] <= TOL[1] and w["x"] <= XTOL[1]
+
+
+def test_mixed_brkfac_headline_width(kfb):
+    d, r, n, p, q, T, steps = 4096, 256, 256, 16, 2, 2, 4
+    print(f"mixed B-R-KFAC d={d} r={r} n={n}", flush=True)
+    f, w = _trajectory(kfb, kfb.KFB_BF16_MIXED, d, r, n, p, q, T, steps, cfg=83)
+    assert w["over"] <= TOL[2] and w["upd"] <= TOL[2] and w["orth"] <= TOL[2] and w["x"] <= XTOL[2]
+
+
+def test_mixed_brkfac_hybrid_large_layer(kfb):
+    # the hybrid large layer: d = 16384, r = n = 1024 (core N = 2048), oversampling 16,
+    # 2 power iterations; two updates, the overwrite from the EA factor, one more update
+    d, r, n, p, q = 16384, 1024, 1024, 16, 2
+    MIX = kfb.KFB_BF16_MIXED
+    print(f"mixed B-R-KFAC hybrid layer d={d} r={r} n={n}", flush=True)
+    try:
+        kfb.tune_set_jacobi(MIX, r + n, kfb.KFB_JAC_STREAMED | 32)
+        kfb.tune_set_jacobi(MIX, r + p, kfb.KFB_JAC_STREAMED | 32)
+        f, w = _trajectory(kfb, MIX, d, r, n, p, q, 2, 3, cfg=84, check_x=False)
+    finally:
+        kfb.tune_set_jacobi(MIX, r + n, 0)
+        kfb.tune_set_jacobi(MIX, r + p, 0)
+    assert w["over"] <= TOL[2] and w["upd"] <= TOL[2] and w["orth"] <= TOL[2]
+    assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
+
+
+def test_rsvd_of_low_rank_factor(kfb):
+    # the EA factor of one step has rank n < l: the sketch's range is deficient (reported),
+    # and the overwrite is the exact leading eigenpairs of the factor
+    import torch
+    d, r, n, p = 128, 8, 6, 10
+    print("rsvd of a low-rank factor", flush=True)
+    f = kfb.Factor(d, r, 2 * n, 0.9, kfb.KFB_FP64)   # capacity r + n_max >= l
+    X = kfb.dense_factor(f)
+    M = synth.batch_for(85, 0, "G", n, d)
+    Md = _to_dev(M, torch.float64)
+    f.update(Md)
+    kfb.dense_update(f, X, Md, first=True)
+    Om = synth.sketch_for(85, 1, d, r + p)
+    kfb.rsvd_overwrite(f, X, _to_dev(Om, torch.float64), p, 2)
+    Ug, Dg = _front_np(f)
+    E = oracle.ea_update(None, M.T, 0.9)
+    lam, V = oracle.sorted_eigh(E)
+    assert np.max(np.abs(Dg[:n] - lam[:n])) <= 1e-12 * lam[0]
+    assert np.all(np.abs(Dg[n:]) <= 1e-12 * lam[0])
+    assert oracle.e_rec_lowrank(Ug, Dg, V[:, :n], lam[:n]) <= 1e-10
+    assert f.status() & kfb.KFB_EV_CHOL_DEFICIENT
+
+
+def test_brkfac_argument_errors(kfb):
+    import torch
+    lib = kfb.load()
+    d, r, n = 64, 8, 8
+    f = kfb.Factor(d, r, n, 0.95, kfb.KFB_FP64)
+    assert lib.kfb_rsvd_workspace_bytes(f.handle, n + 1) == 0      # l > r + n_max
+    assert lib.kfb_rsvd_workspace_bytes(f.handle, -1) == 0
+    assert lib.kfb_rsvd_workspace_bytes(f.handle, n) > 0
+    assert lib.kfb_dense_bytes(d, d - 1, 0) == 0 and lib.kfb_dense_bytes(d, d, 0) == d * d * 8
+    X = kfb.dense_factor(f)
+    Om = torch.zeros((r + 4, d), device=_dev(), dtype=torch.float64)
+    with pytest.raises(kfb.KfbError):
+        kfb.rsvd_overwrite(f, X, Om, 4, 17)                           # too many power iterations
+    M = torch.zeros((n, d), device=_dev(), dtype=torch.float64)
+    with pytest.raises(kfb.KfbError):
+        kfb.dense_update(f, X, M[:0], first=True)                    # n = 0
+    torch.cuda.synchronize()
