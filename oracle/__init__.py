@@ -22,6 +22,8 @@ precond   The regularised inverse applied on both sides of a layer gradient:
 rsvd      B-R-KFAC (Algorithm 5): the dense EA factor and the randomized SVD
           (range finder with re-orthonormalised power iterations) whose
           rank-r result overwrites a factor's representation.
+correct   B-KFAC-C (Algorithms 6 and 7): the light correction of a
+          representation on randomly chosen modes against the EA factor.
 metrics   Basis-invariant comparisons (reconstruction, eigenvalues,
           orthonormality, preconditioned-gradient error).
 """
@@ -30,4 +32,5 @@ from .brand import BrandFactor, symmetric_brand  # noqa: F401
 from .precond import (precondition_dense, lowrank_inverse_apply, precondition_lowrank,  # noqa: F401
                       precondition_factored, spectrum_continuation)
 from .rsvd import ea_update, range_basis, rsvd, rsvd_overwrite  # noqa: F401
+from .correct import light_correction  # noqa: F401
 from .metrics import e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S  # noqa: F401

@@ -15,8 +15,9 @@ fully-connected layer fed batches of n samples):
 * output grads g = Z' . diag(k^-beta), Z' ~ N(0,1)^{n x d}, beta = 0.7, no ReLU.
   The K-factor input is M_G = g^T.
 * layer gradient G ~ N(0,1)^{d_out x d_in}, a fresh draw every step.
-* the Gaussian test matrix of a randomized SVD, iid N(0,1), d x l (stream 4);
-  the method's random draws are inputs, so both sides get the same ones.
+* the Gaussian test matrix of a randomized SVD, iid N(0,1), d x l (stream 4),
+  and the columns a light correction picks (stream 5): the method's random
+  draws are inputs, so both sides get the same ones.
 
 Every array is generated in float64 by numpy's PCG64, seeded from
 SeedSequence(entropy=20221015, spawn_key=(config_id, step, stream)), and
@@ -87,6 +88,14 @@ def sketch_for(config_id: int, step: int, d: int, l: int) -> np.ndarray:
     As a d x l column-major matrix (the layout the C-ABI takes) it is the
     row-major numpy array of shape (l, d)."""
     return rng_for(config_id, step, STREAM_SKETCH).standard_normal((l, d))
+
+
+STREAM_CORRECT = 5
+
+
+def correction_columns(config_id: int, step: int, r: int, n_crc: int) -> np.ndarray:
+    """n_crc distinct column indices out of the leading r (B-KFAC-C's random choice)."""
+    return rng_for(config_id, step, STREAM_CORRECT).choice(r, size=n_crc, replace=False).astype(np.int32)
 
 
 def to_bf16_values(x: np.ndarray) -> np.ndarray:

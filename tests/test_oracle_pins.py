@@ -446,3 +446,59 @@ def test_structured_overwrite_matches_dense():
         D.update(M)
         E = ea_update(E, M, rho)
         assert e_rec_dense(b.U, b.D, D.X) <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# B-KFAC-C (Algorithm 6): the light correction
+# ----------------------------------------------------------------------------
+from oracle import light_correction  # noqa: E402
+
+
+def _bkfac_state(d, r, n, rho, steps, seed):
+    Ms = _batches(d, n, steps, seed=seed, decay=0.5)
+    b = BrandFactor(d, r, rho)
+    E = None
+    for M in Ms:
+        b.update(M)
+        E = ea_update(E, M, rho)
+    return b, E
+
+
+def test_light_correction_zeroes_projected_error():
+    d, r, n, rho = 60, 10, 5, 0.9
+    b, E = _bkfac_state(d, r, n, rho, 8, seed=51)
+    idx = np.array([7, 2, 9, 0, 4])
+    U2, D2 = light_correction(b.U, b.D, E, idx)
+    Uc = b.U[:, idx]
+    R = Uc.T @ (E - (U2 * D2) @ U2.T) @ Uc
+    assert np.linalg.norm(R) <= 1e-12 * np.linalg.norm(E)
+    assert e_orth(U2) <= 1e-13
+    assert np.all(np.diff(D2) <= 0)
+    # untouched modes survive as they were (the correction only mixes the chosen columns)
+    rest = [j for j in range(b.U.shape[1]) if j not in set(idx.tolist())]
+    for j in rest:
+        k = int(np.argmin(np.abs(D2 - b.D[j])))
+        assert abs(D2[k] - b.D[j]) <= 1e-15 * b.D[0] and abs(abs(U2[:, k] @ b.U[:, j]) - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [52, 53, 54])
+def test_light_correction_never_increases_error(seed):
+    d, r, n, rho = 50, 8, 6, 0.85
+    b, E = _bkfac_state(d, r, n, rho, 9, seed=seed)
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(r, size=4, replace=False)
+    U2, D2 = light_correction(b.U, b.D, E, idx)
+    before = np.linalg.norm(E - (b.U * b.D) @ b.U.T)
+    after = np.linalg.norm(E - (U2 * D2) @ U2.T)
+    assert after <= before * (1 + 1e-12)
+
+
+def test_light_correction_all_modes_is_rayleigh_ritz():
+    # every mode chosen: the result is the EVD of U^T E U lifted by U (library eigh)
+    d, r, n, rho = 40, 6, 4, 0.9
+    b, E = _bkfac_state(d, r, n, rho, 6, seed=55)
+    k = b.U.shape[1]
+    U2, D2 = light_correction(b.U, b.D, E, np.arange(k))
+    lam, W = np.linalg.eigh(b.U.T @ E @ b.U)
+    assert np.max(np.abs(D2 - lam[::-1])) <= 1e-13 * lam[-1]
+    assert e_rec_lowrank(U2, D2, b.U @ W, lam) <= 1e-12
