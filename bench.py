@@ -310,6 +310,40 @@ def main():
                 "s_write_gbs": round(L * 4.0 * D * D / (fac_call * 1e-3) / 1e9, 1),
                 "unit_work": "per layer 8*N*d*n (both sides) + 2*d^2*n (S = Y_G Y_A^T) flops; S written once (FP32)"}
 
+    # ---- B-R-KFAC pieces at the same shape: one dense EA-factor step and one
+    # randomized-SVD overwrite (oversampling 16, two power iterations)
+    fbr = kfb.Factor(D, R, N_BATCH, RHO, MIX, device=dev)
+    Xd = kfb.dense_factor(fbr, device=dev)
+    kfb.dense_update(fbr, Xd, batches[0][0], first=True)
+    for j in range(2):
+        fbr.update(batches[j][0])
+        kfb.dense_update(fbr, Xd, batches[j][0], first=False)
+    gsk = torch.Generator(device=dev)
+    gsk.manual_seed(13)
+    Om = torch.randn(R + 16, D, generator=gsk, device=dev)
+    kfb.rsvd_overwrite(fbr, Xd, Om, 16, 2)
+    torch.cuda.synchronize()
+
+    def _time(fn, reps):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return _percentile(ts, 50)
+    dense_ms = _time(lambda: kfb.dense_update(fbr, Xd, batches[1][0], first=False), 5)
+    rsvd_ms = _time(lambda: kfb.rsvd_overwrite(fbr, Xd, Om, 16, 2), 3)
+    brkfac = {"dense_update_ms": round(dense_ms, 3),
+              "dense_update_tflops": round(2.0 * D * D * N_BATCH / (dense_ms * 1e-3) / 1e12, 1),
+              "rsvd_overwrite_ms": round(rsvd_ms, 3),
+              "rsvd_tflops": round(6 * 2.0 * D * D * (R + 16) / (rsvd_ms * 1e-3) / 1e12, 1),
+              "config": f"one factor, d={D}, r={R}, l={R + 16}, 2 power iterations; dense factor FP32",
+              "unit_work": "dense step 2*d^2*n flops; RSVD 6 products 2*d^2*l (sketch, 2 x 2 power, final)"}
+    del Xd
+
     # ---- single mixed update latency (no grouping), for the latency columns
     lat1 = []
     for i in range(6):
@@ -350,6 +384,7 @@ def main():
         "roofline": roofline,
         "stages": stages,
         "factored_apply": factored,
+        "brkfac": brkfac,
         "status_events": sorted(set(status)),
         "autotune": {"jacobi_config": tune.config_name(best_bw) if best_bw else None,
                      "candidates_ms": {tune.config_name(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},

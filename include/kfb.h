@@ -63,7 +63,11 @@ enum kfb_status_code {
 /* kfb_precondition flags */
 enum kfb_flags {
   KFB_SPECTRUM_CONTINUATION = 1, /* Section 3.5: lam += min(D), D -= min(D) per factor */
-  KFB_TRUNCATE_AFTER = 2         /* apply with the leading r modes only (default: all r+n) */
+  KFB_TRUNCATE_AFTER = 2,        /* apply with the leading r modes only (default: all r+n) */
+  KFB_RELATIVE_DAMPING = 4       /* Section 6: lam = phi * lambda_max per factor, the lam argument
+                                    being phi and lambda_max the largest eigenvalue of the modes
+                                    used (lam = phi when that is not positive); applied before
+                                    spectrum continuation */
 };
 
 /* bits of the device status word */
@@ -114,7 +118,8 @@ size_t kfb_precondition_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a);
 /* Two-sided regularised inverse (Section 2.1, Algorithm 1 inverse lines):
  *   S = (U_G D_G U_G^T + lam_gamma I)^{-1} G (U_A D_A U_A^T + lam_a I)^{-1}
  * with G, S row-major d_out x d_in, d_out = st_gamma's d and d_in = st_a's d.
- * lam > 0 absolute.  Uses all k_valid modes (or r with KFB_TRUNCATE_AFTER).
+ * lam > 0 absolute (or relative with KFB_RELATIVE_DAMPING).  Uses all k_valid
+ * modes (or r with KFB_TRUNCATE_AFTER).
  * G and S may not alias.  FP64 form: double G/S; FP32 and mixed: float. */
 int kfb_precondition(kfb_state_t st_gamma, kfb_state_t st_a, const void* G, int64_t ldg, void* S,
                      int64_t lds, double lam_gamma, double lam_a, uint32_t flags, void* workspace,
@@ -210,6 +215,24 @@ size_t kfb_rsvd_workspace_bytes(kfb_state_t st, int32_t oversample);
 int kfb_rsvd_overwrite(kfb_state_t st, const void* X, int64_t ldx, const void* Omega, int64_t ldo,
                        int32_t oversample, int32_t power_its, void* workspace, size_t ws_bytes,
                        kfb_stream_t stream);
+
+/* ---- B-KFAC-C (Section 3.5, Algorithms 6 and 7) -----------------------------
+ * Light correction of the current representation against the dense EA factor
+ * X of the same step (kept with kfb_dense_update):
+ *   U_c = U[:, col_idx];  M_S = U_c^T X U_c = W L W^T;
+ *   U[:, col_idx] = U_c W;  D[col_idx] = L;
+ * then the modes are re-sorted by eigenvalue, descending, so the next
+ * truncation keeps the largest (the paper writes the columns back in place).
+ * col_idx: HOST array of n_crc distinct indices among the leading
+ * min(r, k_valid) modes (the method's random choice, drawn by the caller;
+ * validated, then copied to the workspace on the stream).  X as for
+ * kfb_rsvd_overwrite.  The small EVD is the core eigensolver on the Cholesky
+ * factor of M_S.  Writes the back buffers and swaps; k_valid is unchanged.
+ * Errors: KFB_EINVAL (bad indices, n_crc out of range, k_valid > 4096),
+ * KFB_EEMPTY, KFB_EWORKSPACE. */
+size_t kfb_correct_workspace_bytes(kfb_state_t st, int32_t n_crc);
+int kfb_light_correction(kfb_state_t st, const void* X, int64_t ldx, const int32_t* col_idx, int32_t n_crc,
+                         void* workspace, size_t ws_bytes, kfb_stream_t stream);
 
 /* Host-side metadata: modes held, updates applied, sizes. Any pointer may be NULL. */
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,

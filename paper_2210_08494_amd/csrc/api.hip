@@ -656,6 +656,74 @@ int run_rsvd(const Rec* drecs, const UpdPlan& p, int64_t oZc, int r, int64_t ldx
   return KFB_OK;
 }
 
+// Light correction (Algorithm 6) of k modes on the chosen columns:
+//   U_c = U[:, idx];  M_S = U_c^T X U_c;  M_S = W L W^T;  U[:, idx] = U_c W,
+//   D[idx] = L;  modes re-sorted descending into the back buffers.
+// The small symmetric EVD runs as the core eigensolver on the Cholesky factor
+// R of M_S (M_S = R^T R), whose square factor's Gram it diagonalises.
+struct CorrPlan {
+  UpdPlan p;      // n = n_crc: U_c (oZ), X U_c (oZb), M_S (oGram), Cholesky, core
+  int64_t oUcw, oIdx, oSrc;
+  size_t per_problem;
+};
+
+template <int PR>
+int run_correct(const Rec* drecs, const CorrPlan& cp, int k, int64_t ldx, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::Z TZ; typedef typename T::P TP; typedef typename T::G TG;
+  typedef typename T::Core TC; typedef typename T::W TW; typedef typename T::D TD; typedef typename T::Acc TA;
+  const UpdPlan& p = cp.p;
+  const int64_t d = p.d;
+  const int nc = p.n;
+  {
+    StageTimer st("correct_project", s, 4);
+    GatherArgs ga;
+    ga.src_slot = U_FRONT; ga.lds = p.ldu; ga.d = d; ga.n = nc; ga.off_idx = cp.oIdx; ga.off_dst = p.oZ;
+    KFB_TRY(gather_cols<TU>(drecs, 1, ga, s));
+    // X U_c
+    GemmArgs g;
+    g.A = op(B_X, 0, 1, ldx); g.B = op(WS, p.oZ, 1, d); g.C = op(WS, p.oZb, 1, d);
+    g.m = (int)d; g.n = nc; g.k = (int)d;
+    KFB_TRY((mm<PR, 1, TU, TU, TZ, TZ, TA>(drecs, 1, g, s)));
+    // M_S = U_c^T (X U_c), accumulated in the Gram type
+    GemmArgs gs;
+    gs.A = op(WS, p.oZ, d, 1); gs.B = op(WS, p.oZb, 1, d); gs.C = op(WS, p.oGram, 1, nc);
+    gs.m = nc; gs.n = nc; gs.k = (int)d; gs.ksplit = p.ksG; gs.Part = op(WS, p.oPart, 1, nc);
+    KFB_TRY((gemm<TZ, TZ, TG, TG, TG>(drecs, 1, gs, s)));
+  }
+  {
+    StageTimer st("core", s, 4);
+    CholArgs ca;
+    const double ueps = sizeof(TG) == 4 ? 1.1920929e-07 : 2.220446049250313e-16;
+    ca.n = nc; ca.off_gram = p.oGram; ca.off_R = p.oR1; ca.off_Rinv = p.oX2; ca.off_rowbuf = 0;
+    ca.tau_rel = 64.0 * ueps; ca.shift_rel = 0.0;
+    KFB_TRY(chol_inv<TG>(drecs, 1, ca, s));
+    KFB_TRY((copy2d<TG, TG>(drecs, 1, op(WS, p.oX1, 1, nc), op(WS, p.oR1, nc, 1), nc, nc, s)));
+    CoreArgs co;
+    co.r = 0; co.n = nc; co.N = nc; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = -1;
+    co.off_R = p.oX1; co.off_B = p.oB; co.off_V = p.oV;
+    KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, 1, co, s)));
+    KFB_TRY(zero_words(drecs, 1, WS, p.oCnt, MAX_SWEEPS, s));
+  }
+  {
+    const int rc = core_evd<PR>(drecs, 1, p, s);
+    if (rc != KFB_OK) return rc;
+  }
+  StageTimer st("correct_write", s, 3);
+  // U_c W, then the merged, re-sorted modes into the back buffers
+  GemmArgs ro;
+  ro.A = op(WS, p.oZ, 1, d); ro.B = op(WS, p.oW, 1, nc); ro.C = op(WS, cp.oUcw, 1, d);
+  ro.m = (int)d; ro.n = nc; ro.k = nc;
+  KFB_TRY((mm<PR, 1, TZ, TW, TZ, TZ, TA>(drecs, 1, ro, s)));
+  MergeArgs ma;
+  ma.k = k; ma.n_crc = nc; ma.off_lam = p.oLam; ma.off_idx = cp.oIdx; ma.off_src = cp.oSrc;
+  KFB_TRY((correct_merge<TC, TD>(drecs, 1, ma, s)));
+  PermuteArgs pa;
+  pa.d = d; pa.ldu = p.ldu; pa.k = k; pa.off_src = cp.oSrc; pa.off_ucw = cp.oUcw;
+  KFB_TRY(correct_permute<TU>(drecs, 1, pa, s));
+  return KFB_OK;
+}
+
 inline int upd_r_eff(kfb_state_t st) { return st->k_valid < st->r ? st->k_valid : st->r; }
 
 int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, int64_t ldm, int32_t n,
@@ -928,6 +996,63 @@ int dispatch_rsvd(kfb_state_t st, const void* X, int64_t ldx, const void* Omega,
   return KFB_OK;
 }
 
+int dispatch_correct(kfb_state_t st, const void* X, int64_t ldx, const int32_t* col_idx, int n_crc,
+                     void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only) {
+  if (!st || n_crc < 1) return KFB_EINVAL;
+  const int k = st->k_valid;
+  const int rlead = st->r < k ? st->r : k;  // the columns Algorithm 6 draws from
+  if (k <= 0) return KFB_EEMPTY;
+  if (n_crc > rlead || k > 4096) return KFB_EINVAL;
+  CorrPlan cp;
+  bool ok = false;
+  if (st->prec == KFB_FP64) ok = make_upd_plan<KFB_FP64>(st->d, st->ldu, st->d, 0, n_crc, 1, &cp.p);
+  else if (st->prec == KFB_FP32) ok = make_upd_plan<KFB_FP32>(st->d, st->ldu, st->d, 0, n_crc, 1, &cp.p);
+  else ok = make_upd_plan<KFB_BF16_MIXED>(st->d, st->ldu, st->d, 0, n_crc, 1, &cp.p);
+  if (!ok) return KFB_EINVAL;
+  const size_t ze = st->prec == KFB_FP64 ? 8 : 4;
+  size_t o = cp.p.per_problem;
+  cp.oUcw = (int64_t)o; o = align256(o + (size_t)st->d * n_crc * ze);
+  cp.oIdx = (int64_t)o; o = align256(o + (size_t)n_crc * 4);
+  cp.oSrc = (int64_t)o; o = align256(o + (size_t)k * 4);
+  cp.per_problem = o;
+  const size_t head = align256(sizeof(Rec));
+  const size_t need = head + cp.per_problem;
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!X || !col_idx || !workspace || ldx < st->d) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  // host-side check of the draw: distinct indices among the leading modes
+  std::vector<char> seen((size_t)rlead, 0);
+  for (int t = 0; t < n_crc; ++t) {
+    const int j = col_idx[t];
+    if (j < 0 || j >= rlead || seen[(size_t)j]) return KFB_EINVAL;
+    seen[(size_t)j] = 1;
+  }
+  Rec host;
+  memset(&host, 0, sizeof(Rec));
+  host.p[U_FRONT] = st->buf + st->off_U[st->front];
+  host.p[U_BACK] = st->buf + st->off_U[1 - st->front];
+  host.p[WS] = (char*)workspace + head;
+  host.p[D_FRONT] = st->buf + st->off_D[st->front];
+  host.p[D_BACK] = st->buf + st->off_D[1 - st->front];
+  host.p[STATUS] = st->buf + st->off_status;
+  host.p[B_X] = const_cast<void*>(X);
+  host.s[0] = 0.0;
+  host.s[1] = 1.0;
+  Rec* dev = (Rec*)workspace;
+  if (upload_recs(&host, 1, dev, s) != hipSuccess) return KFB_EHIP;
+  if (hipMemcpyAsync((char*)workspace + head + cp.oIdx, col_idx, (size_t)n_crc * 4, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return KFB_EHIP;
+  int rc;
+  if (st->prec == KFB_FP64) rc = run_correct<KFB_FP64>(dev, cp, k, ldx, s);
+  else if (st->prec == KFB_FP32) rc = run_correct<KFB_FP32>(dev, cp, k, ldx, s);
+  else rc = run_correct<KFB_BF16_MIXED>(dev, cp, k, ldx, s);
+  if (rc != KFB_OK) return rc;
+  st->front = 1 - st->front;
+  return KFB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1102,6 +1227,17 @@ int kfb_rsvd_overwrite(kfb_state_t st, const void* X, int64_t ldx, const void* O
                        kfb_stream_t stream) {
   return dispatch_rsvd(st, X, ldx, Omega, ldo, oversample, power_its, workspace, ws_bytes, (hipStream_t)stream,
                        nullptr);
+}
+
+size_t kfb_correct_workspace_bytes(kfb_state_t st, int32_t n_crc) {
+  size_t need = 0;
+  if (dispatch_correct(st, nullptr, 0, nullptr, n_crc, nullptr, 0, nullptr, &need) != KFB_OK) return 0;
+  return need;
+}
+
+int kfb_light_correction(kfb_state_t st, const void* X, int64_t ldx, const int32_t* col_idx, int32_t n_crc,
+                         void* workspace, size_t ws_bytes, kfb_stream_t stream) {
+  return dispatch_correct(st, X, ldx, col_idx, n_crc, workspace, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,

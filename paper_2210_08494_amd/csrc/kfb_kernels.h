@@ -110,4 +110,29 @@ hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s)
 template <typename T>
 hipError_t sqrt_prefix(const Rec* recs, int nrec, int slot, int64_t off, int count, hipStream_t s);
 
+// ---- light correction (B-KFAC-C) ---------------------------------------------
+struct GatherArgs {
+  int src_slot;
+  int64_t lds, d;
+  int n;
+  int64_t off_idx, off_dst;  // in WS: n column indices (int32), d x n destination
+};
+template <typename T>
+hipError_t gather_cols(const Rec* recs, int nrec, const GatherArgs& a, hipStream_t s);
+
+struct MergeArgs {
+  int k, n_crc;
+  int64_t off_lam, off_idx, off_src;  // in WS: new eigenvalues (TC), chosen columns, source map (int32)
+};
+template <typename TC, typename TD>
+hipError_t correct_merge(const Rec* recs, int nrec, const MergeArgs& a, hipStream_t s);
+
+struct PermuteArgs {
+  int64_t d, ldu;
+  int k;
+  int64_t off_src, off_ucw;  // in WS: source map, corrected columns (d x n_crc)
+};
+template <typename T>
+hipError_t correct_permute(const Rec* recs, int nrec, const PermuteArgs& a, hipStream_t s);
+
 }  // namespace kfb

@@ -1794,9 +1794,18 @@ __global__ __launch_bounds__(256) void precond_coefs_kernel(const Rec* __restric
   const Rec& rec = recs[blockIdx.x];
   const TD* DG = at<const TD>(rec, PD_G, 0);
   const TD* DA = at<const TD>(rec, PD_A, 0);
-  double lamG = rec.s[0], lamA = rec.s[1];
-  __shared__ double mins[2];
+  __shared__ double mins[2], lams[2];
   if (threadIdx.x == 0) {
+    double lG0 = rec.s[0], lA0 = rec.s[1];
+    if (a.flags & KFB_RELATIVE_DAMPING) {  // lam = phi * lambda_max (Section 6)
+      double xG = 0.0, xA = 0.0;
+      for (int i = 0; i < a.kG; ++i) xG = fmax(xG, (double)DG[i]);
+      for (int i = 0; i < a.kA; ++i) xA = fmax(xA, (double)DA[i]);
+      lG0 = xG > 0.0 ? lG0 * xG : lG0;
+      lA0 = xA > 0.0 ? lA0 * xA : lA0;
+    }
+    lams[0] = lG0;
+    lams[1] = lA0;
     double mG = 0.0, mA = 0.0;
     if (a.flags & KFB_SPECTRUM_CONTINUATION) {
       mG = a.kG > 0 ? (double)DG[0] : 0.0;
@@ -1811,7 +1820,7 @@ __global__ __launch_bounds__(256) void precond_coefs_kernel(const Rec* __restric
   }
   __syncthreads();
   const double mG = mins[0], mA = mins[1];
-  const double lG = lamG + mG, lA = lamA + mA;
+  const double lG = lams[0] + mG, lA = lams[1] + mA;
   TAcc* cG = at<TAcc>(rec, PWS, a.off_cG);
   TAcc* cA = at<TAcc>(rec, PWS, a.off_cA);
   for (int i = threadIdx.x; i < a.kG; i += 256) {
@@ -1891,6 +1900,102 @@ hipError_t sqrt_prefix(const Rec* recs, int nrec, int slot, int64_t off, int cou
 }
 
 // ---------------------------------------------------------------------------
+// Light correction (B-KFAC-C) helpers
+// ---------------------------------------------------------------------------
+// dst(:, j) = src(:, idx[j]): d x n column gather into the workspace
+template <typename T>
+__global__ __launch_bounds__(256) void gather_cols_kernel(const Rec* __restrict__ recs, GatherArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const T* src = at<const T>(rec, a.src_slot, 0);
+  const int32_t* idx = at<const int32_t>(rec, WS, a.off_idx);
+  T* dst = at<T>(rec, WS, a.off_dst);
+  const int64_t tot = a.d * a.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e % a.d, j = e / a.d;
+    dst[e] = src[i + (int64_t)idx[j] * a.lds];
+  }
+}
+
+template <typename T>
+hipError_t gather_cols(const Rec* recs, int nrec, const GatherArgs& a, hipStream_t s) {
+  const int64_t tot = a.d * a.n;
+  if (tot <= 0 || nrec <= 0) return hipSuccess;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((gather_cols_kernel<T>), dim3(blocks, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// New eigenvalues of the k modes (the chosen ones from the small EVD, sorted
+// descending in lam), their stable descending order into D_BACK, and for each
+// output position its source: a front column (>= 0) or corrected column t
+// (-(t + 1)).  One workgroup per problem.
+constexpr int MERGE_MAXK = 4096;
+template <typename TC, typename TD>
+__global__ __launch_bounds__(256) void correct_merge_kernel(const Rec* __restrict__ recs, MergeArgs a) {
+  const Rec& rec = recs[blockIdx.x];
+  __shared__ double dv[MERGE_MAXK];
+  __shared__ int pos[MERGE_MAXK];
+  const TD* Din = at<const TD>(rec, D_FRONT, 0);
+  TD* Dout = at<TD>(rec, D_BACK, 0);
+  const TC* lam = at<const TC>(rec, WS, a.off_lam);
+  const int32_t* idx = at<const int32_t>(rec, WS, a.off_idx);
+  int32_t* src = at<int32_t>(rec, WS, a.off_src);
+  for (int j = threadIdx.x; j < a.k; j += 256) pos[j] = -1;
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.n_crc; t += 256) pos[idx[t]] = t;
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.k; j += 256) dv[j] = pos[j] >= 0 ? (double)lam[pos[j]] : (double)Din[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.k; j += 256) {
+    const double v = dv[j];
+    int rk = 0;
+    for (int i = 0; i < a.k; ++i) rk += (dv[i] > v) || (dv[i] == v && i < j);
+    Dout[rk] = TD(v);
+    src[rk] = pos[j] >= 0 ? -(pos[j] + 1) : j;
+  }
+}
+
+template <typename TC, typename TD>
+hipError_t correct_merge(const Rec* recs, int nrec, const MergeArgs& a, hipStream_t s) {
+  if (a.k > MERGE_MAXK || a.k <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((correct_merge_kernel<TC, TD>), dim3(nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// U_BACK(:, p) = front column src[p], or corrected column -src[p] - 1
+template <typename T>
+__global__ __launch_bounds__(256) void correct_permute_kernel(const Rec* __restrict__ recs, PermuteArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const T* Uf = at<const T>(rec, U_FRONT, 0);
+  const T* Uc = at<const T>(rec, WS, a.off_ucw);
+  const int32_t* src = at<const int32_t>(rec, WS, a.off_src);
+  T* Ub = at<T>(rec, U_BACK, 0);
+  const int64_t tot = a.d * a.k;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e % a.d, p = e / a.d;
+    const int sc = src[p];
+    Ub[i + p * a.ldu] = sc >= 0 ? Uf[i + (int64_t)sc * a.ldu] : Uc[i + (int64_t)(-sc - 1) * a.d];
+  }
+}
+
+template <typename T>
+hipError_t correct_permute(const Rec* recs, int nrec, const PermuteArgs& a, hipStream_t s) {
+  const int64_t tot = a.d * a.k;
+  if (tot <= 0 || nrec <= 0) return hipSuccess;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((correct_permute_kernel<T>), dim3(blocks, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template hipError_t gather_cols<double>(const Rec*, int, const GatherArgs&, hipStream_t);
+template hipError_t gather_cols<float>(const Rec*, int, const GatherArgs&, hipStream_t);
+template hipError_t correct_merge<double, double>(const Rec*, int, const MergeArgs&, hipStream_t);
+template hipError_t correct_merge<float, float>(const Rec*, int, const MergeArgs&, hipStream_t);
+template hipError_t correct_permute<double>(const Rec*, int, const PermuteArgs&, hipStream_t);
+template hipError_t correct_permute<float>(const Rec*, int, const PermuteArgs&, hipStream_t);
 template hipError_t sqrt_prefix<double>(const Rec*, int, int, int64_t, int, hipStream_t);
 template hipError_t sqrt_prefix<float>(const Rec*, int, int, int64_t, int, hipStream_t);
 template hipError_t chol_inv<double>(const Rec*, int, const CholArgs&, hipStream_t);

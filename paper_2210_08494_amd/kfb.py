@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkfb.so")
 
 KFB_FP64, KFB_FP32, KFB_BF16_MIXED = 0, 1, 2
-KFB_SPECTRUM_CONTINUATION, KFB_TRUNCATE_AFTER = 1, 2
+KFB_SPECTRUM_CONTINUATION, KFB_TRUNCATE_AFTER, KFB_RELATIVE_DAMPING = 1, 2, 4
 KFB_EV_NONFINITE, KFB_EV_CHOL_DEFICIENT, KFB_EV_JACOBI_MAXSWEEPS = 1, 2, 4
 KFB_JAC_STREAMED = 0x100
 ERRORS = {0: "KFB_OK", 1: "KFB_EINVAL", 2: "KFB_EWORKSPACE", 3: "KFB_EHIP", 4: "KFB_ESTATE",
@@ -54,6 +54,8 @@ _SIGS = {
     "kfb_dense_update": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, _sz, _vp]),
     "kfb_rsvd_workspace_bytes": (_sz, [_vp, _i32]),
     "kfb_rsvd_overwrite": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, _i32, _vp, _sz, _vp]),
+    "kfb_correct_workspace_bytes": (_sz, [_vp, _i32]),
+    "kfb_light_correction": (ctypes.c_int, [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _sz, _vp]),
     "kfb_state_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
@@ -343,6 +345,20 @@ def rsvd_overwrite(f: Factor, X, Omega, oversample: int, power_its: int, ws: Wor
     _check(lib.kfb_rsvd_overwrite(f.handle, _ptr(X), int(X.stride(0)), _ptr(Omega), int(Omega.stride(0)),
                                   int(oversample), int(power_its), _ptr(w), int(w.numel()), _stream()),
            "kfb_rsvd_overwrite")
+
+
+def light_correction(f: Factor, X, col_idx, ws: Workspace | None = None):
+    """B-KFAC-C (Algorithm 6): correct the modes col_idx (host ints) of f against the dense EA factor X."""
+    lib = load()
+    assert X.is_cuda and X.shape == (f.d, f.d) and X.stride(1) == 1 and X.dtype == _dtype_of(f.prec)
+    idx = [int(i) for i in col_idx]
+    arr = (_i32 * len(idx))(*idx)
+    need = lib.kfb_correct_workspace_bytes(f.handle, len(idx))
+    if need == 0:
+        raise KfbError("kfb_correct_workspace_bytes rejected the sizes")
+    w = (ws or f.ws).get(need)
+    _check(lib.kfb_light_correction(f.handle, _ptr(X), int(X.stride(0)), arr, len(idx), _ptr(w), int(w.numel()),
+                                    _stream()), "kfb_light_correction")
 
 
 def profile_enable(on: bool = True):

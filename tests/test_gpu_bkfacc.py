@@ -1,0 +1,121 @@
+"""GPU parity of B-KFAC-C (Algorithms 6 and 7) through the C-ABI.
+
+Every T_corct steps, after the B-update, n_crc = phi r of the leading modes
+(chosen at random, the same indices on both sides) are corrected against the
+dense EA factor of the step.  Checked against the FP64 oracle
+(oracle/correct.py on the same dense factor, Oracle-B for the updates): the
+state after every correction and every update (basis-invariant reconstruction
+error), orthonormality, descending eigenvalues.  Tolerances 1e-10 / 1e-5 /
+2e-2 for the FP64 / FP32 / BF16-mixed forms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_08494_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-5, 2: 2e-2}
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _to_dev(x, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=_dev(), dtype=dtype)
+
+
+def _front_np(f):
+    import torch
+    torch.cuda.synchronize()
+    U, D = f.front()
+    return U.double().cpu().numpy(), D.double().cpu().numpy()
+
+
+def _batch(cfg, k, side, n, d, prec):
+    x = synth.batch_for(cfg, k, side, n, d)
+    if prec == 1:
+        x = x.astype(np.float32).astype(np.float64)
+    if prec == 2:
+        x = synth.to_bf16_values(x)
+    return x
+
+
+def _trajectory(kfb, prec, d, r, n, phi, Tc, steps, cfg, side="A", rho=0.95):
+    import torch
+    mdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[prec]
+    f = kfb.Factor(d, r, n, rho, prec)
+    X = kfb.dense_factor(f)
+    ob = oracle.BrandFactor(d, r, rho)
+    E = None
+    n_crc = int(phi * r)
+    worst = dict(corr=0.0, upd=0.0, orth=0.0, gain=[])
+    for k in range(steps):
+        M = _batch(cfg, k, side, n, d, prec)
+        Md = _to_dev(M, mdt)
+        f.update(Md)
+        kfb.dense_update(f, X, Md, first=(k == 0))
+        ob.update(M.T)
+        E = oracle.ea_update(E, M.T, rho)
+        Ug, Dg = _front_np(f)
+        worst["upd"] = max(worst["upd"], oracle.e_rec_lowrank(Ug, Dg, ob.U, ob.D))
+        if k > 0 and k % Tc == 0:
+            idx = synth.correction_columns(cfg, k, min(r, len(ob.D)), n_crc)
+            kfb.light_correction(f, X, idx)
+            Xh = E if prec == 0 else X.double().cpu().numpy().T
+            before = np.linalg.norm(E - (ob.U * ob.D) @ ob.U.T)
+            U, D = oracle.light_correction(ob.U, ob.D, Xh, idx)
+            ob.overwrite(U, D)
+            Ug, Dg = _front_np(f)
+            assert np.all(np.diff(Dg) <= 0)
+            worst["corr"] = max(worst["corr"], oracle.e_rec_lowrank(Ug, Dg, U, D))
+            worst["orth"] = max(worst["orth"], oracle.e_orth(Ug))
+            worst["gain"].append(np.linalg.norm(E - (Ug * Dg) @ Ug.T) / before)
+    print(f"  worst {worst}", flush=True)
+    return f, worst
+
+
+def test_fp64_bkfacc_trajectory(kfb):
+    d, r, n, phi, Tc, steps = 256, 32, 32, 0.5, 3, 10
+    print(f"fp64 B-KFAC-C d={d} r={r} n={n} n_crc={int(phi * r)} T={Tc}", flush=True)
+    f, w = _trajectory(kfb, kfb.KFB_FP64, d, r, n, phi, Tc, steps, cfg=91)
+    assert w["corr"] <= TOL[0] and w["upd"] <= TOL[0] and w["orth"] <= TOL[0]
+    assert max(w["gain"]) <= 1.0 + 1e-12     # a correction never increases the error (Section 3.5)
+    assert f.status() == 0
+
+
+def test_fp32_bkfacc_trajectory(kfb):
+    d, r, n, phi, Tc, steps = 1024, 64, 64, 0.5, 2, 6
+    print(f"fp32 B-KFAC-C d={d} r={r} n={n}", flush=True)
+    f, w = _trajectory(kfb, kfb.KFB_FP32, d, r, n, phi, Tc, steps, cfg=92, side="G")
+    assert w["corr"] <= TOL[1] and w["upd"] <= TOL[1] and w["orth"] <= TOL[1]
+
+
+def test_mixed_bkfacc_headline_width(kfb):
+    d, r, n, phi, Tc, steps = 4096, 256, 256, 0.5, 2, 5
+    print(f"mixed B-KFAC-C d={d} r={r} n={n}", flush=True)
+    f, w = _trajectory(kfb, kfb.KFB_BF16_MIXED, d, r, n, phi, Tc, steps, cfg=93)
+    assert w["corr"] <= TOL[2] and w["upd"] <= TOL[2] and w["orth"] <= TOL[2]
+
+
+def test_correction_argument_errors(kfb):
+    import torch
+    lib = kfb.load()
+    d, r, n = 64, 8, 8
+    f = kfb.Factor(d, r, n, 0.95, kfb.KFB_FP64)
+    X = kfb.dense_factor(f)
+    assert lib.kfb_correct_workspace_bytes(f.handle, 2) == 0          # no modes yet
+    M = _to_dev(synth.batch_for(94, 0, "A", n, d), torch.float64)
+    f.update(M)
+    f.update(M)
+    kfb.dense_update(f, X, M, first=True)
+    assert lib.kfb_correct_workspace_bytes(f.handle, r + 1) == 0      # more than the leading r
+    for bad in ([1, 1], [0, r], [-1, 2]):
+        with pytest.raises(kfb.KfbError):
+            kfb.light_correction(f, X, bad)
+    kfb.light_correction(f, X, [3, 0, 5])
+    torch.cuda.synchronize()

@@ -43,7 +43,7 @@ def _loaded(kfb, b, r, n, prec, udt, ddt):
     return f
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 5])
 @pytest.mark.parametrize("nk", [12, 1, 37])
 def test_fp64_factored_equals_dense_definition(kfb, flags, nk):
     import torch
@@ -68,9 +68,11 @@ def test_fp64_factored_equals_dense_definition(kfb, flags, nk):
     if flags & 2:
         UG, DG, UA, DA = UG[:, :r], DG[:r], UA[:, :r], DA[:r]
     lgx, lax = lg, la
+    if flags & 4:   # relative damping: lam = phi * lambda_max of the modes used
+        lgx, lax = lg * DG.max(), la * DA.max()
     if flags & 1:
-        DG, lgx = oracle.spectrum_continuation(DG, lg)
-        DA, lax = oracle.spectrum_continuation(DA, la)
+        DG, lgx = oracle.spectrum_continuation(DG, lgx)
+        DA, lax = oracle.spectrum_continuation(DA, lax)
     XG, XA = (UG * DG) @ UG.T, (UA * DA) @ UA.T
     S_ref = oracle.precondition_dense(XG, XA, J, lgx, lax)
     Sg = S.cpu().numpy()

@@ -172,7 +172,7 @@ def _oracle_state(d, r, n, rho, steps, cfg, side):
     return b
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_fp64_precondition_on_loaded_state(kfb, flags):
     # the apply in isolation: both sides start from the same oracle-built state
     import torch
@@ -194,9 +194,11 @@ def test_fp64_precondition_on_loaded_state(kfb, flags):
     if flags & 2:
         UG, DG, UA, DA = UG[:, :r], DG[:r], UA[:, :r], DA[:r]
     lgx, lax = lg, la
+    if flags & 4:   # relative damping: lam = phi * lambda_max of the modes used
+        lgx, lax = lg * DG.max(), la * DA.max()
     if flags & 1:
-        DG, lgx = oracle.spectrum_continuation(DG, lg)
-        DA, lax = oracle.spectrum_continuation(DA, la)
+        DG, lgx = oracle.spectrum_continuation(DG, lgx)
+        DA, lax = oracle.spectrum_continuation(DA, lax)
     XG, XA = (UG * DG) @ UG.T, (UA * DA) @ UA.T
     S_ref = oracle.precondition_dense(XG, XA, G, lgx, lax)
     Sg = S.cpu().numpy()
