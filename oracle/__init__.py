@@ -25,7 +25,8 @@ rsvd      B-R-KFAC (Algorithm 5): the dense EA factor and the randomized SVD
 correct   B-KFAC-C (Algorithms 6 and 7): the light correction of a
           representation on randomly chosen modes against the EA factor.
 metrics   Basis-invariant comparisons (reconstruction, eigenvalues,
-          orthonormality, preconditioned-gradient error).
+          orthonormality, preconditioned-gradient error) and the error
+          metrics of the paper's numerical study (Section 4.2).
 """
 from .bprocess import DenseFactor, truncate_rank, sorted_eigh  # noqa: F401
 from .brand import BrandFactor, symmetric_brand  # noqa: F401
@@ -33,4 +34,5 @@ from .precond import (precondition_dense, lowrank_inverse_apply, precondition_lo
                       precondition_factored, spectrum_continuation)
 from .rsvd import ea_update, range_basis, rsvd, rsvd_overwrite  # noqa: F401
 from .correct import light_correction  # noqa: F401
-from .metrics import e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S  # noqa: F401
+from .metrics import (e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S,  # noqa: F401
+                      regularised_inverse_lowrank, e_inverse, e_angle)

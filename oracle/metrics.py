@@ -64,3 +64,29 @@ def e_S(S1, S2) -> float:
     S1 = np.asarray(S1, dtype=np.float64)
     S2 = np.asarray(S2, dtype=np.float64)
     return float(np.linalg.norm(S1 - S2) / np.linalg.norm(S2))
+
+
+# ----------------------------------------------------------------------------
+# The error metrics of the paper's numerical error study (Section 4.2): an
+# approximate algorithm against K-FAC holding the exact regularised inverse of
+# the current EA factors.
+# ----------------------------------------------------------------------------
+def regularised_inverse_lowrank(U, D, lam: float) -> np.ndarray:
+    """(U diag(D) U^T + lam I)^{-1} as a dense matrix (U orthonormal), spectral form."""
+    U = np.asarray(U, dtype=np.float64)
+    c = 1.0 / (np.asarray(D, dtype=np.float64) + lam) - 1.0 / lam
+    return (U * c[None, :]) @ U.T + np.eye(U.shape[0]) / lam
+
+
+def e_inverse(U, D, lam: float, E: np.ndarray, lam_ref: float) -> float:
+    """Metrics (1) and (2): || inv~ - inv_ref ||_F / || inv_ref ||_F with
+    inv_ref = (E + lam_ref I)^{-1} of the exact EA factor (dense solve)."""
+    ref = np.linalg.solve(E + lam_ref * np.eye(E.shape[0]), np.eye(E.shape[0]))
+    return float(np.linalg.norm(regularised_inverse_lowrank(U, D, lam) - ref) / np.linalg.norm(ref))
+
+
+def e_angle(S1, S2) -> float:
+    """Metric (4): 1 - cos of the angle between two steps (Frobenius inner product)."""
+    S1 = np.asarray(S1, dtype=np.float64)
+    S2 = np.asarray(S2, dtype=np.float64)
+    return float(1.0 - np.sum(S1 * S2) / (np.linalg.norm(S1) * np.linalg.norm(S2)))

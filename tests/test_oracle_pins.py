@@ -502,3 +502,28 @@ def test_light_correction_all_modes_is_rayleigh_ritz():
     lam, W = np.linalg.eigh(b.U.T @ E @ b.U)
     assert np.max(np.abs(D2 - lam[::-1])) <= 1e-13 * lam[-1]
     assert e_rec_lowrank(U2, D2, b.U @ W, lam) <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Error metrics of the numerical study (Section 4.2)
+# ----------------------------------------------------------------------------
+from oracle import regularised_inverse_lowrank, e_inverse, e_angle  # noqa: E402
+
+
+def test_error_metrics():
+    rng = np.random.default_rng(60)
+    d = 30
+    E = _psd(d, d, seed=61)
+    lam, V = sorted_eigh(E)
+    # the full eigendecomposition gives the exact inverse (scipy Cholesky solve as the reference)
+    inv = regularised_inverse_lowrank(V, lam, 0.3)
+    ref = cho_solve(cho_factor(E + 0.3 * np.eye(d)), np.eye(d))
+    assert np.linalg.norm(inv - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert e_inverse(V, lam, 0.3, E, 0.3) <= 1e-12
+    # a truncated representation has a strictly positive error, larger for a smaller rank
+    assert 0 < e_inverse(V[:, :20], lam[:20], 0.3, E, 0.3) < e_inverse(V[:, :5], lam[:5], 0.3, E, 0.3)
+    S = rng.standard_normal((5, 7))
+    assert abs(e_angle(S, 3.0 * S)) <= 1e-15 and abs(e_angle(S, -S) - 2.0) <= 1e-15
+    T = rng.standard_normal((5, 7))
+    T -= np.sum(T * S) / np.sum(S * S) * S
+    assert abs(e_angle(S, T) - 1.0) <= 1e-14
