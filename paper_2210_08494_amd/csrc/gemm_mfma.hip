@@ -359,12 +359,36 @@ __device__ __forceinline__ void fast_store(const f32x4* x, int t, __bf16* dst) {
   }
 }
 
+// XCD-aware tile order.  Workgroups go to the eight XCDs round-robin in
+// dispatch order and each XCD has its own L2, so the linear workgroup index is
+// remapped: XCD x takes a contiguous range of tiles, and within it the tiles
+// run in groups of GM tile rows (column by column inside a group), so the
+// workgroups resident on one XCD at a time share both their A row panels and
+// their B column panels through that XCD's L2.
+constexpr int XCDS = 8, TILE_GM = 8;
+__device__ __forceinline__ void xcd_tile(int nx, int ny, int nz, int* tm, int* tn, int* tz) {
+  const int total = nx * ny * nz;
+  const int lin = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const int q = total / XCDS, rmd = total % XCDS, x = lin % XCDS;
+  const int t = x * q + min(x, rmd) + lin / XCDS;
+  const int per = nx * ny;
+  *tz = t / per;
+  const int u = t - *tz * per;
+  const int in_group = TILE_GM * ny;
+  const int first = (u / in_group) * TILE_GM;
+  const int gsz = min(nx - first, TILE_GM);
+  const int v = u % in_group;
+  *tm = first + v % gsz;
+  *tn = v / gsz;
+}
+
 template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP>
 __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restrict__ recs, GemmArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 sA[2][128 * MLD];
   __shared__ __attribute__((aligned(16))) __bf16 sB[2][128 * MLD];
-  const Rec& rec = recs[blockIdx.z];
-  const int tm = blockIdx.x, tn = blockIdx.y;
+  int tm, tn, tz;
+  xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
+  const Rec& rec = recs[tz];
   const int t = threadIdx.x, w = t / 64, l = t % 64;
   const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
   constexpr bool swp = SWP;  // output column-major: issue (B^T A^T) so stores coalesce
