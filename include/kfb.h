@@ -74,7 +74,10 @@ enum kfb_flags {
 enum kfb_event {
   KFB_EV_NONFINITE = 1u,       /* a non-finite value reached the Gram of the residual */
   KFB_EV_CHOL_DEFICIENT = 2u,  /* a CholQR pivot was below tolerance: null directions dropped */
-  KFB_EV_JACOBI_MAXSWEEPS = 4u /* the core eigensolver hit its sweep limit */
+  KFB_EV_JACOBI_MAXSWEEPS = 4u, /* the core eigensolver hit its sweep limit */
+  KFB_EV_ORTHO_DRIFT = 8u        /* after an update, a column of U with a positive eigenvalue has a
+                                    squared norm off 1 by more than 1e-10 (FP64), 1e-4 (FP32) or
+                                    1e-3 (mixed): U has drifted from orthonormality */
 };
 
 /* Bytes of the state buffer for a factor of width d, truncation rank r and

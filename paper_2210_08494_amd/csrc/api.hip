@@ -377,8 +377,11 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   if (r == 0) ro.A = op(WS, oQ, 1, d);
   ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
   ro.m = (int)d; ro.n = N; ro.k = N;
-  StageTimer st_rot("rotate", s, 1);
+  StageTimer st_rot("rotate", s, 2);
   KFB_TRY((mm<PR, 1, TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
+  // drift detector on the new basis (column norms)
+  const double drift_tol = PR == KFB_FP64 ? 1e-10 : (PR == KFB_FP32 ? 1e-4 : 1e-3);
+  KFB_TRY((ortho_check<TU, TD>(drecs, nrec, U_BACK, D_BACK, d, ldu, N, drift_tol, s)));
   return KFB_OK;
 }
 

@@ -106,6 +106,13 @@ struct ScaleArgs {
 template <typename T, typename TS>
 hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s);
 
+// KFB_EV_ORTHO_DRIFT when a column j < ncols of the d x ncols matrix at
+// rec.p[slot] (leading dimension ld) with eigenvalue rec.p[dslot][j] > 0 has
+// |sum_i u_ij^2 - 1| > tol
+template <typename T, typename TD>
+hipError_t ortho_check(const Rec* recs, int nrec, int slot, int dslot, int64_t d, int64_t ld, int ncols, double tol,
+                       hipStream_t s);
+
 // x_i <- sqrt(max(x_i, 0)), i < count, for the vector at rec.p[slot] + off
 template <typename T>
 hipError_t sqrt_prefix(const Rec* recs, int nrec, int slot, int64_t off, int count, hipStream_t s);

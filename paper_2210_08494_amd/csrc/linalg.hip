@@ -1989,7 +1989,38 @@ hipError_t correct_permute(const Rec* recs, int nrec, const PermuteArgs& a, hipS
   return hipGetLastError();
 }
 
+// Drift detector: one wave per column, FP64 sum of squares
+// (columns of zero eigenvalue, left by a rank-deficient batch, are not checked)
+template <typename T, typename TD>
+__global__ __launch_bounds__(256) void ortho_check_kernel(const Rec* __restrict__ recs, int slot, int dslot,
+                                                          int64_t d, int64_t ld, int ncols, double tol) {
+  const Rec& rec = recs[blockIdx.y];
+  const int j = blockIdx.x * 4 + threadIdx.x / 64, l = threadIdx.x % 64;
+  if (j >= ncols || !((double)at<const TD>(rec, dslot, 0)[j] > 0.0)) return;
+  const T* u = at<const T>(rec, slot, 0) + (int64_t)j * ld;
+  double sum = 0.0;
+  for (int64_t i = l; i < d; i += 64) {
+    const double v = (double)u[i];
+    sum = fma(v, v, sum);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (l == 0 && !(fabs(sum - 1.0) <= tol)) atomicOr(at<uint32_t>(rec, STATUS, 0), (uint32_t)KFB_EV_ORTHO_DRIFT);
+}
+
+template <typename T, typename TD>
+hipError_t ortho_check(const Rec* recs, int nrec, int slot, int dslot, int64_t d, int64_t ld, int ncols, double tol,
+                       hipStream_t s) {
+  if (ncols <= 0 || nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL((ortho_check_kernel<T, TD>), dim3((ncols + 3) / 4, nrec), dim3(256), 0, s, recs, slot, dslot, d,
+                     ld, ncols, tol);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
+template hipError_t ortho_check<double, double>(const Rec*, int, int, int, int64_t, int64_t, int, double, hipStream_t);
+template hipError_t ortho_check<float, float>(const Rec*, int, int, int, int64_t, int64_t, int, double, hipStream_t);
+template hipError_t ortho_check<float, double>(const Rec*, int, int, int, int64_t, int64_t, int, double, hipStream_t);
 template hipError_t gather_cols<double>(const Rec*, int, const GatherArgs&, hipStream_t);
 template hipError_t gather_cols<float>(const Rec*, int, const GatherArgs&, hipStream_t);
 template hipError_t correct_merge<double, double>(const Rec*, int, const MergeArgs&, hipStream_t);

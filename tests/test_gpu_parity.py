@@ -399,3 +399,24 @@ def test_mixed_streamed_panel_headline_core(kfb, bw):
         assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
     finally:
         kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, r + n, 0)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_ortho_drift_is_reported(kfb, prec):
+    # a clean trajectory never sets the drift bit; a basis loaded with columns scaled by
+    # 1.01 (squared norms off by 0.02) carries the defect into the next update's basis
+    import torch
+    d, r, n, rho = 192, 16, 16, 0.95
+    mdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[prec]
+    udt = torch.float64 if prec == 0 else torch.float32
+    ddt = torch.float32 if prec == 1 else torch.float64
+    _announce(f"ortho drift prec={prec}")
+    f = kfb.Factor(d, r, n, rho, prec)
+    for k in range(6):
+        f.update(_to_dev(_batch(12, k, "A", n, d, prec=prec), mdt))
+    assert f.status() & kfb.KFB_EV_ORTHO_DRIFT == 0
+    b = _oracle_state(d, r, n, rho, 3, 13, "A")
+    g = kfb.Factor(d, r, n, rho, prec)
+    g.load_state(_to_dev(1.01 * b.U, udt), _to_dev(b.D, ddt), step=3)
+    g.update(_to_dev(_batch(13, 3, "A", n, d, prec=prec), mdt))
+    assert g.status() & kfb.KFB_EV_ORTHO_DRIFT
