@@ -52,6 +52,11 @@ struct CoreArgs {
   int r, n, N, Np;
   int64_t off_P, off_P2, off_R;  // P, P2: r x n col-major (TP); R: n x n col-major (TG)
   int64_t off_B, off_V;          // Np x Np col-major (TCore)
+  // optional pre-rotated new-direction block (off_preB >= 0): the trailing n
+  // columns of B and the trailing n x n block of V are taken from the converged
+  // B_R = sqrt(w) R^T V_R and V_R of a smaller eigensolve (preNp x preNp)
+  int64_t off_preB = -1, off_preV = -1;
+  int preNp = 0;
 };
 template <typename TCore, typename TP, typename TG, typename TD>
 hipError_t assemble_core(const Rec* recs, int nrec, const CoreArgs& a, hipStream_t s);

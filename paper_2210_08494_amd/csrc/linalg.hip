@@ -164,7 +164,7 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
 }
 
 
-// Blocked form of the same factorisation and inverse (n <= 256), in 32-wide
+// Blocked form of the same factorisation and inverse (n <= 272), in 32-wide
 // blocks with the block row of R staged in LDS.  Per block column: one wave
 // factors the diagonal block; the block row right of it is solved column by
 // column (R_JJ^T Y = R_J,rest); the trailing upper triangle takes the rank-32
@@ -172,7 +172,11 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
 // bottom-up: X_JJ = R_JJ^{-1}, X_J,rest = -X_JJ (R_J,rest X_rest,rest).  The
 // pivot rule, the shift and the zero rows are those of the column kernel;
 // only the order of the sums differs.
-constexpr int CB = 32, CHB_NT = 512, CHB_MAXN = 256;
+// n <= 272: the two staged block rows (2 CB (n + 4) values) and the static
+// arrays fit the 160 KB of LDS, and the inverse's column mapping below covers
+// the m <= n - CB <= 256 columns right of a block row
+constexpr int CB = 32, CHB_NT = 512, CHB_MAXN = 272;
+static_assert(CHB_MAXN - CB <= 256, "the inverse maps at most 256 columns onto the workgroup");
 
 template <typename T>
 __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restrict__ recs, CholArgs a) {
@@ -599,6 +603,8 @@ __global__ __launch_bounds__(256) void assemble_core_kernel(const Rec* __restric
   const TP* P = r > 0 ? at<const TP>(rec, WS, a.off_P) : nullptr;
   const TP* P2 = (r > 0 && a.off_P2 >= 0) ? at<const TP>(rec, WS, a.off_P2) : nullptr;
   const TG* R = at<const TG>(rec, WS, a.off_R);
+  const TCore* pB = a.off_preB >= 0 ? at<const TCore>(rec, WS, a.off_preB) : nullptr;
+  const TCore* pV = a.off_preV >= 0 ? at<const TCore>(rec, WS, a.off_preV) : nullptr;
   const int64_t tot = (int64_t)Np * Np;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -619,11 +625,13 @@ __global__ __launch_bounds__(256) void assemble_core_kernel(const Rec* __restric
           v = sw * pv;
         }
       } else if (q >= r) {
-        v = sw * TCore(R[(p - r) + (int64_t)(q - r) * n]);
+        v = pB ? pB[(i - r) + (int64_t)(j - r) * a.preNp] : sw * TCore(R[(p - r) + (int64_t)(q - r) * n]);
       }
     }
     Bm[e] = v;
-    Vm[e] = (i == j) ? TCore(1) : TCore(0);
+    TCore vv = (i == j) ? TCore(1) : TCore(0);
+    if (pV && i >= r && j >= r && i < N && j < N) vv = pV[(i - r) + (int64_t)(j - r) * a.preNp];
+    Vm[e] = vv;
   }
 }
 
