@@ -296,6 +296,35 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
       const int i = e % nbk, j = e / nbk;
       if (i <= j) R[(kb + i) + (int64_t)(kb + j) * n] = Dg[i][j];
     }
+    if (t >= CHB_NT - 64 && t - (CHB_NT - 64) < CB) {
+      // the last wave inverts the diagonal block (rows bottom-up, lane j holds
+      // column j) into X's diagonal block while the others solve the block row;
+      // zero pivots (dropped directions) give zero rows
+      const int j = t - (CHB_NT - 64);
+      const T rjj = Dg[j][j];
+      Di[0][j] = (j < nbk && rjj > T(0)) ? T(1) / rjj : T(0);
+      wave_sync();
+      T x[CB];
+#pragma unroll
+      for (int i = CB - 1; i >= 0; --i) {
+        x[i] = T(0);
+        if (i < nbk) {
+          const T dinv = Di[0][i];
+          T s0 = T(0), s1 = T(0);
+#pragma unroll
+          for (int k2 = i + 1; k2 < CB; ++k2)
+            if (k2 <= j && k2 < nbk) {
+              if (k2 & 1) s1 = fma(Dg[i][k2], x[k2], s1);
+              else s0 = fma(Dg[i][k2], x[k2], s0);
+            }
+          x[i] = (j == i) ? dinv : (j > i ? -(s0 + s1) * dinv : T(0));
+        }
+      }
+      if (j < nbk)
+#pragma unroll
+        for (int i = 0; i < CB; ++i)
+          if (i <= j) X[(kb + i) + (int64_t)(kb + j) * n] = x[i];
+    }
     // block row: for each column, forward substitution with Dg^T
     for (int c = t; c < m; c += CHB_NT) {
       T y[CB];
@@ -361,93 +390,81 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
     __syncthreads();
   }
 
-  // ---- inverse, block rows bottom-up
-  for (int kb = ((n - 1) / CB) * CB; kb >= 0; kb -= CB) {
-    const int nbk = min(CB, n - kb), c0 = kb + nbk, m = n - c0;
-    for (int e = t; e < CB * CB; e += CHB_NT) {
-      const int i = e % CB, j = e / CB;
-      Dg[i][j] = (i <= j && j < nbk) ? R[(kb + i) + (int64_t)(kb + j) * n] : T(0);
-      Di[i][j] = T(0);
-    }
-    const int m8 = ((m + 7) / 8) * 8;  // columns read by the 8-wide chunks (zero beyond m)
-#pragma unroll 4
-    for (int e = t; e < CB * m8; e += CHB_NT) {
-      const int i = e % CB, c = e / CB;
-      Pn[i * LDW + c] = (i < nbk && c < m) ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
-    }
-    __syncthreads();
-    if (t < CB) {  // Di = Dg^{-1} in registers: rows bottom-up, lane j holds column j
-      const int j = t;
-      {
-        const T rjj = Dg[j][j];
-        invrow[j] = (j < nbk && rjj > T(0)) ? T(1) / rjj : T(0);
-      }
-      wave_sync();
-      T x[CB];
-#pragma unroll
-      for (int i = CB - 1; i >= 0; --i) {
-        x[i] = T(0);
-        if (i < nbk) {
-          const T dinv = invrow[i];
-          T s0 = T(0), s1 = T(0);
-#pragma unroll
-          for (int k = i + 1; k < CB; ++k)
-            if (k <= j && k < nbk) {
-              if (k & 1) s1 = fma(Dg[i][k], x[k], s1);
-              else s0 = fma(Dg[i][k], x[k], s0);
-            }
-          x[i] = (j == i) ? dinv : (j > i ? -(s0 + s1) * dinv : T(0));
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < CB; ++i) Di[i][j] = j < nbk ? x[i] : T(0);
-    }
-    // T = R_J,rest X_rest,rest: item (column c, half h) sums 16 rows over k <= c;
-    // columns interleave over the waves so each wave gets short and long ones
-    const int c = 8 * ((t & 63) >> 1) + (t >> 6), h = t & 1;
-    T acc[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = T(0);
-    if (c < m) {
-      // column c of X below the block row, 8 rows per chunk, the next chunk in flight
-      const T* xc = X + c0 + (int64_t)(c0 + c) * n;
-      const int kend = c + 1;
-      T xa[8], xn[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) xa[q] = q < kend ? xc[q] : T(0);
-      for (int k0 = 0; k0 < kend; k0 += 8) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) xn[q] = (k0 + 8 + q < kend) ? xc[k0 + 8 + q] : T(0);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) acc[r] = fma(Pn[(16 * h + r) * LDW + k0 + q], xa[q], acc[r]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) xa[q] = xn[q];
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) Tb[(16 * h + r) * LDW + c] = acc[r];
-    }
-    __syncthreads();
-    for (int e = t; e < nbk * nbk; e += CHB_NT) {
-      const int i = e % nbk, j = e / nbk;
-      if (i <= j) X[(kb + i) + (int64_t)(kb + j) * n] = Di[i][j];
-    }
-    if (c < m) {  // X_J,c = -Di T_c, rows 16 h .. 16 h + 15
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 16 * h + r;
-        if (i >= nbk) continue;
-        T sum = T(0);
-        for (int s2 = i; s2 < nbk; ++s2) sum = fma(Di[i][s2], Tb[s2 * LDW + c], sum);
-        X[(kb + i) + (int64_t)(c0 + c) * n] = -sum;
-      }
-    }
-    __syncthreads();
-  }
   if (t == 0) {
     uint32_t ev = (deficient ? KFB_EV_CHOL_DEFICIENT : 0u) | (nonfinite ? KFB_EV_NONFINITE : 0u);
     if (ev) atomicOr(at<uint32_t>(rec, STATUS, 0), ev);
+  }
+}
+
+// The rest of R^{-1} (X), one workgroup per 32-column block cb: back
+// substitution over the block rows above it,
+//   X_ib,cb = -X_ib,ib (R_ib,(ib,cb] X_(ib,cb],cb),  ib = cb-1, ..., 0,
+// with the diagonal-block inverses X_ib,ib from the factorisation.  The
+// column block of X being built stays in LDS; each step stages the block row
+// of R it needs.  Column blocks are independent, so all of them run at once.
+constexpr int CHI_NT = 256;
+template <typename T>
+__global__ __launch_bounds__(CHI_NT) void chol_inv_cols_kernel(const Rec* __restrict__ recs, CholArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char chi_smem[];
+  const Rec& rec = recs[blockIdx.y];
+  const int n = a.n, cb = blockIdx.x, c0 = cb * CB;
+  if (cb == 0 || c0 >= n) return;  // the first block is its diagonal inverse only
+  const int nc = min(CB, n - c0), top = c0 + nc;  // rows 0 .. top-1 of the column block
+  const T* R = at<const T>(rec, WS, a.off_R);
+  T* X = at<T>(rec, WS, a.off_Rinv);
+  T* Xc = reinterpret_cast<T*>(chi_smem);  // top x CB (row-major: Xc[i * CB + c])
+  T* Rp = Xc + (size_t)top * CB;           // CB x (top - CB) block row of R (row-major)
+  __shared__ T Dv[CB][CB + 1];
+  __shared__ T Tt[CB][CB + 1];
+  const int t = threadIdx.x;
+  // the diagonal block of this column block
+  for (int e = t; e < nc * CB; e += CHI_NT) {
+    const int i = e / CB, c = e % CB;
+    Xc[(size_t)(c0 + i) * CB + c] = c < nc ? X[(c0 + i) + (int64_t)(c0 + c) * n] : T(0);
+  }
+  __syncthreads();
+  for (int ib = cb - 1; ib >= 0; --ib) {
+    const int i0 = ib * CB, k0 = i0 + CB, K = top - k0;  // columns k0 .. top-1 of the block row
+    for (int e = t; e < CB * K; e += CHI_NT) {  // R(i0 + i, k0 + k): 32 consecutive rows per column
+      const int i = e % CB, k = e / CB;
+      Rp[(size_t)i * K + k] = R[(i0 + i) + (int64_t)(k0 + k) * n];
+    }
+    for (int e = t; e < CB * CB; e += CHI_NT) {
+      const int i = e % CB, j = e / CB;
+      Dv[i][j] = X[(i0 + i) + (int64_t)(i0 + j) * n];
+    }
+    __syncthreads();
+    // T = R_ib,(ib,cb] X_(ib,cb],cb: thread (i, four columns)
+    {
+      const int i = t / 8, cq = 4 * (t % 8);
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      const T* rr = Rp + (size_t)i * K;
+      for (int k = 0; k < K; ++k) {
+        const T rv = rr[k];
+        const T* xr = Xc + (size_t)(k0 + k) * CB + cq;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fma(rv, xr[q], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Tt[i][cq + q] = acc[q];
+    }
+    __syncthreads();
+    {  // X_ib,cb = -Dv T (Dv upper triangular)
+      const int i = t / 8, cq = 4 * (t % 8);
+      T acc[4] = {T(0), T(0), T(0), T(0)};
+      for (int s2 = i; s2 < CB; ++s2) {
+        const T dv = Dv[i][s2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fma(dv, Tt[s2][cq + q], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Xc[(size_t)(i0 + i) * CB + cq + q] = -acc[q];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < c0 * CB; e += CHI_NT) {  // rows above the diagonal block
+    const int i = e % c0, c = e / c0;
+    if (c < nc) X[i + (int64_t)(c0 + c) * n] = Xc[(size_t)i * CB + c];
   }
 }
 
@@ -465,6 +482,17 @@ hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s)
       attr = true;
     }
     hipLaunchKernelGGL((chol_blocked_kernel<T>), dim3(nrec), dim3(CHB_NT), lds, s, recs, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.n <= CB) return e;
+    const int nbc = (a.n + CB - 1) / CB;
+    const size_t ilds = ((size_t)a.n * CB + (size_t)CB * (a.n - CB)) * sizeof(T);
+    static bool iattr = false;
+    if (!iattr) {
+      (void)hipFuncSetAttribute((const void*)chol_inv_cols_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(((size_t)CHB_MAXN * CB + (size_t)CB * (CHB_MAXN - CB)) * sizeof(T)));
+      iattr = true;
+    }
+    hipLaunchKernelGGL((chol_inv_cols_kernel<T>), dim3(nbc, nrec), dim3(CHI_NT), ilds, s, recs, a);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((chol_inv_kernel<T>), dim3(nrec), dim3(CHOL_NT), 0, s, recs, a);
