@@ -292,7 +292,11 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
     GemmArgs q;
     q.A = op(WS, srcZ, 1, d); q.B = op(WS, oX[pass & 1], 1, n); q.C = op(WS, dstZ, 1, d);
     q.m = (int)d; q.n = n; q.k = n;
-    KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
+    if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {
+      KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));  // Q = Z R^-1 on FP32 MFMA
+    } else {
+      KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
+    }
     const int64_t tmp = srcZ; srcZ = dstZ; dstZ = tmp;
   }
   *oQ_out = srcZ;  // the orthonormal Q after the last pass

@@ -561,6 +561,117 @@ hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// FP32 products on FP32 MFMA (v_mfma_f32_16x16x4f32): FP32 operands (B may be
+// FP64, rounded to FP32 on load, as the FMA engine does), FP32 accumulation.
+// 128 x 128 tiles of four waves (64 x 64 each), k in steps of 16 staged in LDS
+// (k-major rows, so a wave's fragment reads are consecutive words), the next
+// step's operands loaded while the current one is multiplied; XCD-aware tile
+// order; column-major outputs issue (B^T A^T) so the stores coalesce.  Plain
+// operands only (no segment split, no split-K).
+// ---------------------------------------------------------------------------
+constexpr int F32_BK = 16, F32_LD = 128 + 4;
+
+template <typename TB, typename TC0, bool SWP>
+__global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restrict__ recs, GemmArgs g) {
+  __shared__ float sA[2][F32_BK][F32_LD];
+  __shared__ float sB[2][F32_BK][F32_LD];
+  int tm, tn, tz;
+  xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
+  const Rec& rec = recs[tz];
+  const float* A = at<const float>(rec, g.A.slot, g.A.off);
+  const TB* B = at<const TB>(rec, g.B.slot, g.B.off);
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int m0 = tm * 128, n0 = tn * 128;
+  // staging: A element e = t + 256 q -> (row e % 128, k e / 128); B element -> (k e % 16, col e / 16)
+  float ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      const int ia = e % 128, ka = e / 128;
+      const int gi = m0 + ia, gk = k0 + ka;
+      ra[q] = (gi < g.m && gk < g.k) ? A[(int64_t)gi * g.A.rs + (int64_t)gk * g.A.cs] : 0.f;
+      const int kb = e % F32_BK, jb = e / F32_BK;
+      const int gj = n0 + jb, gkb = k0 + kb;
+      rb[q] = (gj < g.n && gkb < g.k) ? (float)B[(int64_t)gkb * g.B.rs + (int64_t)gj * g.B.cs] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      sA[buf][e / 128][e % 128] = ra[q];
+      sB[buf][e % F32_BK][e / F32_BK] = rb[q];
+    }
+  };
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < g.k; k0 += F32_BK) {
+    const bool more = k0 + F32_BK < g.k;
+    if (more) load(k0 + F32_BK);
+#pragma unroll
+    for (int ks = 0; ks < F32_BK / 4; ++ks) {
+      const int kr = 4 * ks + l / 16;
+      float af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        af[i] = sA[cur][kr][wm + 16 * i + (l % 16)];
+        bf[i] = sB[cur][kr][wn + 16 * i + (l % 16)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = SWP ? __builtin_amdgcn_mfma_f32_16x16x4f32(bf[j], af[i], acc[i][j], 0, 0, 0)
+                          : __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  float* C = at<float>(rec, g.C.slot, g.C.off);
+  const bool use_c0 = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
+  const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
+  const float alpha = (float)g.alpha;
+  const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi, gj;
+        if (SWP) { gi = m0 + wm + 16 * i + (l % 16); gj = n0 + wn + 16 * j + 4 * (l / 16) + v; }
+        else { gi = m0 + wm + 16 * i + 4 * (l / 16) + v; gj = n0 + wn + 16 * j + (l % 16); }
+        if (gi < g.m && gj < g.n) {
+          float val = alpha * acc[i][j][v];
+          if (C0) val += beta * to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+          C[gi * g.C.rs + gj * g.C.cs] = val;
+        }
+      }
+}
+
+template <typename TB, typename TC0>
+hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0 || nrec <= 0) return hipSuccess;
+  if (g.A.slot2 >= 0 || g.B.slot2 >= 0 || g.ksplit > 1) return hipErrorInvalidValue;
+  dim3 grid((g.m + 127) / 128, (g.n + 127) / 128, nrec);
+  if (g.C.rs == 1) hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, true>), grid, dim3(256), 0, s, recs, g);
+  else hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, false>), grid, dim3(256), 0, s, recs, g);
+  return hipGetLastError();
+}
+template hipError_t gemm_f32_mfma<double, float>(const Rec*, int, const GemmArgs&, hipStream_t);
+template hipError_t gemm_f32_mfma<float, float>(const Rec*, int, const GemmArgs&, hipStream_t);
+
 #define KFB_GEMM_BF16(TA, TB, TC, TC0, SP) \
   template hipError_t gemm_bf16<TA, TB, TC, TC0, SP>(const Rec*, int, const GemmArgs&, hipStream_t);
 // mixed-form update: projections (U FP32 split, M BF16 exact), residuals, rotation

@@ -17,6 +17,11 @@ hipError_t gemm(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
 template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
 hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
 
+// FP32 MFMA variant for FP32 products (A FP32, B FP32 or FP64 rounded to FP32,
+// C FP32; plain operands, no split-K).
+template <typename TB, typename TC0>
+hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
+
 // ---- small helpers ---------------------------------------------------------
 hipError_t upload_recs(const Rec* host, int nrec, Rec* dev, hipStream_t s);
 
