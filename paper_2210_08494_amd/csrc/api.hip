@@ -379,6 +379,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     GemmArgs z;
     z.A = op(U_FRONT, 0, 1, ldu); z.B = op(WS, p.oP, 1, r); z.C0 = op(M_IN, 0, 1, ldm);
     z.C = op(WS, p.oZ, 1, d); z.m = (int)d; z.n = n; z.k = r; z.alpha = -1.0; z.beta = 1.0;
+    z.aligned16 = (d % 4 == 0) && (r % 4 == 0);  // U columns (ldu: 256 B multiples), P columns (ld r)
     KFB_TRY((mm<PR, 1, TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
     // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
     GemmArgs g2 = g;
@@ -434,6 +435,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   if (r == 0) ro.A = op(WS, oQ, 1, d);
   ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
   ro.m = (int)d; ro.n = N; ro.k = N;
+  ro.aligned16 = (d % 4 == 0) && (N % 4 == 0);  // U, Q (ld d) and W (ld N) columns
   StageTimer st_rot("rotate", s, 2);
   KFB_TRY((mm<PR, 1, TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
   // drift detector on the new basis (column norms)

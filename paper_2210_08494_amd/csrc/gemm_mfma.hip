@@ -348,14 +348,20 @@ struct FastSrc {
   }
 };
 
-template <bool KC>
-__device__ __forceinline__ void fast_store(const f32x4* x, int t, __bf16* dst) {
+template <bool KC, bool LO = false>
+__device__ __forceinline__ void fast_store(const f32x4* x, int t, __bf16* dst, __bf16* dlo = nullptr) {
   const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
   typedef __attribute__((__vector_size__(8))) __bf16 v4b;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const f32x4 v = KC ? x[r] : f32x4{x[0][r], x[1][r], x[2][r], x[3][r]};  // row r, k = 4kb .. 4kb+3
-    *reinterpret_cast<v4b*>(&dst[fast_lds_off<KC>(4 * rb + r, 4 * kb)]) = __builtin_convertvector(v, v4b);
+    const int o = fast_lds_off<KC>(4 * rb + r, 4 * kb);
+    const v4b h = __builtin_convertvector(v, v4b);
+    *reinterpret_cast<v4b*>(&dst[o]) = h;
+    if constexpr (LO) {  // remainder term: x - hi, exact in FP32, rounded to BF16
+      const f32x4 rem = v - __builtin_convertvector(h, f32x4);
+      *reinterpret_cast<v4b*>(&dlo[o]) = __builtin_convertvector(rem, v4b);
+    }
   }
 }
 
@@ -382,10 +388,13 @@ __device__ __forceinline__ void xcd_tile(int nx, int ny, int nz, int* tm, int* t
   *tn = v / gsz;
 }
 
-template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP>
+template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP, bool SPL = false>
 __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restrict__ recs, GemmArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 sA[2][128 * MLD];
   __shared__ __attribute__((aligned(16))) __bf16 sB[2][128 * MLD];
+  // SPL: BF16 remainders of both operands (hi*hi + hi*lo + lo*hi, ~16 bits)
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[SPL ? 2 : 1][SPL ? 128 * MLD : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[SPL ? 2 : 1][SPL ? 128 * MLD : 8];
   int tm, tn, tz;
   xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
   const Rec& rec = recs[tz];
@@ -412,8 +421,8 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
   f32x4 fa[4], fb[4];
   A.load(0, fa);
   B.load(0, fb);
-  fast_store<AKC>(fa, t, sA[0]);
-  fast_store<BKC>(fb, t, sB[0]);
+  fast_store<AKC, SPL>(fa, t, sA[0], sAl[0]);
+  fast_store<BKC, SPL>(fb, t, sB[0], sBl[0]);
   __syncthreads();
   int cur = 0;
   for (int k0 = 0; k0 < g.k; k0 += MBK) {
@@ -422,26 +431,42 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
       A.load(k0 + MBK, fa);
       B.load(k0 + MBK, fb);
     }
-    bf16x8 af[4], bfr[4];
+    bf16x8 af[4], bfr[4], afl[4], bfl[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       af[i] = *reinterpret_cast<const bf16x8*>(&sA[cur][offA[i]]);
       bfr[i] = *reinterpret_cast<const bf16x8*>(&sB[cur][offB[i]]);
+      if constexpr (SPL) {
+        afl[i] = *reinterpret_cast<const bf16x8*>(&sAl[cur][offA[i]]);
+        bfl[i] = *reinterpret_cast<const bf16x8*>(&sBl[cur][offB[i]]);
+      }
     }
     if constexpr (!swp) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          if constexpr (SPL) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl[i], bfr[j], acc[i][j], 0, 0, 0);
+          }
+        }
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+          if constexpr (SPL) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfl[j], af[i], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], afl[i], acc[i][j], 0, 0, 0);
+          }
+        }
     }
     if (more) {
-      fast_store<AKC>(fa, t, sA[cur ^ 1]);
-      fast_store<BKC>(fb, t, sB[cur ^ 1]);
+      fast_store<AKC, SPL>(fa, t, sA[cur ^ 1], sAl[SPL ? cur ^ 1 : 0]);
+      fast_store<BKC, SPL>(fb, t, sB[cur ^ 1], sBl[SPL ? cur ^ 1 : 0]);
     }
     __syncthreads();
     cur ^= 1;
@@ -484,7 +509,7 @@ static int fast_orient(const OpRef& o, bool isa) {
   return one(o.rs2, o.cs2) == a ? a : -1;
 }
 
-template <typename TC, typename TC0>
+template <typename TC, typename TC0, bool SPL = false>
 static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s, hipError_t* err) {
   if (!g.aligned16 || g.ksplit > 1 || g.k <= 0 || g.k % MBK || g.m % 4 || g.n % 4) return false;
   const int ao = fast_orient(g.A, true), bo = fast_orient(g.B, false);
@@ -492,7 +517,7 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g, hipStre
   dim3 grid((g.m + 127) / 128, (g.n + 127) / 128, nrec);
   const bool swp = g.C.rs == 1;
 #define KFB_FAST(AK, BK, SW) \
-  hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW>), grid, dim3(MNT), 0, s, recs, g)
+  hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, SPL>), grid, dim3(MNT), 0, s, recs, g)
   if (swp) {
     if (ao && bo) KFB_FAST(true, true, true);
     else if (ao) KFB_FAST(true, false, true);
@@ -533,9 +558,9 @@ __global__ __launch_bounds__(256) void mfma_splitk_reduce(const Rec* __restrict_
 template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
 hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t s) {
   if (g0.m <= 0 || g0.n <= 0 || nrec <= 0) return hipSuccess;
-  if constexpr (SPLIT == 0 && sizeof(TA) == 4 && sizeof(TB) == 4 && sizeof(TC) == 4) {
+  if constexpr (sizeof(TA) == 4 && sizeof(TB) == 4 && sizeof(TC) == 4) {
     hipError_t e;
-    if (gemm_bf16_fast<TC, TC0>(recs, nrec, g0, s, &e)) return e;
+    if (gemm_bf16_fast<TC, TC0, SPLIT != 0>(recs, nrec, g0, s, &e)) return e;
   }
   GemmArgs g = g0;
   if (g.k < 0) g.k = 0;
