@@ -152,7 +152,8 @@ def serve_mixed_leg(torch, kfb, dev, args):
     ranks: widths w_0..w_24 drawn from {512, ..., 8192} (layer l: d_in = w_l,
     d_out = w_{l+1}), r per factor drawn from {64, ..., 512} and clamped to d - 256,
     n per update request drawn from {64, 128, 256}; 70% updates (uniform over layer
-    and factor), 30% preconditionings (uniform layer), BF16-mixed."""
+    and factor), 30% preconditionings (uniform layer), BF16-mixed.  Updates of one
+    factor shape but uneven batch widths are grouped by zero-padding to n_max."""
     import numpy as np
     from paper_2210_08494_amd import serve
     L = args.layers
@@ -163,7 +164,7 @@ def serve_mixed_leg(torch, kfb, dev, args):
     layers = [(widths[l], widths[l + 1], min(ranks[l], widths[l] - nmax), min(ranks[l], widths[l + 1] - nmax))
               for l in range(L)]
     srv = serve.Server(layers, n_max=nmax, rho=RHO, prec=kfb.KFB_BF16_MIXED, streams=4,
-                       byte_budget=24 << 30, max_group=48)
+                       byte_budget=24 << 30, max_group=48, pad_updates=True)
     pool = {}
     for l, (d_in, d_out, _, _) in enumerate(layers):
         for s_i, (side, d) in enumerate((("A", d_in), ("G", d_out))):
@@ -191,16 +192,17 @@ def serve_mixed_leg(torch, kfb, dev, args):
         return serve.PrecondRequest(l, grads[l], outs[l], LAM, LAM)
 
     res = {"widths": widths, "ranks": [(a, g) for (_, _, a, g) in layers]}
-    rate = 2000.0
-    srv.stats = serve.ServerStats()
-    wall, done = serve.poisson_run(srv, make, rate, args.serve_requests, seed=2024)
-    lat_ms = [1e3 * (r.t_done - r.t_arrival) for r in done]
-    upd = sum(1 for r in done if isinstance(r, serve.UpdateRequest))
-    res[f"{int(rate)}_req_per_s"] = {
-        "requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
-        "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
-        "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
-        "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
+    # an offered rate far above capacity (throughput) and one below it (latency)
+    for rate, nreq in ((2000.0, args.serve_requests), (150.0, max(args.serve_requests // 2, 1))):
+        srv.stats = serve.ServerStats()
+        wall, done = serve.poisson_run(srv, make, rate, nreq, seed=2024 + int(rate))
+        lat_ms = [1e3 * (r.t_done - r.t_arrival) for r in done]
+        upd = sum(1 for r in done if isinstance(r, serve.UpdateRequest))
+        res[f"{int(rate)}_req_per_s"] = {
+            "requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
+            "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
+            "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
+            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
     return res
 
 

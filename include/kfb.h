@@ -115,6 +115,21 @@ int kfb_brand_update_batched(int32_t count, kfb_state_t const* states, const voi
                              int64_t ldm, int32_t n, void* workspace, size_t ws_bytes,
                              kfb_stream_t stream);
 
+/* Grouped update of batches of uneven widths (one launch sequence for a
+ * group whose batches differ in n): batch i has widths[i] (1..n) real columns
+ * followed by zero columns up to n (the caller pads).  Each problem takes the
+ * weight of its own width, (1 - rho)/widths[i] (1/widths[i] on a first
+ * update), so the result is the exact update by the real columns; the
+ * padding's zero pivots in CholeskyQR are expected and not reported as rank
+ * deficiency.  The state then holds min(k_valid, r) + n modes, the padded
+ * ones with eigenvalue 0: they add nothing to the inverse and leave at the
+ * next truncation.  widths: HOST array of count values.  Workspace as
+ * kfb_update_batched_workspace_bytes(count, states, n).  KFB_EINVAL for a
+ * width outside 1..n. */
+int kfb_brand_update_batched_widths(int32_t count, kfb_state_t const* states, const void* const* Ms,
+                                    int64_t ldm, int32_t n, const int32_t* widths, void* workspace,
+                                    size_t ws_bytes, kfb_stream_t stream);
+
 /* Workspace bytes for kfb_precondition on this pair of states. */
 size_t kfb_precondition_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a);
 

@@ -789,7 +789,8 @@ int run_correct(const Rec* drecs, const CorrPlan& cp, int k, int64_t ldx, hipStr
 inline int upd_r_eff(kfb_state_t st) { return st->k_valid < st->r ? st->k_valid : st->r; }
 
 int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, int64_t ldm, int32_t n,
-                    void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only) {
+                    void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only,
+                    const int32_t* widths = nullptr) {
   if (count <= 0 || !sts) return KFB_EINVAL;
   kfb_state_t s0 = sts[0];
   if (!s0) return KFB_EINVAL;
@@ -817,6 +818,9 @@ int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, in
   if (!Ms || !workspace) return KFB_EINVAL;
   if (ws_bytes < need) return KFB_EWORKSPACE;
   if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  if (widths)
+    for (int i = 0; i < count; ++i)
+      if (widths[i] < 1 || widths[i] > n) return KFB_EINVAL;
   Rec* host = (Rec*)malloc(sizeof(Rec) * (size_t)count);
   if (!host) return KFB_EINVAL;
   for (int i = 0; i < count; ++i) {
@@ -831,8 +835,10 @@ int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, in
     rc->p[D_FRONT] = st->buf + st->off_D[st->front];
     rc->p[D_BACK] = st->buf + st->off_D[1 - st->front];
     rc->p[STATUS] = st->buf + st->off_status;
+    const int nw = widths ? widths[i] : n;                  // the batch's own width
     rc->s[0] = st->k_valid > 0 ? st->rho : 0.0;           // decay applied to the kept modes
-    rc->s[1] = st->k_valid > 0 ? (1.0 - st->rho) / n : 1.0 / n;  // batch weight w
+    rc->s[1] = st->k_valid > 0 ? (1.0 - st->rho) / nw : 1.0 / nw;  // batch weight w
+    rc->s[2] = widths ? (double)nw : 0.0;                 // columns >= nw are zero padding
   }
   Rec* dev = (Rec*)workspace;
   hipError_t he = upload_recs(host, count, dev, s);
@@ -1300,6 +1306,13 @@ size_t kfb_correct_workspace_bytes(kfb_state_t st, int32_t n_crc) {
 int kfb_light_correction(kfb_state_t st, const void* X, int64_t ldx, const int32_t* col_idx, int32_t n_crc,
                          void* workspace, size_t ws_bytes, kfb_stream_t stream) {
   return dispatch_correct(st, X, ldx, col_idx, n_crc, workspace, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+int kfb_brand_update_batched_widths(int32_t count, kfb_state_t const* states, const void* const* Ms,
+                                    int64_t ldm, int32_t n, const int32_t* widths, void* workspace,
+                                    size_t ws_bytes, kfb_stream_t stream) {
+  if (!widths) return KFB_EINVAL;
+  return dispatch_update(count, states, Ms, ldm, n, workspace, ws_bytes, (hipStream_t)stream, nullptr, widths);
 }
 
 int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, int32_t* r,

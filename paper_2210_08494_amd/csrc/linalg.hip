@@ -60,6 +60,9 @@ template <typename T>
 __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict__ recs, CholArgs a) {
   const Rec& rec = recs[blockIdx.x];
   const int n = a.n;
+  // columns at or beyond nreal are zero padding of the batch (a grouped update of
+  // uneven widths): their zero pivots are expected, not a rank deficiency
+  const int nreal = rec.s[2] > 0.0 ? (int)rec.s[2] : n;
   const T* Wg = at<const T>(rec, WS, a.off_gram);
   T* R = at<T>(rec, WS, a.off_R);
   T* X = at<T>(rec, WS, a.off_Rinv);
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
       R[j + (int64_t)k * n] = v;
       row[k] = v;
     }
-    if (!ok && t == 0) deficient = 1;
+    if (!ok && t == 0 && j < nreal) deficient = 1;
     __syncthreads();
     const int m = n - j - 1;
     if (ok && m > 0) {
@@ -183,6 +186,9 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
   extern __shared__ __attribute__((aligned(16))) unsigned char chb_smem[];
   const Rec& rec = recs[blockIdx.x];
   const int n = a.n;
+  // columns at or beyond nreal are zero padding of the batch (a grouped update of
+  // uneven widths): their zero pivots are expected, not a rank deficiency
+  const int nreal = rec.s[2] > 0.0 ? (int)rec.s[2] : n;
   const int LDW = ((n + 3) / 4) * 4 + 4;  // row stride of the staged block rows
   T* Pn = reinterpret_cast<T*>(chb_smem);  // CB x LDW: block row of R
   T* Tb = Pn + CB * LDW;                   // CB x LDW: R_J,rest X_rest,rest
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
             pvt[1] = ok ? T(1) / sp : T(0);
             okrow[j] = ok;
             invrow[j] = pvt[1];
-            if (!ok) deficient = 1;
+            if (!ok && kb + j < nreal) deficient = 1;
           }
           wave_sync();
           const T sp = pvt[0], inv = pvt[1];

@@ -33,6 +33,8 @@ _SIGS = {
     "kfb_update_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), _i32]),
     "kfb_brand_update_batched": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64, _i32,
                                                 _vp, _sz, _vp]),
+    "kfb_brand_update_batched_widths": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64, _i32,
+                                                       ctypes.POINTER(_i32), _vp, _sz, _vp]),
     "kfb_precondition_workspace_bytes": (_sz, [_vp, _vp]),
     "kfb_precondition": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _dbl, _dbl, _u32, _vp, _sz, _vp]),
     "kfb_precondition_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
@@ -251,6 +253,22 @@ def update_batched(factors, Ms, ws: Workspace):
     w = ws.get(need)
     _check(lib.kfb_brand_update_batched(cnt, hs, ms, int(Ms[0].stride(0)), n, _ptr(w), int(w.numel()),
                                         _stream()), "kfb_brand_update_batched")
+
+
+def update_batched_widths(factors, Ms, widths, ws: Workspace):
+    """Grouped update of batches padded with zero columns to a common n; widths[i] = real columns of Ms[i]."""
+    lib = load()
+    cnt = len(factors)
+    hs = (_vp * cnt)(*[f.handle.value for f in factors])
+    ms = (_vp * cnt)(*[m.data_ptr() for m in Ms])
+    ws_ = (_i32 * cnt)(*[int(x) for x in widths])
+    n = int(Ms[0].shape[0])
+    need = lib.kfb_update_batched_workspace_bytes(cnt, hs, n)
+    if need == 0:
+        raise KfbError("kfb_update_batched_workspace_bytes rejected the bucket")
+    w = ws.get(need)
+    _check(lib.kfb_brand_update_batched_widths(cnt, hs, ms, int(Ms[0].stride(0)), n, ws_, _ptr(w), int(w.numel()),
+                                               _stream()), "kfb_brand_update_batched_widths")
 
 
 def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):

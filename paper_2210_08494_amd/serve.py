@@ -20,6 +20,13 @@ Scheduling (host side; all arithmetic runs in the HIP library):
   are taken, arriving requests wait and are fused into larger groups when a
   slot frees (this is what lets throughput approach the grouped closed loop
   under load instead of flooding the device with groups of one);
+* with ``pad_updates``, updates of one factor shape (d, r) but uneven batch
+  widths share a bucket: each batch is padded with zero columns to the widest
+  batch of its group and the group runs as ``kfb_brand_update_batched_widths`` (each problem
+  weighted by its own width, so the result is the exact update by its real
+  columns; the padded modes carry eigenvalue 0).  This trades extra work per
+  update for far larger groups when widths vary; results are then no longer
+  bit-identical to a request run alone, only equal within rounding;
 * groups go round-robin onto several default-priority HIP streams, each first
   waiting on the completion events of the last operations on its states, so
   work on different states overlaps on the device while per-state order holds;
@@ -70,6 +77,7 @@ class _Group:
     ws: object
     nbytes: int
     t_issue: float = 0.0
+    keep: object = None   # padded batches, alive until the group completes
 
 
 @dataclass
@@ -87,13 +95,14 @@ class ServerStats:
 class Server:
     def __init__(self, layers, n_max: int, rho: float = 0.95, prec: int = kfb.KFB_BF16_MIXED,
                  streams: int = 4, byte_budget: int = 8 << 30, max_group: int = 64, device="cuda",
-                 max_inflight: int | None = None):
+                 max_inflight: int | None = None, pad_updates: bool = False):
         """layers: list of (d_in, d_out, r_A, r_G)."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.prec = prec
         self.n_max = n_max
+        self.pad_updates = bool(pad_updates)
         self.fa, self.fg = [], []
         for (d_in, d_out, r_a, r_g) in layers:
             self.fa.append(kfb.Factor(d_in, r_a, n_max, rho, prec, device=self.device))
@@ -188,6 +197,8 @@ class Server:
             f = self.factor(r.layer, r.side)
             info = f.info()
             r_eff = min(info["k_valid"], f.r)
+            if self.pad_updates:
+                return ("U", f.d, f.r, r_eff, self.n_max, f.d)
             return ("U", f.d, f.r, r_eff, int(r.M.shape[0]), int(r.M.stride(0)))
         fg, fa = self.fg[r.layer], self.fa[r.layer]
         kg, ka = fg.info()["k_valid"], fa.info()["k_valid"]
@@ -254,9 +265,22 @@ class Server:
                 self.hooks_before_issue(key[0], reqs, stream)
             ws = kfb.Workspace(self.device)
             ws.get(nbytes)
+            keep = None
             if key[0] == "U":
                 factors = [self.factor(r.layer, r.side) for r in reqs]
-                kfb.update_batched(factors, [r.M for r in reqs], ws)
+                if self.pad_updates:
+                    n = max(int(r.M.shape[0]) for r in reqs)   # pad to the widest batch of the group
+                    keep = []
+                    for r in reqs:
+                        if r.M.shape[0] == n and r.M.stride(0) == r.M.shape[1]:
+                            keep.append(r.M)
+                        else:
+                            Mp = torch.zeros((n, r.M.shape[1]), dtype=r.M.dtype, device=self.device)
+                            Mp[:r.M.shape[0]].copy_(r.M)
+                            keep.append(Mp)
+                    kfb.update_batched_widths(factors, keep, [int(r.M.shape[0]) for r in reqs], ws)
+                else:
+                    kfb.update_batched(factors, [r.M for r in reqs], ws)
                 self.stats.updates += len(reqs)
             else:
                 kfb.precondition_batched([self.fg[r.layer] for r in reqs], [self.fa[r.layer] for r in reqs],
@@ -270,7 +294,7 @@ class Server:
         for r in reqs:
             for f in self._states_of(r):
                 self.last_event[f.handle.value] = ev
-        self.inflight.append(_Group(key[0], reqs, stream, ev, ws, nbytes, time.perf_counter()))
+        self.inflight.append(_Group(key[0], reqs, stream, ev, ws, nbytes, time.perf_counter(), keep))
         self.inflight_bytes += nbytes
         self.stats.max_inflight_bytes = max(self.stats.max_inflight_bytes, self.inflight_bytes)
         self.stats.groups += 1

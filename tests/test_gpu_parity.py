@@ -420,3 +420,40 @@ def test_ortho_drift_is_reported(kfb, prec):
     g.load_state(_to_dev(1.01 * b.U, udt), _to_dev(b.D, ddt), step=3)
     g.update(_to_dev(_batch(13, 3, "A", n, d, prec=prec), mdt))
     assert g.status() & kfb.KFB_EV_ORTHO_DRIFT
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batched_uneven_widths_equal_unpadded(kfb, prec):
+    # batches of widths 40, 64, 25 zero-padded to 64 in one grouped call equal the
+    # same updates run alone at their own widths (the padded modes carry eigenvalue 0)
+    import torch
+    d, r, nmax, rho = 256, 32, 64, 0.95
+    widths = [40, 64, 25]
+    mdt = torch.float64 if prec == 0 else torch.bfloat16
+    tol = 1e-10 if prec == 0 else 1e-5
+    _announce(f"uneven widths prec={prec}")
+    padded = [kfb.Factor(d, r, nmax, rho, prec) for _ in widths]
+    alone = [kfb.Factor(d, r, nmax, rho, prec) for _ in widths]
+    ws = kfb.Workspace()
+    worst = 0.0
+    for k in range(4):
+        Ms, Mp = [], []
+        for i, w in enumerate(widths):
+            M = _batch(14, 4 * k + i, "A" if i % 2 else "G", w, d, prec=prec)
+            Md = _to_dev(M, mdt)
+            P = torch.zeros((nmax, d), dtype=mdt, device=_dev())
+            P[:w] = Md
+            Ms.append(Md)
+            Mp.append(P)
+        kfb.update_batched_widths(padded, Mp, widths, ws)
+        for f, Md in zip(alone, Ms):
+            f.update(Md)
+        for a, b in zip(padded, alone):
+            Ua, Da = _front_np(a)
+            Ub, Db = _front_np(b)
+            worst = max(worst, oracle.e_rec_lowrank(Ua, Da, Ub, Db))
+    _announce(f"  worst e_rec {worst:.3e}")
+    assert worst <= tol
+    for f in padded:
+        assert f.status() & kfb.KFB_EV_CHOL_DEFICIENT == 0
+        assert f.info()["k_valid"] == r + nmax
