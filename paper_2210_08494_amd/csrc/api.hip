@@ -178,7 +178,9 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
     // split depends on the problem's own shape only, never on its batch-mates
     const int tiles = ((m + 63) / 64) * ((nn + 63) / 64);
     int ks = 1;
-    while (tiles * ks < 512 && (k / (ks * 2)) >= 256) ks *= 2;
+    // enough workgroups for one problem alone (64 tile-splits); more splits only
+    // add partial-sum traffic, which a grouped call pays once per problem
+    while (tiles * ks < 64 && (k / (ks * 2)) >= 256) ks *= 2;
     return ks;
   };
   p->ksP = r > 0 ? ks_for(r, n, d) : 1;
@@ -266,12 +268,15 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
   int64_t dstZ = altZ;
   const int64_t oR[3] = {p.oR1, p.oR2, p.oR3}, oX[2] = {p.oX1, p.oX2};
   for (int pass = 0; pass < passes; ++pass) {
+    bool prepped = false;
     if constexpr (sizeof(TG) == 8) {
       if (d % 16 == 0) {  // upper blocks on FP64 MFMA
         GramArgs ga;
         ga.n = n; ga.ks = p.ksG; ga.kchunk = 0; ga.d = d;
         ga.off_Z = srcZ; ga.off_part = p.oPart; ga.off_gram = p.oGram;
+        ga.off_R = oR[pass]; ga.off_X = oX[pass & 1];  // the Cholesky's starting point
         KFB_TRY(gram_f64<TZ>(drecs, nrec, ga, s));
+        prepped = true;
       } else {
         GemmArgs gg;
         gg.A = op(WS, srcZ, d, 1); gg.B = op(WS, srcZ, 1, d); gg.C = op(WS, p.oGram, 1, n);
@@ -288,10 +293,12 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
     ca.n = n; ca.off_gram = p.oGram; ca.off_R = oR[pass]; ca.off_Rinv = oX[pass & 1]; ca.off_rowbuf = 0;
     ca.tau_rel = tau;
     ca.shift_rel = (fp32_chol && pass == 0) ? 11.0 * ((double)d * n + (double)n * (n + 1)) * ueps : 0.0;
+    ca.prepped = prepped ? 1 : 0;
     KFB_TRY(chol_inv<TG>(drecs, nrec, ca, s));
     GemmArgs q;
     q.A = op(WS, srcZ, 1, d); q.B = op(WS, oX[pass & 1], 1, n); q.C = op(WS, dstZ, 1, d);
     q.m = (int)d; q.n = n; q.k = n;
+    q.b_upper = 1;  // R^-1 is upper triangular
     if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {
       KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));  // Q = Z R^-1 on FP32 MFMA
     } else {
@@ -352,7 +359,7 @@ int core_evd(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s, bool f
   fa.N = N; fa.Np = p.Np; fa.max_sweeps = MAX_SWEEPS; fa.off_B = p.oB; fa.off_V = p.oV;
   fa.off_cnt = p.oCnt; fa.off_lam = p.oLam; fa.off_rank = p.oRank; fa.off_W = p.oW;
   {
-    StageTimer st_fin("finalize", s, 2);
+    StageTimer st_fin("finalize", s, 3);
     KFB_TRY((finalize_core<TC, TW, TD>(drecs, nrec, fa, s)));
   }
   return KFB_OK;

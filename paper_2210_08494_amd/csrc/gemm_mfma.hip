@@ -593,7 +593,8 @@ hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t 
 // (k-major rows, so a wave's fragment reads are consecutive words), the next
 // step's operands loaded while the current one is multiplied; XCD-aware tile
 // order; column-major outputs issue (B^T A^T) so the stores coalesce.  Plain
-// operands only (no segment split, no split-K).
+// operands only (no segment split, no split-K); with b_upper the k loop of a
+// tile stops at its last column (the skipped terms are exact zeros).
 // ---------------------------------------------------------------------------
 constexpr int F32_BK = 16, F32_LD = 128 + 4;
 
@@ -636,12 +637,14 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restric
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // an upper-triangular B contributes nothing below the tile's last column
+  const int kend = g.b_upper ? min(g.k, n0 + 128) : g.k;
   load(0);
   store(0);
   __syncthreads();
   int cur = 0;
-  for (int k0 = 0; k0 < g.k; k0 += F32_BK) {
-    const bool more = k0 + F32_BK < g.k;
+  for (int k0 = 0; k0 < kend; k0 += F32_BK) {
+    const bool more = k0 + F32_BK < kend;
     if (more) load(k0 + F32_BK);
 #pragma unroll
     for (int ks = 0; ks < F32_BK / 4; ++ks) {

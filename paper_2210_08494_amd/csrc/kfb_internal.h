@@ -56,6 +56,9 @@ struct GemmArgs {
   int64_t beta_off = 0;
   // caller's promise: every pointer of A, B, C0 and C is 16-byte aligned
   int32_t aligned16 = 0;
+  // caller's promise: B is upper triangular (B(k, j) = 0 for k > j), so a tile
+  // of columns [n0, n0 + 128) only needs k < n0 + 128 (FP32 MFMA kernel)
+  int32_t b_upper = 0;
 };
 
 template <typename T>

@@ -39,6 +39,9 @@ struct GramArgs {
   int n, ks, kchunk;
   int64_t d;
   int64_t off_Z, off_part, off_gram;  // in WS: Z, ks x n x n partials, n x n result
+  // optional (>= 0): the reduction also writes R = upper triangle of the result
+  // and X = 0 (n x n each), the starting point of the blocked Cholesky
+  int64_t off_R = -1, off_X = -1;
 };
 template <typename TZ>
 hipError_t gram_f64(const Rec* recs, int nrec, const GramArgs& a, hipStream_t s);
@@ -49,6 +52,7 @@ struct CholArgs {
   int64_t off_rowbuf;                  // n elements scratch
   double tau_rel;                      // pivot tolerance relative to max diagonal
   double shift_rel;                    // diagonal shift relative to trace(W) (shifted CholeskyQR)
+  int prepped = 0;                     // R = upper(W) and R^-1 = 0 already written (Gram reduction)
 };
 template <typename T>
 hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s);

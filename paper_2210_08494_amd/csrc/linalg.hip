@@ -28,6 +28,18 @@ template <> __device__ __forceinline__ float dev_rsqrt<float>(float x) {
 
 // Orders the LDS accesses of one wave (performed in program order) without a
 // workgroup barrier: keeps the compiler from moving them across this point.
+// value of x held by lane `lane` of the wave (lane a compile-time constant in
+// the unrolled loops that use it)
+__device__ __forceinline__ double lane_value(double x, int lane) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
   T* Tb = Pn + CB * LDW;                   // CB x LDW: R_J,rest X_rest,rest
   __shared__ T Dg[CB][CB + 1], Di[CB][CB + 1];
   __shared__ T red[CHB_NT / 64], redt[CHB_NT / 64];
-  __shared__ T rowb[CB], invrow[CB], pvt[2];
+  __shared__ T invrow[CB];
   __shared__ int okrow[CB];
   __shared__ int deficient, nonfinite;
   const T* Wg = at<const T>(rec, WS, a.off_gram);
@@ -216,7 +228,7 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
     tr += __shfl_xor(tr, off);
   }
   if ((t & 63) == 0) { red[t >> 6] = mx; redt[t >> 6] = tr; }
-  {  // R = upper triangle of W, X = 0; eight consecutive elements per thread, loads first
+  if (!a.prepped) {  // R = upper triangle of W, X = 0; eight consecutive elements per thread, loads first
     const int nn = n * n;
     for (int e0 = 8 * t; e0 < nn; e0 += 8 * CHB_NT) {
       T v[8];
@@ -262,40 +274,36 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
       Pn[i * LDW + c] = (i < nbk && c < m) ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
     }
     __syncthreads();
-    if (t < CB) {  // diagonal block in registers: lane k holds column k; row j shared through LDS
+    if (t < 64) {
+      // diagonal block in the registers of one wave: lane k holds column k; the
+      // pivot and row j of R are read from their lanes (no LDS round trips)
       const int k = t;
       T d[CB];
 #pragma unroll
-      for (int i = 0; i < CB; ++i) d[i] = Dg[i][k];
+      for (int i = 0; i < CB; ++i) d[i] = k < CB ? Dg[i][k] : T(0);
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         if (j < nbk) {
-          if (k == j) {
-            const T p = d[j];
-            const bool ok = p > tau && dmax > T(0);
-            const T sp = ok ? dev_sqrt(p) : T(0);
-            pvt[0] = sp;
-            pvt[1] = ok ? T(1) / sp : T(0);
+          const T p = lane_value(d[j], j);
+          const bool ok = p > tau && dmax > T(0);
+          const T sp = ok ? dev_sqrt(p) : T(0);
+          const T inv = ok ? T(1) / sp : T(0);
+          if (k == 0) {
             okrow[j] = ok;
-            invrow[j] = pvt[1];
+            invrow[j] = inv;
             if (!ok && kb + j < nreal) deficient = 1;
           }
-          wave_sync();
-          const T sp = pvt[0], inv = pvt[1];
-          const bool ok = okrow[j];
           if (k >= j) d[j] = (k == j) ? sp : d[j] * inv;  // row j of R
-          rowb[k] = d[j];
-          wave_sync();
 #pragma unroll
           for (int i = j + 1; i < CB; ++i) {
-            const T rji = rowb[i];  // R[j][i]
+            const T rji = lane_value(d[j], i);  // R[j][i]
             if (ok && i < nbk && k >= i) d[i] -= rji * d[j];
           }
-          wave_sync();
         }
       }
+      if (k < CB)
 #pragma unroll
-      for (int i = 0; i < CB; ++i) Dg[i][k] = d[i];
+        for (int i = 0; i < CB; ++i) Dg[i][k] = d[i];
     }
     __syncthreads();
     for (int e = t; e < nbk * nbk; e += CHB_NT) {
@@ -582,22 +590,44 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const Rec* __restrict__ r
       }
 }
 
+// Sums the split partials of the upper blocks in a fixed order.  With off_R >=
+// 0 the grid covers every 64 x 64 block: upper blocks also write R = upper(W)
+// and X = 0, blocks below the diagonal write zeros to both.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const Rec* __restrict__ recs, GramArgs a) {
   const Rec& rec = recs[blockIdx.z];
-  const int n = a.n;
-  int b = blockIdx.x, bj = 0;
-  while (b > bj) { b -= bj + 1; ++bj; }
-  const int bi = b;
+  const int n = a.n, nb = (n + 63) / 64;
+  const bool prep = a.off_R >= 0;
+  int bi, bj;
+  if (prep) {
+    bi = blockIdx.x % nb;
+    bj = blockIdx.x / nb;
+  } else {
+    int b = blockIdx.x;
+    bj = 0;
+    while (b > bj) { b -= bj + 1; ++bj; }
+    bi = b;
+  }
   const double* part = at<const double>(rec, WS, a.off_part);
   double* W = at<double>(rec, WS, a.off_gram);
+  double* R = prep ? at<double>(rec, WS, a.off_R) : nullptr;
+  double* X = prep ? at<double>(rec, WS, a.off_X) : nullptr;
   const int64_t nn = (int64_t)n * n;
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int i = 64 * bi + (e & 63), j = 64 * bj + (e >> 6);
     if (i >= n || j >= n) continue;
     const int64_t o = i + (int64_t)j * n;
+    if (bi > bj) {  // below the diagonal blocks (prep only)
+      R[o] = 0.0;
+      X[o] = 0.0;
+      continue;
+    }
     double s = 0.0;
     for (int kz = 0; kz < a.ks; ++kz) s += part[kz * nn + o];
     W[o] = s;
+    if (prep) {
+      R[o] = i <= j ? s : 0.0;
+      X[o] = 0.0;
+    }
   }
 }
 
@@ -612,7 +642,7 @@ hipError_t gram_f64(const Rec* recs, int nrec, const GramArgs& a0, hipStream_t s
   hipLaunchKernelGGL((gram_f64_kernel<TZ>), dim3(nblk, a.ks, nrec), dim3(256), 0, s, recs, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(nblk, 1, nrec), dim3(256), 0, s, recs, a);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.off_R >= 0 ? nb * nb : nblk, 1, nrec), dim3(256), 0, s, recs, a);
   return hipGetLastError();
 }
 template hipError_t gram_f64<float>(const Rec*, int, const GramArgs&, hipStream_t);
@@ -1738,41 +1768,47 @@ hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, 
 // same factor (visible in FP32); the eigenvalue estimate ||B_j||^2 / ||V_j||^2
 // cancels that factor and W takes the normalised columns of V.  Eigenvalues
 // are sorted descending (ties by column index); D and the permuted,
-// normalised W are written.
+// normalised W are written.  The column norms are formed by many workgroups
+// (one wave per column, the eigenvalue estimate stored unsorted in place),
+// then one workgroup per problem ranks them.
 // ---------------------------------------------------------------------------
 constexpr int FIN_MAXN = 4096;
+
+template <typename TCore>
+__global__ __launch_bounds__(256) void fin_norms_kernel(const Rec* __restrict__ recs, FinArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const int N = a.N, Np = a.Np;
+  const int j = 4 * blockIdx.x + threadIdx.x / 64, ln = threadIdx.x % 64;
+  if (j >= N) return;
+  const TCore* col = at<const TCore>(rec, WS, a.off_B) + (int64_t)j * Np;
+  const TCore* vc = at<const TCore>(rec, WS, a.off_V) + (int64_t)j * Np;
+  TCore* lam = at<TCore>(rec, WS, a.off_lam);
+  TCore sb = TCore(0), sv = TCore(0);
+  for (int i = ln; i < Np; i += 64) {
+    sb = fma(col[i], col[i], sb);
+    sv = fma(vc[i], vc[i], sv);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sb += __shfl_xor(sb, off);
+    sv += __shfl_xor(sv, off);
+  }
+  if (ln == 0) {
+    const bool ok = sv > TCore(0);
+    lam[j] = ok ? sb / sv : sb;                          // unsorted estimate
+    lam[Np + j] = ok ? TCore(1) / dev_sqrt(sv) : TCore(1);  // 1 / ||V_j||
+  }
+}
 
 template <typename TCore, typename TD>
 __global__ __launch_bounds__(256) void fin_sort_kernel(const Rec* __restrict__ recs, FinArgs a) {
   const Rec& rec = recs[blockIdx.x];
-  const int N = a.N, Np = a.Np;
-  const TCore* Bm = at<const TCore>(rec, WS, a.off_B);
-  const TCore* Vm = at<const TCore>(rec, WS, a.off_V);
+  const int N = a.N;
   TCore* lam = at<TCore>(rec, WS, a.off_lam);
-  TCore* vscale = lam + Np;
   int32_t* rank = at<int32_t>(rec, WS, a.off_rank);
   TD* Dout = at<TD>(rec, D_BACK, 0);
   __shared__ TCore sl[FIN_MAXN];
-  const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
-  for (int j = wv; j < N; j += 4) {
-    const TCore* col = Bm + (int64_t)j * Np;
-    const TCore* vc = Vm + (int64_t)j * Np;
-    TCore sb = TCore(0), sv = TCore(0);
-    for (int i = ln; i < Np; i += 64) {
-      sb = fma(col[i], col[i], sb);
-      sv = fma(vc[i], vc[i], sv);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      sb += __shfl_xor(sb, off);
-      sv += __shfl_xor(sv, off);
-    }
-    if (ln == 0) {
-      const bool ok = sv > TCore(0);
-      sl[j] = ok ? sb / sv : sb;
-      vscale[j] = ok ? TCore(1) / dev_sqrt(sv) : TCore(1);
-    }
-  }
-  __syncthreads();
+  for (int j = threadIdx.x; j < N; j += 256) sl[j] = lam[j];
+  __syncthreads();  // every estimate is read before the sorted ones overwrite them
   for (int j = threadIdx.x; j < N; j += 256) {
     const TCore v = sl[j];
     int rk = 0;
@@ -1809,8 +1845,11 @@ __global__ __launch_bounds__(256) void fin_gather_kernel(const Rec* __restrict__
 template <typename TCore, typename TW, typename TD>
 hipError_t finalize_core(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s) {
   if (a.N > FIN_MAXN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fin_sort_kernel<TCore, TD>), dim3(nrec), dim3(256), 0, s, recs, a);
+  hipLaunchKernelGGL((fin_norms_kernel<TCore>), dim3((a.N + 3) / 4, nrec), dim3(256), 0, s, recs, a);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fin_sort_kernel<TCore, TD>), dim3(nrec), dim3(256), 0, s, recs, a);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = (int64_t)a.N * a.N;
   int blocks = (int)((tot + 255) / 256);
