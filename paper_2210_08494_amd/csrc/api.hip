@@ -159,7 +159,7 @@ struct UpdPlan {
 // large enough for the eigensolver's cost to matter.
 // The block solve is only a preconditioner (any orthogonal V_R is correct), so
 // it stops after PRE_SWEEPS sweeps: more buys no further reduction.
-constexpr int PRE_MIN_N = 128, PRE_SWEEPS = 4;
+constexpr int PRE_MIN_N = 128, PRE_SWEEPS = 5;
 
 template <int PR>
 bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, UpdPlan* p) {

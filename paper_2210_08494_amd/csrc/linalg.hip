@@ -183,10 +183,11 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
 // blocks with the block row of R staged in LDS.  Per block column: one wave
 // factors the diagonal block; the block row right of it is solved column by
 // column (R_JJ^T Y = R_J,rest); the trailing upper triangle takes the rank-32
-// update in 4 x 4 register blocks.  The inverse runs over block rows
-// bottom-up: X_JJ = R_JJ^{-1}, X_J,rest = -X_JJ (R_J,rest X_rest,rest).  The
-// pivot rule, the shift and the zero rows are those of the column kernel;
-// only the order of the sums differs.
+// update in 4 x 4 register blocks.  The inverse follows in two launches: the
+// diagonal blocks X_JJ = R_JJ^{-1} (one wave each), then the block rows
+// X_J,rest = -X_JJ (R_J,rest X_rest,rest) by column blocks.  The pivot rule,
+// the shift and the zero rows are those of the column kernel; only the order
+// of the sums differs.
 // n <= 272: the two staged block rows (2 CB (n + 4) values) and the static
 // arrays fit the 160 KB of LDS, and the inverse's column mapping below covers
 // the m <= n - CB <= 256 columns right of a block row
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
   const int LDW = ((n + 3) / 4) * 4 + 4;  // row stride of the staged block rows
   T* Pn = reinterpret_cast<T*>(chb_smem);  // CB x LDW: block row of R
   T* Tb = Pn + CB * LDW;                   // CB x LDW: R_J,rest X_rest,rest
-  __shared__ T Dg[CB][CB + 1], Di[CB][CB + 1];
+  __shared__ T Dg[CB][CB + 1];
   __shared__ T red[CHB_NT / 64], redt[CHB_NT / 64];
   __shared__ T invrow[CB];
   __shared__ int okrow[CB];
@@ -275,69 +276,61 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
     }
     __syncthreads();
     if (t < 64) {
-      // diagonal block in the registers of one wave: lane k holds column k; the
-      // pivot and row j of R are read from their lanes (no LDS round trips)
-      const int k = t;
-      T d[CB];
+      // diagonal block, right-looking on its upper triangle: lane (ti, tk) holds
+      // the 4 x 4 tile of rows 4 ti.., columns 4 tk..; at step j the pivot comes
+      // from its lane and the pieces of row j from the lanes of tile row j / 4
+      // by cross-lane reads (a rolled loop: the unrolled form overflows the
+      // instruction cache)
+      const int ti = t & 7, tk = t >> 3;
+      T a4[4][4];
 #pragma unroll
-      for (int i = 0; i < CB; ++i) d[i] = k < CB ? Dg[i][k] : T(0);
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        if (j < nbk) {
-          const T p = lane_value(d[j], j);
-          const bool ok = p > tau && dmax > T(0);
-          const T sp = ok ? dev_sqrt(p) : T(0);
-          const T inv = ok ? T(1) / sp : T(0);
-          if (k == 0) {
-            okrow[j] = ok;
-            invrow[j] = inv;
-            if (!ok && kb + j < nreal) deficient = 1;
-          }
-          if (k >= j) d[j] = (k == j) ? sp : d[j] * inv;  // row j of R
+        for (int c = 0; c < 4; ++c) a4[r][c] = Dg[4 * ti + r][4 * tk + c];
+      for (int j = 0; j < nbk; ++j) {
+        const int jt = j >> 2, jr = j & 3;
+        T v[4];  // row jr of this lane's tile
 #pragma unroll
-          for (int i = j + 1; i < CB; ++i) {
-            const T rji = lane_value(d[j], i);  // R[j][i]
-            if (ok && i < nbk && k >= i) d[i] -= rji * d[j];
-          }
+        for (int c = 0; c < 4; ++c) v[c] = jr == 0 ? a4[0][c] : jr == 1 ? a4[1][c] : jr == 2 ? a4[2][c] : a4[3][c];
+        T vi[4], vk[4];  // row j at this lane's rows (tile (jt, ti)) and columns (tile (jt, tk))
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          vi[q] = __shfl(v[q], jt + 8 * ti, 64);
+          vk[q] = __shfl(v[q], jt + 8 * tk, 64);
         }
-      }
-      if (k < CB)
+        const T p = lane_value(jr == 0 ? v[0] : jr == 1 ? v[1] : jr == 2 ? v[2] : v[3], 9 * jt);
+        const bool ok = p > tau && dmax > T(0);
+        const T inv = ok ? dev_rsqrt(p) : T(0);
+        const T sp = ok ? p * inv : T(0);
+        T ri[4], rk[4];  // R[j][i] for this lane's rows below j, R[j][k] for its columns
 #pragma unroll
-        for (int i = 0; i < CB; ++i) Dg[i][k] = d[i];
+        for (int q = 0; q < 4; ++q) {
+          const int i = 4 * ti + q, k = 4 * tk + q;
+          ri[q] = i > j ? vi[q] * inv : T(0);
+          rk[q] = k > j ? vk[q] * inv : (k == j ? sp : T(0));
+        }
+        if (t == 0) {
+          okrow[j] = ok;
+          invrow[j] = inv;
+          if (!ok && kb + j < nreal) deficient = 1;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            a4[r][c] = fma(-ri[r], rk[c], a4[r][c]);
+            if (ti == jt && r == jr) a4[r][c] = rk[c];  // row j of R
+          }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Dg[4 * ti + r][4 * tk + c] = 4 * ti + r <= 4 * tk + c ? a4[r][c] : T(0);
     }
     __syncthreads();
     for (int e = t; e < nbk * nbk; e += CHB_NT) {
       const int i = e % nbk, j = e / nbk;
       if (i <= j) R[(kb + i) + (int64_t)(kb + j) * n] = Dg[i][j];
-    }
-    if (t >= CHB_NT - 64 && t - (CHB_NT - 64) < CB) {
-      // the last wave inverts the diagonal block (rows bottom-up, lane j holds
-      // column j) into X's diagonal block while the others solve the block row;
-      // zero pivots (dropped directions) give zero rows
-      const int j = t - (CHB_NT - 64);
-      const T rjj = Dg[j][j];
-      Di[0][j] = (j < nbk && rjj > T(0)) ? T(1) / rjj : T(0);
-      wave_sync();
-      T x[CB];
-#pragma unroll
-      for (int i = CB - 1; i >= 0; --i) {
-        x[i] = T(0);
-        if (i < nbk) {
-          const T dinv = Di[0][i];
-          T s0 = T(0), s1 = T(0);
-#pragma unroll
-          for (int k2 = i + 1; k2 < CB; ++k2)
-            if (k2 <= j && k2 < nbk) {
-              if (k2 & 1) s1 = fma(Dg[i][k2], x[k2], s1);
-              else s0 = fma(Dg[i][k2], x[k2], s0);
-            }
-          x[i] = (j == i) ? dinv : (j > i ? -(s0 + s1) * dinv : T(0));
-        }
-      }
-      if (j < nbk)
-#pragma unroll
-        for (int i = 0; i < CB; ++i)
-          if (i <= j) X[(kb + i) + (int64_t)(kb + j) * n] = x[i];
     }
     // block row: for each column, forward substitution with Dg^T
     for (int c = t; c < m; c += CHB_NT) {
@@ -408,6 +401,49 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
     uint32_t ev = (deficient ? KFB_EV_CHOL_DEFICIENT : 0u) | (nonfinite ? KFB_EV_NONFINITE : 0u);
     if (ev) atomicOr(at<uint32_t>(rec, STATUS, 0), ev);
   }
+}
+
+// X_JJ = R_JJ^{-1} for every 32 x 32 diagonal block J (one wave each): lane j
+// back-substitutes column j bottom-up in registers (R_JJ staged in LDS); a
+// zero pivot (dropped direction) gives a zero row.
+template <typename T>
+__global__ __launch_bounds__(64) void chol_diag_inv_kernel(const Rec* __restrict__ recs, CholArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const int n = a.n, b0 = blockIdx.x * CB;
+  if (b0 >= n) return;
+  const int nb = min(CB, n - b0);
+  const T* R = at<const T>(rec, WS, a.off_R);
+  T* X = at<T>(rec, WS, a.off_Rinv);
+  __shared__ T Rd[CB][CB + 1];
+  __shared__ T dinv[CB];
+  const int j = threadIdx.x;
+  for (int e = j; e < CB * CB; e += 64) {
+    const int i = e % CB, c = e / CB;
+    Rd[i][c] = (i <= c && c < nb) ? R[(b0 + i) + (int64_t)(b0 + c) * n] : T(0);
+  }
+  __syncthreads();
+  if (j < CB) dinv[j] = Rd[j][j] > T(0) ? T(1) / Rd[j][j] : T(0);
+  __syncthreads();
+  if (j >= CB) return;
+  T x[CB];
+#pragma unroll
+  for (int i = CB - 1; i >= 0; --i) {
+    x[i] = T(0);
+    if (i < nb) {
+      T s0 = T(0), s1 = T(0);  // two partial sums shorten the dependent chain
+#pragma unroll
+      for (int k = i + 1; k < CB; ++k)
+        if (k <= j && k < nb) {
+          if (k & 1) s1 = fma(Rd[i][k], x[k], s1);
+          else s0 = fma(Rd[i][k], x[k], s0);
+        }
+      x[i] = (j == i) ? dinv[i] : (j > i ? -(s0 + s1) * dinv[i] : T(0));
+    }
+  }
+  if (j < nb)
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+      if (i <= j) X[(b0 + i) + (int64_t)(b0 + j) * n] = x[i];
 }
 
 // The rest of R^{-1} (X), one workgroup per 32-column block cb: back
@@ -497,6 +533,9 @@ hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s)
     }
     hipLaunchKernelGGL((chol_blocked_kernel<T>), dim3(nrec), dim3(CHB_NT), lds, s, recs, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((chol_diag_inv_kernel<T>), dim3((a.n + CB - 1) / CB, nrec), dim3(64), 0, s, recs, a);
+    e = hipGetLastError();
     if (e != hipSuccess || a.n <= CB) return e;
     const int nbc = (a.n + CB - 1) / CB;
     const size_t ilds = ((size_t)a.n * CB + (size_t)CB * (a.n - CB)) * sizeof(T);
