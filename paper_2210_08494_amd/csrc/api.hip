@@ -394,6 +394,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
     GemmArgs g2 = g;
     g2.B = op(WS, p.oZ, 1, d); g2.C = op(WS, p.oP2, 1, r);
+    g2.aligned16 = (d % 4 == 0) && (r % 4 == 0);  // U and Z columns (the result goes through split-K)
     KFB_TRY((mm<PR, 1, TU, TZ, TP, TP, TP>(drecs, nrec, g2, s)));
     GemmArgs z2 = z;
     z2.B = op(WS, p.oP2, 1, r); z2.C0 = op(WS, p.oZ, 1, d);
@@ -512,6 +513,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   GemmArgs g3;
   g3.A = op(PWS, p.oT1, dA, 1); g3.B = op(PU_A, 0, 1, p.lduA); g3.C = op(PWS, p.oT3, 1, NG);
   g3.m = NG; g3.n = NA; g3.k = (int)dA; g3.ksplit = p.ks3; g3.Part = op(PWS, p.oPart, 1, NG);
+  g3.aligned16 = p.aligned16;  // T1 rows need dA % 4 == 0 as well (checked with the strides)
   KFB_TRY((mm<PR, 0, TA, TU, TA, TA, TA>(drecs, nrec, g3, s)));
   st_pre.reset(new StageTimer("pre_scale_X2", s, 4));
   // X1 = diag(c_G / lam_A) T1;  T2 <- T2 diag(c_A / lam_G);  T3 <- diag(c_G) T3 diag(c_A)
@@ -532,6 +534,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   GemmArgs g4;
   g4.A = op(PU_G, 0, 1, p.lduG); g4.B = op(PWS, p.oT3, 1, NG); g4.C0 = op(PWS, p.oT2, 1, dG);
   g4.C = op(PWS, p.oT2, 1, dG); g4.m = (int)dG; g4.n = NA; g4.k = NG; g4.beta = 1.0;
+  g4.aligned16 = p.aligned16;  // U_G columns (256-byte multiples) and the workspace blocks
   KFB_TRY((mm<PR, 0, TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
   st_pre.reset();
   StageTimer st_s("pre_S", s, 1);
@@ -617,6 +620,9 @@ int run_fac(const Rec* drecs, int nrec, const FacPlan& p, uint32_t flags, hipStr
       y.A = op(slotU, 0, 1, ldu); y.B = op(PWS, oT, 1, N); y.C0 = op(slotX, 0, 1, ldx);
       y.beta_slot = PWS; y.beta_off = p.oBeta + (side ? 16 : 8);
       y.C = op(PWS, oY, 1, d); y.m = (int)d; y.n = n; y.k = N;
+      // the vector loads touch only A (a state's U, 256-byte aligned columns) and
+      // B (workspace); C0 and C are read and written element by element
+      y.aligned16 = 1;
       KFB_TRY((mm<PR, 1, TU, TA, TA, TM, TA>(drecs, nrec, y, s)));
     }
   }

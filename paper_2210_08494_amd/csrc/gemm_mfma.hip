@@ -283,10 +283,10 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_kernel(const Rec* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Streamlined variant for large single-term FP32 products (the two-sided
-// apply): every operand 16-byte aligned with a unit stride along rows (MN)
-// or along k (KC), k and segment splits multiples of 32, m and n multiples
-// of 4.  The orientation of each operand is a template parameter and every
+// Streamlined variant for FP32 operands (single term, or the hi/lo split):
+// every operand 16-byte aligned with a unit stride along rows (MN) or along k
+// (KC), k, segment splits and split-K chunks multiples of 32, m and n
+// multiples of 4; split-K partials go to the same fixed-order reduction.  The orientation of each operand is a template parameter and every
 // per-thread address is formed once, so a k tile costs four vector loads,
 // eight packed conversions and four LDS stores per operand.  LDS rows of
 // MN-staged operands permute their four 16-byte k chunks by bits 4-5 of the
@@ -398,6 +398,11 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
   int tm, tn, tz;
   xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
   const Rec& rec = recs[tz];
+  // split-K: blockIdx.x also enumerates the k chunks (tm = kz * tiles_m + tile row)
+  const int tiles_m = (g.m + 127) / 128, kz = tm / tiles_m;
+  tm -= kz * tiles_m;
+  const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
+  const int kend = g.ksplit > 1 ? min(g.k, kbeg + g.kchunk) : g.k;
   const int t = threadIdx.x, w = t / 64, l = t % 64;
   const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
   constexpr bool swp = SWP;  // output column-major: issue (B^T A^T) so stores coalesce
@@ -419,14 +424,14 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   f32x4 fa[4], fb[4];
-  A.load(0, fa);
-  B.load(0, fb);
+  A.load(kbeg, fa);
+  B.load(kbeg, fb);
   fast_store<AKC, SPL>(fa, t, sA[0], sAl[0]);
   fast_store<BKC, SPL>(fb, t, sB[0], sBl[0]);
   __syncthreads();
   int cur = 0;
-  for (int k0 = 0; k0 < g.k; k0 += MBK) {
-    const bool more = k0 + MBK < g.k;
+  for (int k0 = kbeg; k0 < kend; k0 += MBK) {
+    const bool more = k0 + MBK < kend;
     if (more) {
       A.load(k0 + MBK, fa);
       B.load(k0 + MBK, fb);
@@ -471,12 +476,25 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
     __syncthreads();
     cur ^= 1;
   }
+  const int gm0 = tm * 128 + wm, gn0 = tn * 128 + wn;
+  if (g.ksplit > 1) {  // raw partial of chunk kz, column-major (the launch issues SWP)
+    float* part = at<float>(rec, g.Part.slot, g.Part.off) + (int64_t)kz * g.m * g.n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = gm0 + 16 * i + (l % 16), gj = gn0 + 16 * j + 4 * (l / 16) + v;
+          if (gi < g.m && gj < g.n) part[gi + (int64_t)gj * g.m] = acc[i][j][v];
+        }
+    return;
+  }
   TC* C = at<TC>(rec, g.C.slot, g.C.off);
   const bool use_c0 = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
   const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
   const float alpha = (float)g.alpha;
   const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
-  const int gm0 = tm * 128 + wm, gn0 = tn * 128 + wn;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -509,13 +527,25 @@ static int fast_orient(const OpRef& o, bool isa) {
   return one(o.rs2, o.cs2) == a ? a : -1;
 }
 
+template <typename TC, typename TC0>
+__global__ __launch_bounds__(256) void mfma_splitk_reduce(const Rec* __restrict__ recs, GemmArgs g);
+
 template <typename TC, typename TC0, bool SPL = false>
-static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s, hipError_t* err) {
-  if (!g.aligned16 || g.ksplit > 1 || g.k <= 0 || g.k % MBK || g.m % 4 || g.n % 4) return false;
-  const int ao = fast_orient(g.A, true), bo = fast_orient(g.B, false);
+static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t s, hipError_t* err) {
+  if (!g0.aligned16 || g0.k <= 0 || g0.k % MBK || g0.m % 4 || g0.n % 4) return false;
+  const int ao = fast_orient(g0.A, true), bo = fast_orient(g0.B, false);
   if (ao < 0 || bo < 0) return false;
-  dim3 grid((g.m + 127) / 128, (g.n + 127) / 128, nrec);
-  const bool swp = g.C.rs == 1;
+  GemmArgs g = g0;
+  int ks = g.ksplit < 1 ? 1 : g.ksplit;
+  if (ks > 1) {  // chunks of whole k tiles, the fixed-order reduction afterwards
+    int chunk = (g.k + ks - 1) / ks;
+    chunk = ((chunk + MBK - 1) / MBK) * MBK;
+    ks = (g.k + chunk - 1) / chunk;
+    g.kchunk = chunk;
+  }
+  g.ksplit = ks;
+  dim3 grid(((g.m + 127) / 128) * ks, (g.n + 127) / 128, nrec);
+  const bool swp = ks > 1 || g.C.rs == 1;
 #define KFB_FAST(AK, BK, SW) \
   hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, SPL>), grid, dim3(MNT), 0, s, recs, g)
   if (swp) {
@@ -530,6 +560,12 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g, hipStre
     else KFB_FAST(false, false, false);
   }
 #undef KFB_FAST
+  *err = hipGetLastError();
+  if (*err != hipSuccess || ks == 1) return true;
+  const int64_t mn = (int64_t)g.m * g.n;
+  int blocks = (int)((mn + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL((mfma_splitk_reduce<TC, TC0>), dim3(blocks, nrec), dim3(256), 0, s, recs, g);
   *err = hipGetLastError();
   return true;
 }

@@ -54,7 +54,9 @@ struct GemmArgs {
   // when beta_slot >= 0; lets a launch use per-problem values computed on the GPU
   int32_t beta_slot = -1;
   int64_t beta_off = 0;
-  // caller's promise: every pointer of A, B, C0 and C is 16-byte aligned
+  // caller's promise: the A and B base pointers are 16-byte aligned (the
+  // streamlined BF16 kernel loads them as 16-byte vectors; their strides are
+  // checked there; C0 and C are accessed by element)
   int32_t aligned16 = 0;
   // caller's promise: B is upper triangular (B(k, j) = 0 for k > j), so a tile
   // of columns [n0, n0 + 128) only needs k < n0 + 128 (FP32 MFMA kernel)
