@@ -502,7 +502,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   // T1 = U_G^T G   (NG x dA, row-major)
   GemmArgs g1;
   g1.A = op(PU_G, 0, p.lduG, 1); g1.B = op(P_G, 0, p.ldg, 1); g1.C = op(PWS, p.oT1, dA, 1);
-  g1.m = NG; g1.n = (int)dA; g1.k = (int)dG; g1.aligned16 = p.aligned16;
+  g1.m = NG; g1.n = (int)dA; g1.k = (int)dG; g1.aligned16 = p.aligned16; g1.c_vec = 1;  // workspace
   KFB_TRY((mm<PR, 0, TU, TGrad, TA, TA, TA>(drecs, nrec, g1, s)));
   // T2 = G U_A     (dG x NA, column-major)
   GemmArgs g2;
@@ -547,6 +547,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g5.C0 = op(P_G, 0, p.ldg, 1); g5.beta_slot = PWS; g5.beta_off = p.oBeta;
   g5.C = op(P_S, 0, p.lds, 1);
   g5.m = (int)dG; g5.n = (int)dA; g5.k = NG + NA; g5.aligned16 = p.aligned16;
+  g5.c_vec = p.aligned16;  // S and G pointers 16-byte aligned, lds and ldg multiples of 4
   KFB_TRY((mm<PR, 0, TU, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
   return KFB_OK;
 }
@@ -630,7 +631,7 @@ int run_fac(const Rec* drecs, int nrec, const FacPlan& p, uint32_t flags, hipStr
   // S = Y_G Y_A^T   (dG x dA row-major, inner dimension n)
   GemmArgs g5;
   g5.A = op(PWS, p.oYG, 1, p.dG); g5.B = op(PWS, p.oYA, p.dA, 1); g5.C = op(P_S, 0, p.lds, 1);
-  g5.m = (int)p.dG; g5.n = (int)p.dA; g5.k = n; g5.aligned16 = p.aligned16;
+  g5.m = (int)p.dG; g5.n = (int)p.dA; g5.k = n; g5.aligned16 = p.aligned16; g5.c_vec = p.aligned16;
   KFB_TRY((mm<PR, 0, TA, TA, TGrad, TGrad, TA>(drecs, nrec, g5, s)));
   return KFB_OK;
 }
