@@ -390,6 +390,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
     z.A = op(U_FRONT, 0, 1, ldu); z.B = op(WS, p.oP, 1, r); z.C0 = op(M_IN, 0, 1, ldm);
     z.C = op(WS, p.oZ, 1, d); z.m = (int)d; z.n = n; z.k = r; z.alpha = -1.0; z.beta = 1.0;
     z.aligned16 = (d % 4 == 0) && (r % 4 == 0);  // U columns (ldu: 256 B multiples), P columns (ld r)
+    z.c_vec = 1;  // Z in the workspace (the BF16 batch as C0 keeps the element-wise epilogue)
     KFB_TRY((mm<PR, 1, TU, TP, TZ, TM, TA>(drecs, nrec, z, s)));
     // re-projection: P2 = U_r^T Z;  Z -= U_r P2  (P + P2 enters the core)
     GemmArgs g2 = g;
@@ -447,6 +448,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   ro.B = op(WS, p.oW, 1, N); ro.C = op(U_BACK, 0, 1, ldu);
   ro.m = (int)d; ro.n = N; ro.k = N;
   ro.aligned16 = (d % 4 == 0) && (N % 4 == 0);  // U, Q (ld d) and W (ld N) columns
+  ro.c_vec = 1;                                  // the back buffer's columns (ldu: 256-byte multiples)
   StageTimer st_rot("rotate", s, 2);
   KFB_TRY((mm<PR, 1, TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
   // drift detector on the new basis (column norms)
@@ -507,7 +509,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   // T2 = G U_A     (dG x NA, column-major)
   GemmArgs g2;
   g2.A = op(P_G, 0, p.ldg, 1); g2.B = op(PU_A, 0, 1, p.lduA); g2.C = op(PWS, p.oT2, 1, dG);
-  g2.m = (int)dG; g2.n = NA; g2.k = (int)dA; g2.aligned16 = p.aligned16;
+  g2.m = (int)dG; g2.n = NA; g2.k = (int)dA; g2.aligned16 = p.aligned16; g2.c_vec = 1;  // workspace
   KFB_TRY((mm<PR, 0, TGrad, TU, TA, TA, TA>(drecs, nrec, g2, s)));
   // T3 = T1 U_A    (NG x NA)
   GemmArgs g3;
@@ -535,6 +537,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g4.A = op(PU_G, 0, 1, p.lduG); g4.B = op(PWS, p.oT3, 1, NG); g4.C0 = op(PWS, p.oT2, 1, dG);
   g4.C = op(PWS, p.oT2, 1, dG); g4.m = (int)dG; g4.n = NA; g4.k = NG; g4.beta = 1.0;
   g4.aligned16 = p.aligned16;  // U_G columns (256-byte multiples) and the workspace blocks
+  g4.c_vec = 1;                // T2 (C0 and C) in the workspace
   KFB_TRY((mm<PR, 0, TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
   st_pre.reset();
   StageTimer st_s("pre_S", s, 1);

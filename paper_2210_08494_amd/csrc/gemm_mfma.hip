@@ -495,17 +495,28 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
   const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
   const float alpha = (float)g.alpha;
   const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
-  if constexpr (SWP && sizeof(TC) == 4 && sizeof(TC0) == 4) {
-    if (g.c_vec) {  // row-major C: each lane's four results are four consecutive columns
+  if constexpr (sizeof(TC) == 4 && sizeof(TC0) == 4) {
+    // vector epilogue: each lane's four results are four consecutive columns of
+    // a row-major C (transposed issue) or four consecutive rows of a
+    // column-major C (plain issue); m and n are multiples of 4
+    if (g.c_vec) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int gi = gm0 + 16 * i + (l % 16), gj = gn0 + 16 * j + 4 * (l / 16);
-          if (gi < g.m && gj < g.n) {  // n % 4 == 0: all four columns in range
+          int gi, gj;
+          int64_t oc, oc0;
+          if (SWP) {
+            gi = gm0 + 16 * i + (l % 16); gj = gn0 + 16 * j + 4 * (l / 16);
+            oc = (int64_t)gi * g.C.rs + gj; oc0 = (int64_t)gi * g.C0.rs + gj;
+          } else {
+            gi = gm0 + 16 * i + 4 * (l / 16); gj = gn0 + 16 * j + (l % 16);
+            oc = gi + (int64_t)gj * g.C.cs; oc0 = gi + (int64_t)gj * g.C0.cs;
+          }
+          if (gi < g.m && gj < g.n) {
             f32x4 val = alpha * acc[i][j];
-            if (C0) val += beta * *reinterpret_cast<const f32x4*>(&C0[(int64_t)gi * g.C0.rs + gj]);
-            *reinterpret_cast<f32x4*>(&C[(int64_t)gi * g.C.rs + gj]) = val;
+            if (C0) val += beta * *reinterpret_cast<const f32x4*>(&C0[oc0]);
+            *reinterpret_cast<f32x4*>(&C[oc]) = val;
           }
         }
       return;
@@ -561,12 +572,16 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStr
   }
   g.ksplit = ks;
   dim3 grid(((g.m + 127) / 128) * ks, (g.n + 127) / 128, nrec);
-  // row-major C with 16-byte rows: the transposed issue gives each lane four
-  // consecutive columns, stored (and C0 read) as one vector
+  // vector epilogue (C and C0 as 16-byte vectors): a row-major C takes the
+  // transposed issue (four consecutive columns per lane), a column-major C the
+  // plain one (four consecutive rows per lane)
   const bool c0_used = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
-  g.c_vec = ks == 1 && g.c_vec && sizeof(TC) == 4 && sizeof(TC0) == 4 && g.C.cs == 1 && g.C.rs % 4 == 0 &&
-            (!c0_used || (g.C0.cs == 1 && g.C0.rs % 4 == 0));
-  const bool swp = ks > 1 || g.C.rs == 1 || g.c_vec;
+  const bool vok = ks == 1 && g.c_vec && sizeof(TC) == 4 && sizeof(TC0) == 4;
+  const bool vrow = vok && g.C.cs == 1 && g.C.rs % 4 == 0 && (!c0_used || (g.C0.cs == 1 && g.C0.rs % 4 == 0));
+  const bool vcol = vok && !vrow && g.C.rs == 1 && g.C.cs % 4 == 0 &&
+                    (!c0_used || (g.C0.rs == 1 && g.C0.cs % 4 == 0));
+  g.c_vec = vrow || vcol;
+  const bool swp = vrow || (!vcol && (ks > 1 || g.C.rs == 1));
 #define KFB_FAST(AK, BK, SW) \
   hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, SPL>), grid, dim3(MNT), 0, s, recs, g)
   if (swp) {

@@ -58,8 +58,8 @@ struct GemmArgs {
   // streamlined BF16 kernel loads them as 16-byte vectors; their strides are
   // checked there; C0 and C are accessed by element)
   int32_t aligned16 = 0;
-  // caller's promise: C (and C0 when used) 16-byte aligned; with unit column
-  // strides the streamlined kernel then stores (and reads) 4 columns at once
+  // caller's promise: C (and C0 when used) 16-byte aligned; with a unit row or
+  // column stride the streamlined kernel then stores (and reads) 4 at once
   int32_t c_vec = 0;
   // caller's promise: B is upper triangular (B(k, j) = 0 for k > j), so a tile
   // of columns [n0, n0 + 128) only needs k < n0 + 128 (FP32 MFMA kernel)
