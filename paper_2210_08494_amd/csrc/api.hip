@@ -299,6 +299,7 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
     q.A = op(WS, srcZ, 1, d); q.B = op(WS, oX[pass & 1], 1, n); q.C = op(WS, dstZ, 1, d);
     q.m = (int)d; q.n = n; q.k = n;
     q.b_upper = 1;  // R^-1 is upper triangular
+    q.c_vec = 1;    // Q in the workspace
     if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {
       KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));  // Q = Z R^-1 on FP32 MFMA
     } else {

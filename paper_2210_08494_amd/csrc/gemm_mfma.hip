@@ -743,6 +743,24 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restric
   const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
   const float alpha = (float)g.alpha;
   const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+  if constexpr (!SWP) {
+    if (g.c_vec) {  // column-major C: each lane's four results are four consecutive rows
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int gi = m0 + wm + 16 * i + 4 * (l / 16), gj = n0 + wn + 16 * j + (l % 16);
+          if (gi < g.m && gj < g.n) {  // m % 4 == 0: all four rows in range
+            f32x4 val = alpha * acc[i][j];
+            if (C0)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) val[v] += beta * to_f(C0[(gi + v) * g.C0.rs + gj * g.C0.cs]);
+            *reinterpret_cast<f32x4*>(&C[gi + (int64_t)gj * g.C.cs]) = val;
+          }
+        }
+      return;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -765,8 +783,12 @@ hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream
   if (g.m <= 0 || g.n <= 0 || nrec <= 0) return hipSuccess;
   if (g.A.slot2 >= 0 || g.B.slot2 >= 0 || g.ksplit > 1) return hipErrorInvalidValue;
   dim3 grid((g.m + 127) / 128, (g.n + 127) / 128, nrec);
-  if (g.C.rs == 1) hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, true>), grid, dim3(256), 0, s, recs, g);
-  else hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, false>), grid, dim3(256), 0, s, recs, g);
+  // column-major C with 16-byte columns (c_vec): the plain issue gives each lane
+  // four consecutive rows, stored as one vector
+  GemmArgs gv = g;
+  gv.c_vec = g.c_vec && g.C.rs == 1 && g.C.cs % 4 == 0 && g.m % 4 == 0;
+  if (gv.c_vec || g.C.rs != 1) hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, false>), grid, dim3(256), 0, s, recs, gv);
+  else hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, true>), grid, dim3(256), 0, s, recs, gv);
   return hipGetLastError();
 }
 template hipError_t gemm_f32_mfma<double, float>(const Rec*, int, const GemmArgs&, hipStream_t);
