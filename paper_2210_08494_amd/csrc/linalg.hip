@@ -188,11 +188,10 @@ __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict
 // X_J,rest = -X_JJ (R_J,rest X_rest,rest) by column blocks.  The pivot rule,
 // the shift and the zero rows are those of the column kernel; only the order
 // of the sums differs.
-// n <= 272: the two staged block rows (2 CB (n + 4) values) and the static
-// arrays fit the 160 KB of LDS, and the inverse's column mapping below covers
-// the m <= n - CB <= 256 columns right of a block row
+// n <= 272: the inverse's column blocks (n x 32 of X and a 32 x (n - 32) block
+// row of R, FP64) fit the 160 KB of LDS
 constexpr int CB = 32, CHB_NT = 512, CHB_MAXN = 272;
-static_assert(CHB_MAXN - CB <= 256, "the inverse maps at most 256 columns onto the workgroup");
+static_assert((CHB_MAXN * CB + CB * (CHB_MAXN - CB)) * 8 <= 160 * 1024, "inverse column block exceeds LDS");
 
 template <typename T>
 __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restrict__ recs, CholArgs a) {
@@ -204,7 +203,6 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
   const int nreal = rec.s[2] > 0.0 ? (int)rec.s[2] : n;
   const int LDW = ((n + 3) / 4) * 4 + 4;  // row stride of the staged block rows
   T* Pn = reinterpret_cast<T*>(chb_smem);  // CB x LDW: block row of R
-  T* Tb = Pn + CB * LDW;                   // CB x LDW: R_J,rest X_rest,rest
   __shared__ T Dg[CB][CB + 1];
   __shared__ T red[CHB_NT / 64], redt[CHB_NT / 64];
   __shared__ T invrow[CB];
@@ -524,11 +522,11 @@ hipError_t chol_inv(const Rec* recs, int nrec, const CholArgs& a, hipStream_t s)
   if (a.n > CHOL_MAXN) return hipErrorInvalidValue;
   if (a.n <= CHB_MAXN) {
     const int ldw = ((a.n + 3) / 4) * 4 + 4;
-    const size_t lds = 2 * (size_t)CB * ldw * sizeof(T);
+    const size_t lds = (size_t)CB * ldw * sizeof(T);
     static bool attr = false;
     if (!attr) {
       (void)hipFuncSetAttribute((const void*)chol_blocked_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(2 * CB * (CHB_MAXN + 4) * sizeof(T)));
+                                (int)(CB * (CHB_MAXN + 4) * sizeof(T)));
       attr = true;
     }
     hipLaunchKernelGGL((chol_blocked_kernel<T>), dim3(nrec), dim3(CHB_NT), lds, s, recs, a);
