@@ -208,7 +208,11 @@ class Server:
         lib = self._lib
         if key[0] == "U":
             hs = (ctypes.c_void_p * len(reqs))(*[self.factor(r.layer, r.side).handle.value for r in reqs])
-            return int(lib.kfb_update_batched_workspace_bytes(len(reqs), hs, key[4]))
+            nbytes = int(lib.kfb_update_batched_workspace_bytes(len(reqs), hs, key[4]))
+            if self.pad_updates:  # zero-padded copies of the batches (bounded by n_max columns)
+                nbytes += sum(key[4] * int(r.M.shape[1]) * r.M.element_size() for r in reqs
+                              if r.M.shape[0] != key[4] or r.M.stride(0) != r.M.shape[1])
+            return nbytes
         hg = (ctypes.c_void_p * len(reqs))(*[self.fg[r.layer].handle.value for r in reqs])
         ha = (ctypes.c_void_p * len(reqs))(*[self.fa[r.layer].handle.value for r in reqs])
         return int(lib.kfb_precondition_batched_workspace_bytes(len(reqs), hg, ha))
@@ -264,7 +268,6 @@ class Server:
             if self.hooks_before_issue:
                 self.hooks_before_issue(key[0], reqs, stream)
             ws = kfb.Workspace(self.device)
-            ws.get(nbytes)
             keep = None
             if key[0] == "U":
                 factors = [self.factor(r.layer, r.side) for r in reqs]
