@@ -278,6 +278,27 @@ def test_mixed_trajectory_small(kfb):
     assert worst <= TOL[2]
 
 
+@pytest.mark.parametrize("d,r,n", [(1056, 64, 64), (1000, 36, 20), (4100, 40, 36)])
+def test_mixed_ragged_products(kfb, d, r, n):
+    # shapes off the MFMA GEMMs' tile grid: split-K with a short last chunk
+    # (d = 1056: chunks of 288), d not a multiple of 32 (element-wise fallback),
+    # ranks and widths that are not multiples of 32
+    import torch
+    _announce(f"mixed ragged d={d} r={r} n={n}")
+    f = kfb.Factor(d, r, n, 0.95, kfb.KFB_BF16_MIXED)
+    o = oracle.BrandFactor(d, r, 0.95)
+    worst = 0.0
+    for k in range(5):
+        M = _batch(17, k, "G", n, d, prec=2)
+        f.update(_to_dev(M, torch.bfloat16))
+        o.update(M.T)
+        U, D = _front_np(f)
+        worst = max(worst, oracle.e_rec_lowrank(U, D, o.U, o.D))
+    _announce(f"  worst e_rec {worst:.3e} orth {oracle.e_orth(U):.3e}")
+    assert worst <= TOL[2] and oracle.e_orth(U) <= TOL[2]
+    assert f.status() == 0
+
+
 def test_batched_equals_single(kfb):
     import torch
     d, r, n, rho = 384, 32, 32, 0.95
