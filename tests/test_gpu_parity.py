@@ -443,6 +443,19 @@ def test_ortho_drift_is_reported(kfb, prec):
     assert g.status() & kfb.KFB_EV_ORTHO_DRIFT
 
 
+def test_batched_widths_argument_errors(kfb):
+    import torch
+    d, r, n = 128, 8, 16
+    fs = [kfb.Factor(d, r, n, 0.95, kfb.KFB_FP64) for _ in range(2)]
+    ws = kfb.Workspace()
+    Ms = [torch.zeros((n, d), dtype=torch.float64, device=_dev()) for _ in range(2)]
+    for bad in ([0, 4], [4, n + 1], [-3, 4]):
+        with pytest.raises(kfb.KfbError):
+            kfb.update_batched_widths(fs, Ms, bad, ws)
+    kfb.update_batched_widths(fs, Ms, [n, 1], ws)   # zero batches: valid, state stays empty of energy
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_batched_uneven_widths_equal_unpadded(kfb, prec):
     # batches of widths 40, 64, 25 zero-padded to 64 in one grouped call equal the
