@@ -165,7 +165,11 @@ template <int PR>
 bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, UpdPlan* p) {
   typedef Ty<PR> T;
   p->d = d; p->ldu = ldu; p->ldm = ldm; p->r = r; p->n = n; p->N = r + n;
-  const int tbw = tuned_bw(PR, p->N);
+  // the tuning table's entry for N, else (FP64 cores of N >= 256) 64-column
+  // panels streamed from global memory, the autotuner's pick at the headline
+  // core, else the widest LDS panel
+  int tbw = tuned_bw(PR, p->N);
+  if (!tbw && sizeof(typename T::Core) == 8 && p->N >= 256) tbw = JAC_STREAMED | 32;
   const int tNp = tbw ? jacobi_block_fits(p->N, (int)sizeof(typename T::Core), tbw) : 0;
   if (tNp) {
     p->bw = tbw;
