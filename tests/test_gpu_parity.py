@@ -278,6 +278,32 @@ def test_mixed_trajectory_small(kfb):
     assert worst <= TOL[2]
 
 
+def test_mixed_long_run_stability(kfb):
+    # 150 consecutive BF16-mixed updates: the re-projection and CholeskyQR2 keep
+    # U orthonormal (no accumulation of the BF16 rounding across steps) and the
+    # state tracks the FP64 oracle throughout
+    import torch
+    d, r, n, steps = 1024, 64, 64, 150
+    _announce(f"mixed long run d={d} r={r} n={n} steps={steps}")
+    f = kfb.Factor(d, r, n, 0.95, kfb.KFB_BF16_MIXED)
+    o = oracle.BrandFactor(d, r, 0.95)
+    errs, orths = [], []
+    for k in range(steps):
+        M = _batch(18, k, "A", n, d, prec=2)
+        f.update(_to_dev(M, torch.bfloat16))
+        o.update(M.T)
+        if k % 10 == 9:
+            U, D = _front_np(f)
+            errs.append(oracle.e_rec_lowrank(U, D, o.U, o.D))
+            orths.append(oracle.e_orth(U))
+    _announce(f"  e_rec first {errs[0]:.3e} last {errs[-1]:.3e} max {max(errs):.3e}; "
+              f"orth first {orths[0]:.3e} last {orths[-1]:.3e} max {max(orths):.3e}")
+    assert max(errs) <= TOL[2]
+    assert max(orths) <= 1e-3            # the drift detector's threshold for this form
+    assert orths[-1] <= 10 * orths[0] + 1e-6   # no growth over the run
+    assert f.status() == 0
+
+
 @pytest.mark.parametrize("d,r,n", [(1056, 64, 64), (1000, 36, 20), (4100, 40, 36)])
 def test_mixed_ragged_products(kfb, d, r, n):
     # shapes off the MFMA GEMMs' tile grid: split-K with a short last chunk
