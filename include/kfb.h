@@ -122,8 +122,10 @@ int kfb_brand_update_batched(int32_t count, kfb_state_t const* states, const voi
  * update), so the result is the exact update by the real columns; the
  * padding's zero pivots in CholeskyQR are expected and not reported as rank
  * deficiency.  The state then holds min(k_valid, r) + n modes, the padded
- * ones with eigenvalue 0: they add nothing to the inverse and leave at the
- * next truncation.  widths: HOST array of count values.  Workspace as
+ * ones with eigenvalue 0: they add nothing to the inverse (its coefficient
+ * 1/(0 + lam) - 1/lam vanishes) and leave at the next truncation; with
+ * KFB_SPECTRUM_CONTINUATION they make the minimum eigenvalue 0, i.e. no
+ * shift, until then.  widths: HOST array of count values.  Workspace as
  * kfb_update_batched_workspace_bytes(count, states, n).  KFB_EINVAL for a
  * width outside 1..n. */
 int kfb_brand_update_batched_widths(int32_t count, kfb_state_t const* states, const void* const* Ms,

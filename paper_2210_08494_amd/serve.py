@@ -22,11 +22,13 @@ Scheduling (host side; all arithmetic runs in the HIP library):
   under load instead of flooding the device with groups of one);
 * with ``pad_updates``, updates of one factor shape (d, r) but uneven batch
   widths share a bucket: each batch is padded with zero columns to the widest
-  batch of its group and the group runs as ``kfb_brand_update_batched_widths`` (each problem
-  weighted by its own width, so the result is the exact update by its real
-  columns; the padded modes carry eigenvalue 0).  This trades extra work per
-  update for far larger groups when widths vary; results are then no longer
-  bit-identical to a request run alone, only equal within rounding;
+  batch of its group and the group runs as ``kfb_brand_update_batched_widths``
+  (each problem weighted by its own width, so the result is the exact update
+  by its real columns; the padded modes carry eigenvalue 0, so spectrum
+  continuation sees a minimum eigenvalue of 0 until the next truncation drops
+  them).  This trades extra work per update for larger groups when widths
+  vary; results are then no longer bit-identical to a request run alone, only
+  equal within rounding;
 * groups go round-robin onto several default-priority HIP streams, each first
   waiting on the completion events of the last operations on its states, so
   work on different states overlaps on the device while per-state order holds;
