@@ -214,6 +214,7 @@ def main():
     ap.add_argument("--layers", type=int, default=LAYERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-updates", type=int, default=6)
+    ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--serve-rates", default="400,2000")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -329,6 +330,32 @@ def main():
         "pre_scale_X2": _rate("pre_scale_X2", L * 2.0 * D * N * N),
         "pre_S": _rate("pre_S", L * 2.0 * D * D * 2 * N),
     }
+
+    # ---- the same step replayed from a HIP graph: two consecutive steps captured
+    # (every state's front and back buffers trade roles twice and end as they
+    # began), replayed graph_steps / 2 times; the library launches only kernels
+    # on the caller's stream, so the whole step is capturable
+    graph_replay = None
+    if args.graph_steps > 0:
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step(0)
+            step(1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        reps = max(args.graph_steps // 2, 1)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        gwall = time.perf_counter() - t0
+        graph_replay = {"value": round(S * 2 * reps / gwall, 2), "unit": "B-updates/s",
+                        "ms_per_step": round(1e3 * gwall / (2 * reps), 3), "steps": 2 * reps,
+                        "note": "the timed step (grouped updates + grouped preconditioning) captured "
+                                "in one HIP graph and replayed"}
+        del graph
 
     # ---- FP32 plain form: one state at a time, no grouping
     f32 = [kfb.Factor(D, R, N_BATCH, RHO, kfb.KFB_FP32, device=dev) for _ in range(2)]
@@ -448,6 +475,7 @@ def main():
                        "single_update_p99": round(_percentile(lat1, 99), 3),
                        "note": "closed loop; step = 48 updates + 24 preconditionings"},
         "fp32_plain": fp32_plain,
+        "graph_replay": graph_replay,
         "serving": serving,
         "serving_uneven": serving_mixed,
         "roofline": roofline,
