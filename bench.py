@@ -222,7 +222,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (factor states "
-              "are independent, see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "are independent: a multi-GPU run would place whole layers per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
