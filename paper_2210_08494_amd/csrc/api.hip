@@ -304,17 +304,8 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
     q.m = (int)d; q.n = n; q.k = n;
     q.b_upper = 1;  // R^-1 is upper triangular
     q.c_vec = 1;    // Q in the workspace
-    if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {  // Q = Z R^-1 on FP32 MFMA
-      if constexpr (sizeof(TG) == 8) {
-        // R^-1 rounded to FP32 once (the product rounds its operand to FP32 on
-        // load anyway), into the R buffer that the passes leave unused: half
-        // the operand bytes of every tile's loads
-        KFB_TRY((copy2d<float, TG>(drecs, nrec, op(WS, p.oRt, 1, n), op(WS, oX[pass & 1], 1, n), n, n, s)));
-        q.B = op(WS, p.oRt, 1, n);
-        KFB_TRY((gemm_f32_mfma<float, TZ>(drecs, nrec, q, s)));
-      } else {
-        KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));
-      }
+    if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {
+      KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));  // Q = Z R^-1 on FP32 MFMA
     } else {
       KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
     }
