@@ -206,6 +206,11 @@ def serve_mixed_leg(torch, kfb, dev, args):
     return res
 
 
+def _progress(msg):
+    # one line per finished leg on stderr (stdout carries only the JSON line)
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +241,7 @@ def main():
     # ---- autotune the core eigensolver's configuration for this bucket (untimed)
     from paper_2210_08494_amd import tune
     best_bw, tune_ms = tune.tune_jacobi(MIX, D, R, N_BATCH, count=S, reps=2, device=dev)
+    _progress(f"autotune done: {best_bw}")
 
     # ---- states: even index = A factor (d_in), odd = Gamma factor (d_out) of a layer
     states = [kfb.Factor(D, R, N_BATCH, RHO, MIX, device=dev) for _ in range(S)]
@@ -357,6 +363,7 @@ def main():
                                 "in one HIP graph and replayed"}
         del graph
 
+    _progress("timed steps and graph replay done")
     # ---- FP32 plain form: one state at a time, no grouping
     f32 = [kfb.Factor(D, R, N_BATCH, RHO, kfb.KFB_FP32, device=dev) for _ in range(2)]
     b32 = _gen_batches(torch, dev, 2, N_BATCH, D, seed=99, dtype=torch.float32)
@@ -378,6 +385,7 @@ def main():
                       "ms_per_update_p50": round(_percentile(lat32, 50), 3), "states": 2,
                       "mode": "one update at a time, no grouping"}
 
+    _progress("fp32 leg done")
     # ---- factored (linear-cost) application, Algorithm 8: the gradient of each
     # layer given as G_k A_k^T by the step's own batches (grouped over the layers)
     Gks = [batches[0][2 * l + 1] for l in range(L)]
@@ -404,6 +412,7 @@ def main():
                 "s_write_gbs": round(L * 4.0 * D * D / (fac_call * 1e-3) / 1e9, 1),
                 "unit_work": "per layer 8*N*d*n (both sides) + 2*d^2*n (S = Y_G Y_A^T) flops; S written once (FP32)"}
 
+    _progress("factored leg done")
     # ---- B-R-KFAC pieces at the same shape: one dense EA-factor step and one
     # randomized-SVD overwrite (oversampling 16, two power iterations)
     fbr = kfb.Factor(D, R, N_BATCH, RHO, MIX, device=dev)
@@ -438,6 +447,7 @@ def main():
               "unit_work": "dense step 2*d^2*n flops; RSVD 6 products 2*d^2*l (sketch, 2 x 2 power, final)"}
     del Xd
 
+    _progress("brkfac leg done")
     # ---- single mixed update latency (no grouping), for the latency columns
     lat1 = []
     for i in range(6):
@@ -449,7 +459,9 @@ def main():
         lat1.append(e0.elapsed_time(e1))
 
     serving = serve_leg(torch, kfb, dev, args) if args.serve_requests > 0 else None
+    _progress("serving leg done")
     serving_mixed = serve_mixed_leg(torch, kfb, dev, args) if args.serve_requests > 0 else None
+    _progress("uneven serving leg done")
 
     out = {
         "metric": "B-updates/s + p50/p99 latency, BF16-mixed vs FP32 plain, d=4096 r=256 n=256",
