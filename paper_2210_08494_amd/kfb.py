@@ -240,10 +240,23 @@ def precondition(fg: Factor, fa: Factor, G, S, lam_g: float, lam_a: float, flags
            "kfb_precondition")
 
 
+def _same_layout(ts, what: str, count: int):
+    """The grouped calls take one shape and leading dimension for all problems:
+    check every tensor against the first before any pointer reaches the library."""
+    if len(ts) != count:
+        raise KfbError(f"{what}: {len(ts)} tensors for {count} problems")
+    t0 = ts[0]
+    for t in ts:
+        if t.dim() != 2 or t.shape != t0.shape or t.stride() != t0.stride() or t.dtype != t0.dtype \
+                or t.stride(1) != 1:
+            raise KfbError(f"{what}: every tensor must be 2-D, row-contiguous and share shape, strides and dtype")
+
+
 def update_batched(factors, Ms, ws: Workspace):
     """One grouped launch sequence updating every factor with its batch (same shape bucket)."""
     lib = load()
     cnt = len(factors)
+    _same_layout(Ms, "update_batched", cnt)
     hs = (_vp * cnt)(*[f.handle.value for f in factors])
     ms = (_vp * cnt)(*[m.data_ptr() for m in Ms])
     n = int(Ms[0].shape[0])
@@ -259,6 +272,9 @@ def update_batched_widths(factors, Ms, widths, ws: Workspace):
     """Grouped update of batches padded with zero columns to a common n; widths[i] = real columns of Ms[i]."""
     lib = load()
     cnt = len(factors)
+    _same_layout(Ms, "update_batched_widths", cnt)
+    if len(widths) != cnt:
+        raise KfbError(f"update_batched_widths: {len(widths)} widths for {cnt} problems")
     hs = (_vp * cnt)(*[f.handle.value for f in factors])
     ms = (_vp * cnt)(*[m.data_ptr() for m in Ms])
     ws_ = (_i32 * cnt)(*[int(x) for x in widths])
@@ -274,6 +290,10 @@ def update_batched_widths(factors, Ms, widths, ws: Workspace):
 def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):
     lib = load()
     cnt = len(fgs)
+    _same_layout(Gs, "precondition_batched (G)", cnt)
+    _same_layout(Ss, "precondition_batched (S)", cnt)
+    if len(fas) != cnt or len(lam_g) != cnt or len(lam_a) != cnt:
+        raise KfbError("precondition_batched: one A state and one lambda per side for every layer")
     hg = (_vp * cnt)(*[f.handle.value for f in fgs])
     ha = (_vp * cnt)(*[f.handle.value for f in fas])
     gp = (_vp * cnt)(*[g.data_ptr() for g in Gs])

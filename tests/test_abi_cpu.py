@@ -70,3 +70,16 @@ def test_strerror_and_build_info(lib):
     from paper_2210_08494_amd import build as kbuild
     assert info.endswith(b"src=" + kbuild.source_digest().encode())
     assert lib.kfb_destroy(None) == 1
+
+
+def test_grouped_call_layout_checks():
+    # the binding refuses mismatched batches before any pointer reaches the library
+    import pytest
+    import torch
+    from paper_2210_08494_amd import kfb
+    a = torch.zeros(4, 8)
+    kfb._same_layout([a, torch.zeros(4, 8)], "t", 2)
+    for bad, cnt in (([a, torch.zeros(5, 8)], 2), ([a, torch.zeros(4, 8).t().contiguous().t()], 2),
+                     ([a, torch.zeros(4, 8, dtype=torch.float64)], 2), ([a], 2), ([a[:, ::2]], 1)):
+        with pytest.raises(kfb.KfbError):
+            kfb._same_layout(bad, "t", cnt)
