@@ -54,32 +54,59 @@ def _percentile(xs, q):
     return xs[i]
 
 
-def cpu_baseline(budget_s: float = 20.0):
-    """The FP64 oracle (structured Brand update, Algorithm 3) on the host cores."""
+def cpu_baseline(budget_s: float = 8.0):
+    """The FP64 oracle timed on the host cores at the headline shape: Oracle-B (the
+    structured Brand update, Algorithm 3) and Oracle-D (the dense definition: the
+    d x d B-process iterate and a full eigendecomposition per update), each with
+    the BLAS pool on all host cores and on one core; median over the samples that
+    fit the time budget (at least one each)."""
     import numpy as np
     import oracle
     from paper_2210_08494_amd import synth
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=os.cpu_count())
     except Exception:
-        threads = os.cpu_count()
-    f = oracle.BrandFactor(D, R, RHO)
-    for k in range(2):  # bring the state to r + n = 512 modes (untimed)
-        f.update(synth.batch_for(6, k, "A", N_BATCH, D).T)
-    times = []
-    t_all = time.perf_counter()
-    k = 2
-    while time.perf_counter() - t_all < budget_s and len(times) < 100:
-        M = synth.batch_for(6, k, "A", N_BATCH, D).T
-        t0 = time.perf_counter()
-        f.update(M)
-        times.append(time.perf_counter() - t0)
-        k += 1
-    med = float(np.median(times))
-    return {"value": 1.0 / med, "unit": "B-updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(times)} structured FP64 Brand updates (oracle/brand.py) at d={D} r={R} "
-                      f"n={N_BATCH} on the host, median {med:.3f} s each"}
+        threadpool_limits, threads = None, os.cpu_count()
+
+    def warm(make):
+        f = make()
+        for k in range(2):  # bring the state to r + n = 512 modes (untimed, all cores)
+            f.update(synth.batch_for(6, k, "A", N_BATCH, D).T)
+        return f
+
+    def run(f, budget, max_samples, k0):
+        times, k = [], k0
+        t_all = time.perf_counter()
+        while len(times) < max_samples and (not times or time.perf_counter() - t_all < budget):
+            M = synth.batch_for(6, k, "A", N_BATCH, D).T
+            t0 = time.perf_counter()
+            f.update(M)
+            times.append(time.perf_counter() - t0)
+            k += 1
+        return float(np.median(times)), len(times)
+
+    res = {}
+    for name, make, budget, cap in (("oracle_b", lambda: oracle.BrandFactor(D, R, RHO), budget_s, 100),
+                                    ("oracle_d", lambda: oracle.DenseFactor(D, R, RHO), 0.0, 1)):
+        f = warm(make)
+        for cores in ("all", "1"):
+            if cores == "1" and threadpool_limits is None:
+                continue
+            if cores == "1":
+                with threadpool_limits(limits=1):
+                    med, cnt = run(f, budget, cap, 200)
+            else:
+                med, cnt = run(f, budget, cap, 2)
+            res[f"{name}_{cores}"] = {"s_per_update": round(med, 4), "b_updates_per_s": round(1.0 / med, 4),
+                                      "samples": cnt, "threads": int(threads) if cores == "all" else 1}
+    main = res["oracle_b_all"]
+    return {"value": main["b_updates_per_s"], "unit": "B-updates/s", "cores": main["threads"], "kind": "oracle",
+            "sample": f"{main['samples']} structured FP64 Brand updates (oracle/brand.py, Householder QR + "
+                      f"eigh of the {R + N_BATCH}-wide core) at d={D} r={R} n={N_BATCH} on the host, median "
+                      f"{main['s_per_update']:.3f} s each; beside it the dense definition (oracle/bprocess.py, "
+                      f"eigh of the {D}x{D} iterate) and both on one core",
+            "legs": res}
 
 
 def _measured_traffic(kfb, kname):
@@ -101,20 +128,59 @@ def _measured_traffic(kfb, kname):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def serve_leg(torch, kfb, dev, args):
-    """Open-loop Poisson serving at the headline shape: 70% updates (uniform over
-    layer and factor), 30% preconditionings (uniform layer), continuous batching."""
+class _BatchPool:
+    """Distinct pre-generated batches in HBM, handed out in order: every update
+    request of a serving run gets a batch no state has seen (the pool wraps
+    around only if a run needs more than it holds)."""
+
+    def __init__(self, torch, dev, count, n, d, seed, dtype):
+        self.sets = {}
+        for s_i, side in enumerate(("A", "G")):
+            g = torch.Generator(device=dev)
+            g.manual_seed(seed + s_i)
+            k = torch.arange(1, d + 1, device=dev, dtype=torch.float32)
+            out = []
+            for _ in range(count):
+                z = torch.randn(n, d, generator=g, device=dev)
+                x = torch.relu(z * k ** -1.0) if side == "A" else z * k ** -0.7
+                out.append(x.to(dtype).contiguous())
+            self.sets[side] = out
+        self.next = {"A": 0, "G": 0}
+
+    def take(self, side):
+        i = self.next[side]
+        self.next[side] = i + 1
+        b = self.sets[side]
+        return b[i % len(b)]
+
+
+def _serve_stats(serve, srv, wall, done):
+    lat_ms = [1e3 * (r.t_done - r.t_arrival) for r in done]
+    upd = sum(1 for r in done if isinstance(r, serve.UpdateRequest))
+    return {"requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
+            "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
+            "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
+            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
+
+
+def serve_leg(torch, kfb, dev, args, prec, nreq, grouped=True):
+    """Open-loop Poisson serving at the headline shape (24 layers, 48 states at
+    d=4096, r=256, n=256): 70% updates (uniform over layer and factor), 30%
+    preconditionings (uniform layer), a fresh batch for every update.  First at
+    2000 requests/s offered (above the capacity of either form: the achieved rate
+    is the form's saturation), then at half of that measured saturation.  The
+    mixed form runs with continuous batching (grouped launches, up to 48 per
+    group, four streams); the FP32-plain form one request at a time on one
+    stream (no grouping)."""
     from paper_2210_08494_amd import serve
     L = args.layers
     layers = [(D, D, R, R)] * L
-    res = {}
-    srv = serve.Server(layers, n_max=N_BATCH, rho=RHO, prec=kfb.KFB_BF16_MIXED, streams=4,
-                       byte_budget=24 << 30, max_group=48)
-    pool = {}
-    for l in range(L):
-        for s_i, side in enumerate(("A", "G")):
-            pool[(l, side)] = _gen_batches(torch, dev, 2, N_BATCH, D, seed=5000 + 2 * l + s_i,
-                                           dtype=torch.bfloat16)
+    mdt = torch.bfloat16 if prec == kfb.KFB_BF16_MIXED else torch.float32
+    srv = serve.Server(layers, n_max=N_BATCH, rho=RHO, prec=prec, streams=4 if grouped else 1,
+                       byte_budget=24 << 30, max_group=48 if grouped else 1,
+                       max_inflight=None if grouped else 1)
+    # two runs of nreq requests, 70% of them updates, half on each side: ~0.7 nreq per side
+    pool = _BatchPool(torch, dev, int(0.75 * nreq) + 2 * L + 64, N_BATCH, D, seed=5000 + prec, dtype=mdt)
     gen = torch.Generator(device=dev)
     gen.manual_seed(11)
     grads = [torch.randn(D, D, generator=gen, device=dev) for _ in range(L)]
@@ -123,7 +189,7 @@ def serve_leg(torch, kfb, dev, args):
     for j in range(2):  # bring every state to r + n modes
         for l in range(L):
             for side in ("A", "G"):
-                srv.submit(serve.UpdateRequest(l, side, pool[(l, side)][j]))
+                srv.submit(serve.UpdateRequest(l, side, pool.take(side)))
     srv.drain()
     torch.cuda.synchronize()
 
@@ -131,19 +197,21 @@ def serve_leg(torch, kfb, dev, args):
         l = int(rng.integers(L))
         if rng.random() < 0.7:
             side = "A" if rng.random() < 0.5 else "G"
-            return serve.UpdateRequest(l, side, pool[(l, side)][i % 2])
+            return serve.UpdateRequest(l, side, pool.take(side))
         return serve.PrecondRequest(l, grads[l], outs[l], LAM, LAM)
 
-    for rate in [float(x) for x in args.serve_rates.split(",") if x]:
-        srv.stats = serve.ServerStats()
-        wall, done = serve.poisson_run(srv, make, rate, args.serve_requests, seed=int(rate))
-        lat_ms = [1e3 * (r.t_done - r.t_arrival) for r in done]
-        upd = sum(1 for r in done if isinstance(r, serve.UpdateRequest))
-        res[f"{int(rate)}_req_per_s"] = {
-            "requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
-            "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
-            "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
-            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
+    res = {"mode": "continuous batching, grouped launches" if grouped else "one request at a time, no grouping"}
+    srv.stats = serve.ServerStats()
+    wall, done = serve.poisson_run(srv, make, 2000.0, nreq, seed=2000 + prec, timeout_s=600.0)
+    res["2000_req_per_s"] = _serve_stats(serve, srv, wall, done)
+    sat = res["2000_req_per_s"]["achieved_req_per_s"]
+    half = max(0.5 * sat, 1.0)
+    srv.stats = serve.ServerStats()
+    wall, done = serve.poisson_run(srv, make, half, nreq, seed=1000 + prec, timeout_s=900.0)
+    res["half_saturation"] = dict(_serve_stats(serve, srv, wall, done), offered_req_per_s=round(half, 1))
+    res["pool_batches"] = len(pool.sets["A"]) + len(pool.sets["G"])
+    res["batches_used"] = pool.next["A"] + pool.next["G"]
+    del pool, srv
     return res
 
 
@@ -193,7 +261,7 @@ def serve_mixed_leg(torch, kfb, dev, args):
 
     res = {"widths": widths, "ranks": [(a, g) for (_, _, a, g) in layers]}
     # an offered rate far above capacity (throughput) and one below it (latency)
-    for rate, nreq in ((2000.0, args.serve_requests), (150.0, max(args.serve_requests // 2, 1))):
+    for rate, nreq in ((2000.0, args.serve_requests_uneven), (150.0, max(args.serve_requests_uneven // 2, 1))):
         srv.stats = serve.ServerStats()
         wall, done = serve.poisson_run(srv, make, rate, nreq, seed=2024 + int(rate))
         lat_ms = [1e3 * (r.t_done - r.t_arrival) for r in done]
@@ -220,8 +288,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-updates", type=int, default=6)
     ap.add_argument("--graph-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=1200)
-    ap.add_argument("--serve-rates", default="400,2000")
+    ap.add_argument("--fp32-grouped-steps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-requests-fp32", type=int, default=10000)
+    ap.add_argument("--serve-requests-uneven", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -245,10 +315,14 @@ def main():
 
     # ---- states: even index = A factor (d_in), odd = Gamma factor (d_out) of a layer
     states = [kfb.Factor(D, R, N_BATCH, RHO, MIX, device=dev) for _ in range(S)]
-    batches = [_gen_batches(torch, dev, S, N_BATCH, D, seed=1000 + j, dtype=torch.bfloat16) for j in range(2)]
+    # a fresh synthetic batch for every state at every step and a fresh gradient for
+    # every layer at every step, all generated into HBM before the timed region (no
+    # batch repeats: an absorbed batch lies in span(U) and would degenerate the core)
+    nsets = 1 + args.warmup + args.steps
+    batches = [_gen_batches(torch, dev, S, N_BATCH, D, seed=1000 + j, dtype=torch.bfloat16) for j in range(nsets)]
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
-    Gs = [torch.randn(D, D, generator=gen, device=dev) for _ in range(L)]
+    Gsets = [[torch.randn(D, D, generator=gen, device=dev) for _ in range(L)] for _ in range(nsets)]
     Ss = [torch.empty(D, D, device=dev) for _ in range(L)]
     ws_u, ws_p = kfb.Workspace(dev), kfb.Workspace(dev)
     fa = states[0::2]
@@ -256,13 +330,13 @@ def main():
     lam = [LAM] * L
 
     def step(j):
-        kfb.update_batched(states, batches[j % 2], ws_u)
-        kfb.precondition_batched(fg, fa, Gs, Ss, lam, lam, 0, ws_p)
+        kfb.update_batched(states, batches[j], ws_u)
+        kfb.precondition_batched(fg, fa, Gsets[j], Ss, lam, lam, 0, ws_p)
 
     # first update takes every state from empty to n modes; warmup reaches r + n
-    kfb.update_batched(states, batches[1], ws_u)
+    kfb.update_batched(states, batches[0], ws_u)
     for j in range(args.warmup):
-        step(j)
+        step(1 + j)
     torch.cuda.synchronize()
 
     # ---- timed region (stage events recorded live on the same stream)
@@ -273,7 +347,7 @@ def main():
     t0 = time.perf_counter()
     ev[0].record()
     for j in range(args.steps):
-        step(j)
+        step(1 + args.warmup + j)
         ev[j + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -339,43 +413,60 @@ def main():
 
     # ---- the same step replayed from a HIP graph: two consecutive steps captured
     # (every state's front and back buffers trade roles twice and end as they
-    # began), replayed graph_steps / 2 times; the library launches only kernels
-    # on the caller's stream, so the whole step is capturable
+    # began) over two batch slots; before each replay the next two fresh batch
+    # sets are copied into the slots (device-to-device, inside the timed region:
+    # ~200 MB per replay), so no replay re-feeds a batch; the library launches
+    # only kernels on the caller's stream, so the whole step is capturable
     graph_replay = None
     if args.graph_steps > 0:
+        reps = max(args.graph_steps // 2, 1)
+        gsets = [_gen_batches(torch, dev, S, N_BATCH, D, seed=3000 + j, dtype=torch.bfloat16)
+                 for j in range(2 * reps + 2)]
+        slots = [[torch.empty_like(b) for b in batches[0]] for _ in range(2)]
+
+        def gstep(q):
+            kfb.update_batched(states, slots[q], ws_u)
+            kfb.precondition_batched(fg, fa, Gsets[q], Ss, lam, lam, 0, ws_p)
+
+        def refill(j):
+            for q in range(2):
+                for dst, src in zip(slots[q], gsets[2 * j + q]):
+                    dst.copy_(src)
         torch.cuda.synchronize()
+        refill(reps)   # capture-time contents (the capture performs no work)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            step(0)
-            step(1)
+            gstep(0)
+            gstep(1)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
-        reps = max(args.graph_steps // 2, 1)
         t0 = time.perf_counter()
-        for _ in range(reps):
+        for j in range(reps):
+            refill(j)
             graph.replay()
         torch.cuda.synchronize()
         gwall = time.perf_counter() - t0
         graph_replay = {"value": round(S * 2 * reps / gwall, 2), "unit": "B-updates/s",
                         "ms_per_step": round(1e3 * gwall / (2 * reps), 3), "steps": 2 * reps,
                         "note": "the timed step (grouped updates + grouped preconditioning) captured "
-                                "in one HIP graph and replayed"}
-        del graph
+                                "in one HIP graph and replayed; fresh batches copied into the graph's "
+                                "input slots before each replay (copies timed)"}
+        del graph, gsets, slots
 
     _progress("timed steps and graph replay done")
-    # ---- FP32 plain form: one state at a time, no grouping
+    # ---- FP32 plain form: one state at a time, no grouping, fresh batch per update
     f32 = [kfb.Factor(D, R, N_BATCH, RHO, kfb.KFB_FP32, device=dev) for _ in range(2)]
-    b32 = _gen_batches(torch, dev, 2, N_BATCH, D, seed=99, dtype=torch.float32)
-    for _ in range(2):
-        for f, M in zip(f32, b32):
-            f.update(M)
+    b32 = _gen_batches(torch, dev, 4 + args.fp32_updates, N_BATCH, D, seed=99, dtype=torch.float32)
+    for j in range(2):
+        for i, f in enumerate(f32):
+            f.update(b32[2 * j + i])
     torch.cuda.synchronize()
     lat32 = []
     for i in range(args.fp32_updates):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        f32[i % 2].update(b32[i % 2])
+        f32[i % 2].update(b32[4 + i])
         e1.record()
         torch.cuda.synchronize()
         lat32.append(e0.elapsed_time(e1))
@@ -384,6 +475,37 @@ def main():
         fp32_plain = {"value": round(1e3 / (sum(lat32) / len(lat32)), 2), "unit": "B-updates/s",
                       "ms_per_update_p50": round(_percentile(lat32, 50), 3), "states": 2,
                       "mode": "one update at a time, no grouping"}
+    del f32, b32
+
+    # ---- FP32 form grouped like the headline (48 states, one grouped update and
+    # 24 grouped preconditionings per step, fresh inputs): isolates the precision
+    # form's effect from the grouping's
+    fp32_grouped = None
+    if args.fp32_grouped_steps > 0:
+        st32 = [kfb.Factor(D, R, N_BATCH, RHO, kfb.KFB_FP32, device=dev) for _ in range(S)]
+        nq = 3 + args.fp32_grouped_steps
+        bq = [_gen_batches(torch, dev, S, N_BATCH, D, seed=5000 + j, dtype=torch.float32) for j in range(nq)]
+        fa32, fg32 = st32[0::2], st32[1::2]
+        wsu32, wsp32 = kfb.Workspace(dev), kfb.Workspace(dev)
+
+        def step32(j):
+            kfb.update_batched(st32, bq[j], wsu32)
+            kfb.precondition_batched(fg32, fa32, Gsets[j % nsets], Ss, lam, lam, 0, wsp32)
+        kfb.update_batched(st32, bq[0], wsu32)
+        step32(1)
+        step32(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(args.fp32_grouped_steps):
+            step32(3 + j)
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t0
+        fp32_grouped = {"value": round(S * args.fp32_grouped_steps / w32, 2), "unit": "B-updates/s",
+                        "ms_per_step": round(1e3 * w32 / args.fp32_grouped_steps, 3),
+                        "steps": args.fp32_grouped_steps,
+                        "mode": f"FP32 form, the headline step: grouped update of {S} states + grouped "
+                                f"preconditioning of {L} layers, fresh batches"}
+        del st32, bq, wsu32, wsp32
 
     _progress("fp32 leg done")
     # ---- factored (linear-cost) application, Algorithm 8: the gradient of each
@@ -450,17 +572,23 @@ def main():
     _progress("brkfac leg done")
     # ---- single mixed update latency (no grouping), for the latency columns
     lat1 = []
+    b1 = _gen_batches(torch, dev, 6, N_BATCH, D, seed=4000, dtype=torch.bfloat16)
     for i in range(6):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        states[i].update(batches[0][i])
+        states[i].update(b1[i])
         e1.record()
         torch.cuda.synchronize()
         lat1.append(e0.elapsed_time(e1))
 
-    serving = serve_leg(torch, kfb, dev, args) if args.serve_requests > 0 else None
-    _progress("serving leg done")
-    serving_mixed = serve_mixed_leg(torch, kfb, dev, args) if args.serve_requests > 0 else None
+    serving = serving32 = None
+    if args.serve_requests > 0:
+        serving = serve_leg(torch, kfb, dev, args, MIX, args.serve_requests, grouped=True)
+        _progress("serving leg (mixed) done")
+    if args.serve_requests_fp32 > 0:
+        serving32 = serve_leg(torch, kfb, dev, args, kfb.KFB_FP32, args.serve_requests_fp32, grouped=False)
+        _progress("serving leg (fp32 plain) done")
+    serving_mixed = serve_mixed_leg(torch, kfb, dev, args) if args.serve_requests_uneven > 0 else None
     _progress("uneven serving leg done")
 
     out = {
@@ -487,8 +615,10 @@ def main():
                        "single_update_p99": round(_percentile(lat1, 99), 3),
                        "note": "closed loop; step = 48 updates + 24 preconditionings"},
         "fp32_plain": fp32_plain,
+        "fp32_grouped": fp32_grouped,
         "graph_replay": graph_replay,
         "serving": serving,
+        "serving_fp32_plain": serving32,
         "serving_uneven": serving_mixed,
         "roofline": roofline,
         "stages": stages,

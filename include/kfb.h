@@ -62,7 +62,9 @@ enum kfb_status_code {
 
 /* kfb_precondition flags */
 enum kfb_flags {
-  KFB_SPECTRUM_CONTINUATION = 1, /* Section 3.5: lam += min(D), D -= min(D) per factor */
+  KFB_SPECTRUM_CONTINUATION = 1, /* Section 3.5: lam += m, D -= m per factor, m the smallest
+                                    positive eigenvalue of the modes used (a mode of eigenvalue 0
+                                    is an empty slot: a dropped null direction or padding) */
   KFB_TRUNCATE_AFTER = 2,        /* apply with the leading r modes only (default: all r+n) */
   KFB_RELATIVE_DAMPING = 4       /* Section 6: lam = phi * lambda_max per factor, the lam argument
                                     being phi and lambda_max the largest eigenvalue of the modes
@@ -82,13 +84,16 @@ enum kfb_event {
 
 /* Bytes of the state buffer for a factor of width d, truncation rank r and
  * batch capacity n_max: two U buffers (d x (r+n_max), front/back) and two
- * eigenvalue vectors, plus a status word.  Returns 0 on invalid sizes. */
+ * eigenvalue vectors, plus a status word.  Returns 0 on invalid sizes:
+ * d < 1, r < 0, n_max < 1, r + n_max > d (Brand needs r + n <= d, Section 2.3),
+ * n_max > 2048 (the widest residual the CholeskyQR kernels factor) or
+ * r + n_max > 4096 (the largest core the eigensolver finalises). */
 size_t kfb_state_bytes(int64_t d, int32_t r, int32_t n_max, int32_t prec);
 
 /* Create a handle over a caller-owned state buffer of kfb_state_bytes bytes.
  * rho is the EA decay (Section 2.1).  The state starts empty (no modes); the
  * first update uses batch weight 1/n, later ones (1 - rho)/n.
- * Requires 1 <= n_max, 0 <= r, r + n_max <= d (Brand needs r + n <= d). */
+ * Requires the sizes kfb_state_bytes accepts and 0 <= rho < 1 (KFB_EINVAL). */
 int kfb_state_create(kfb_state_t* out, int64_t d, int32_t r, int32_t n_max, double rho,
                      int32_t prec, void* state_buf, size_t state_bytes, kfb_stream_t stream);
 
@@ -103,7 +108,9 @@ size_t kfb_update_workspace_bytes(kfb_state_t st, int32_t n);
  *   U diag(D) U^T <- rho U diag(D) U^T + w M M^T   exactly (Algorithm 3),
  * with w = 1/n for the first update and (1 - rho)/n afterwards.
  * M: d x n column-major (ldm >= d); FP64 / FP32 / BF16 per the precision form.
- * After the call the state holds k_valid = min(k_valid, r) + n modes. */
+ * After the call the state holds k_valid = min(k_valid, r) + n modes.
+ * Errors (returned before anything is enqueued): KFB_EINVAL for a null
+ * pointer, n < 1, n > n_max or ldm < d; KFB_EWORKSPACE. */
 int kfb_brand_update(kfb_state_t st, const void* M, int64_t ldm, int32_t n, void* workspace,
                      size_t ws_bytes, kfb_stream_t stream);
 
@@ -122,10 +129,11 @@ int kfb_brand_update_batched(int32_t count, kfb_state_t const* states, const voi
  * update), so the result is the exact update by the real columns; the
  * padding's zero pivots in CholeskyQR are expected and not reported as rank
  * deficiency.  The state then holds min(k_valid, r) + n modes, the padded
- * ones with eigenvalue 0: they add nothing to the inverse (its coefficient
- * 1/(0 + lam) - 1/lam vanishes) and leave at the next truncation; with
- * KFB_SPECTRUM_CONTINUATION they make the minimum eigenvalue 0, i.e. no
- * shift, until then.  widths: HOST array of count values.  Workspace as
+ * ones empty (eigenvalue 0, zero column in U, sorted after every real mode):
+ * they add nothing to the inverse and spectrum continuation takes its minimum
+ * over the positive eigenvalues only, so a padded update leaves the same
+ * inverse as the unpadded one; the next truncation drops them.
+ * widths: HOST array of count values.  Workspace as
  * kfb_update_batched_workspace_bytes(count, states, n).  KFB_EINVAL for a
  * width outside 1..n. */
 int kfb_brand_update_batched_widths(int32_t count, kfb_state_t const* states, const void* const* Ms,
@@ -196,7 +204,7 @@ int kfb_precondition_factored_batched(int32_t count, kfb_state_t const* st_gamma
                                       uint32_t flags, void* workspace, size_t ws_bytes,
                                       kfb_stream_t stream);
 
-/* ---- B-R-KFAC (Section 3.4, Algorithm 5) ------------------------------------
+/* ---- B-R-KFAC (Section 3.3, Algorithm 5) ------------------------------------
  * Every T_RSVD steps B-R-KFAC replaces a factor's representation by a
  * randomized SVD of the dense EA factor of the previous step, in place of the
  * usual truncation, and then performs the B-update as usual.  The dense factor
@@ -236,7 +244,7 @@ int kfb_rsvd_overwrite(kfb_state_t st, const void* X, int64_t ldx, const void* O
                        int32_t oversample, int32_t power_its, void* workspace, size_t ws_bytes,
                        kfb_stream_t stream);
 
-/* ---- B-KFAC-C (Section 3.5, Algorithms 6 and 7) -----------------------------
+/* ---- B-KFAC-C (Section 3.4, Algorithms 6 and 7) -----------------------------
  * Light correction of the current representation against the dense EA factor
  * X of the same step (kept with kfb_dense_update):
  *   U_c = U[:, col_idx];  M_S = U_c^T X U_c = W L W^T;
@@ -265,12 +273,33 @@ int kfb_state_info(kfb_state_t st, int32_t* k_valid, int64_t* step, int64_t* d, 
 int kfb_state_front(kfb_state_t st, const void** U, int64_t* ldu, const void** D);
 
 /* Overwrite the state with a caller-supplied representation (checkpoint
- * restore, or seeding from a randomized SVD as the paper does at k = 0).
- * U (device, same element type as the state, d x k column-major, ld ldu) must
- * be orthonormal; D (device, same element type as the state's D) descending.
- * Stream-ordered copy. */
+ * restore, or seeding from a randomized SVD: Proposition 4.1 considers the
+ * process started by an RSVD at k = 0).  U (device, same element type as the
+ * state, d x k column-major, ld ldu) must be orthonormal; D (device, same
+ * element type as the state's D) finite, non-negative and descending.
+ * D is read back first (the call synchronises the stream) and a violation
+ * returns KFB_EINVAL with the state untouched; U is then copied and its
+ * column norms checked on the device: a column (of positive eigenvalue)
+ * whose squared norm is off 1 by more than the drift detector's threshold
+ * sets KFB_EV_ORTHO_DRIFT in the status word (see kfb_reorthonormalize).
+ * KFB_EINVAL also for k > min(d, r + n_max), ldu < d, step < 0. */
 int kfb_state_load(kfb_state_t st, const void* U, int64_t ldu, const void* D, int32_t k,
                    int64_t step, kfb_stream_t stream);
+
+/* Drift recovery (the method assumes an orthonormal U, Section 2.3; BF16 and
+ * FP32 products round it): re-orthonormalise the current representation
+ * without changing the matrix it stands for.  U = Q R by CholeskyQR, so
+ * U D U^T = Q (R D R^T) Q^T; the core R D R^T is diagonalised by the core
+ * eigensolver (square factor R diag(sqrt D)) and the state becomes
+ * (Q W, Lambda), modes descending; k_valid and the step count are unchanged.
+ * Meant for a state whose status word reported KFB_EV_ORTHO_DRIFT.  Modes of
+ * eigenvalue 0 with a zero column (empty slots) are dropped directions of the
+ * factorisation and set KFB_EV_CHOL_DEFICIENT.  Writes the back buffers and
+ * swaps.  Workspace: kfb_reorth_workspace_bytes (0 if k_valid > 2048).
+ * Errors: KFB_EEMPTY (no modes), KFB_EINVAL (k_valid > 2048, null or
+ * misaligned workspace), KFB_EWORKSPACE. */
+size_t kfb_reorth_workspace_bytes(kfb_state_t st);
+int kfb_reorthonormalize(kfb_state_t st, void* workspace, size_t ws_bytes, kfb_stream_t stream);
 
 /* Read and clear the device status word (synchronises the given stream). */
 int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);

@@ -14,7 +14,8 @@ bprocess  Oracle-D: the dense definition.  Keeps the d x d B-process iterate
           full symmetric eigendecomposition per step.
 brand     Oracle-B: the structured FP64 algorithm the paper states
           (Algorithm 3, Symmetric Brand, driven as in Algorithm 4, B-KFAC),
-          with a Householder thin QR and a dense eigh of the small core.
+          with a Householder thin QR and a dense eigh of the small core;
+          and the re-orthonormalisation of a drifted representation.
 precond   The regularised inverse applied on both sides of a layer gradient:
           dense Cholesky solves (definition), the low-rank spectral form of
           Algorithm 1 (its inverse-application lines), the factored form of
@@ -29,10 +30,10 @@ metrics   Basis-invariant comparisons (reconstruction, eigenvalues,
           metrics of the paper's numerical study (Section 4.2).
 """
 from .bprocess import DenseFactor, truncate_rank, sorted_eigh  # noqa: F401
-from .brand import BrandFactor, symmetric_brand  # noqa: F401
+from .brand import BrandFactor, symmetric_brand, reorthonormalize  # noqa: F401
 from .precond import (precondition_dense, lowrank_inverse_apply, precondition_lowrank,  # noqa: F401
                       precondition_factored, spectrum_continuation)
 from .rsvd import ea_update, range_basis, rsvd, rsvd_overwrite  # noqa: F401
 from .correct import light_correction  # noqa: F401
-from .metrics import (e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S,  # noqa: F401
+from .metrics import (e_rec_dense, e_rec_lowrank, e_D, e_orth, e_S, e_S_proj,  # noqa: F401
                       regularised_inverse_lowrank, e_inverse, e_angle)

@@ -77,3 +77,21 @@ class BrandFactor:
             Ut, Dt = self.U[:, :keep], self.rho * self.D[:keep]
         self.U, self.D = symmetric_brand(Ut, Dt, np.sqrt(w) * M)
         self.k += 1
+
+
+def reorthonormalize(U: np.ndarray, D: np.ndarray):
+    """Drift recovery: the matrix U diag(D) U^T re-expressed on an orthonormal basis.
+
+    The method assumes an orthonormal U (Section 2.3); rounded products let it
+    drift.  With U = Q R (Householder QR), U D U^T = Q (R D R^T) Q^T, and the
+    EVD R D R^T = W Lam W^T gives the representation (Q W, Lam): the same
+    matrix (Rayleigh-Ritz on span(U), exact in exact arithmetic), modes
+    sorted descending, eigenvalues clipped at 0."""
+    U = np.asarray(U, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    Q, R = np.linalg.qr(U, mode="reduced")
+    K = (R * D[None, :]) @ R.T
+    K = 0.5 * (K + K.T)
+    lam, W = np.linalg.eigh(K)
+    order = np.argsort(-lam, kind="stable")
+    return Q @ W[:, order], np.clip(lam[order], 0.0, None)

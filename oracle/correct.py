@@ -3,11 +3,11 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 Parity unpinned: none.  Pinned in tests/test_oracle_pins.py: the projected
 error vanishes on the corrected subspace, the error never grows (the
-orthogonal-split argument of Section 3.5's footnote), orthonormality and the
+orthogonal-split argument of Section 3.4's footnote), orthonormality and the
 untouched modes are kept, and with every mode selected the correction is the
 Rayleigh-Ritz projection of the EA factor (library eigendecomposition).
 
-Algorithm 6 (Section 3.5): from the B-KFAC representation (U, D), pick n_crc
+Algorithm 6 (Section 3.4): from the B-KFAC representation (U, D), pick n_crc
 of the leading r columns at random without replacement (the indices are an
 input here: the method's random draws come from the input generator), project
 the EA factor onto them, M_S = U_c^T M U_c, take its symmetric EVD

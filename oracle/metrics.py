@@ -66,6 +66,23 @@ def e_S(S1, S2) -> float:
     return float(np.linalg.norm(S1 - S2) / np.linalg.norm(S2))
 
 
+def e_S_proj(S1, S2, UG, UA) -> float:
+    """|| UG^T (S1 - S2) UA ||_F / || UG^T S2 UA ||_F.
+
+    The two-sided inverse (Section 2.1; the spectral form of Algorithm 1's
+    inverse lines) maps the part of G outside span(UG) x span(UA) by the plain
+    scalar 1/(lam_G lam_A); with a small lambda that part dominates ||S||_F and
+    hides errors in the low-rank terms.  Restricted to the modes' span, the
+    error is measured where the representations act.  UG, UA: orthonormal
+    bases of the modes used (the oracle's)."""
+    D = np.asarray(S1, dtype=np.float64) - np.asarray(S2, dtype=np.float64)
+    UG = np.asarray(UG, dtype=np.float64)
+    UA = np.asarray(UA, dtype=np.float64)
+    num = np.linalg.norm(UG.T @ D @ UA)
+    den = np.linalg.norm(UG.T @ np.asarray(S2, dtype=np.float64) @ UA)
+    return float(num / den)
+
+
 # ----------------------------------------------------------------------------
 # The error metrics of the paper's numerical error study (Section 4.2): an
 # approximate algorithm against K-FAC holding the exact regularised inverse of

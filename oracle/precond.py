@@ -15,7 +15,12 @@ applied first on the right (A side), then on the left (Gamma side).
 Algorithm 8 (Section 5) applies each side to the factored gradient
 J = G_k A_k^T instead:  S = [inv(Gamma) G_k] [A_k^T inv(A)].
 
-Section 3.5 (spectrum continuation): lam <- lam + min(D), D <- D - min(D).
+Section 3.5 (spectrum continuation): the eigenvalues missing from the
+low-rank representation are set to the smallest kept one, i.e.
+lam <- lam + m, D <- D - m with m the smallest kept eigenvalue.  Reading: a
+mode of eigenvalue exactly 0 is not a kept mode (it is an empty slot, a zero
+column left by a dropped null direction or by zero padding), so m is the
+smallest positive eigenvalue; such slots stay at 0 and add nothing.
 """
 from __future__ import annotations
 
@@ -52,6 +57,8 @@ def precondition_factored(UG, DG, UA, DA, Gk, Ak, lamG: float, lamA: float):
 
 
 def spectrum_continuation(D: np.ndarray, lam: float):
-    """Section 3.5: missing eigenvalues are set to the smallest kept one."""
-    m = float(np.min(D)) if D.size else 0.0
-    return D - m, lam + m
+    """Section 3.5: missing eigenvalues are set to the smallest kept (positive) one."""
+    D = np.asarray(D, dtype=np.float64)
+    pos = D[D > 0]
+    m = float(np.min(pos)) if pos.size else 0.0
+    return np.maximum(D - m, 0.0), lam + m

@@ -7,7 +7,7 @@ an explicit matrix power, the rank-l reconstruction identity, a probabilistic
 error bound of the randomized range finder, and the overwrite case of
 Proposition 3.2 together with the optimality of Proposition 3.1.
 
-What the paper fixes (Section 3.4, Algorithm 5, B-R-KFAC): every T_RSVD
+What the paper fixes (Section 3.3, Algorithm 5, B-R-KFAC): every T_RSVD
 steps the B-KFAC representation of a factor is overwritten by an RSVD of the
 dense EA factor of the previous step, in place of the usual truncation, and
 the B-update then proceeds as in Algorithm 4.  The dense EA factor is the

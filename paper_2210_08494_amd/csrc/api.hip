@@ -136,6 +136,9 @@ template <> struct Ty<KFB_BF16_MIXED> {
 
 constexpr int MAX_SWEEPS = 20;
 
+// threshold of the orthonormality-drift detector on squared column norms
+inline double drift_tol(int prec) { return prec == KFB_FP64 ? 1e-10 : (prec == KFB_FP32 ? 1e-4 : 1e-3); }
+
 // ---------------------------------------------------------------------------
 // Brand-update plan: workspace layout of one problem for a shape bucket.
 // ---------------------------------------------------------------------------
@@ -164,6 +167,8 @@ constexpr int PRE_MIN_N = 128, PRE_SWEEPS = 5;
 template <int PR>
 bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, UpdPlan* p) {
   typedef Ty<PR> T;
+  // the CholeskyQR kernels and the eigensolver's finalize bound the widths
+  if (n < 1 || r < 0 || n > MAX_QR_COLS || r + n > MAX_CORE) return false;
   p->d = d; p->ldu = ldu; p->ldm = ldm; p->r = r; p->n = n; p->N = r + n;
   // the tuning table's entry for N, else (FP64 cores of N >= 256) 64-column
   // panels streamed from global memory, the autotuner's pick at the headline
@@ -457,8 +462,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   StageTimer st_rot("rotate", s, 2);
   KFB_TRY((mm<PR, 1, TU, TW, TU, TU, TA>(drecs, nrec, ro, s)));
   // drift detector on the new basis (column norms)
-  const double drift_tol = PR == KFB_FP64 ? 1e-10 : (PR == KFB_FP32 ? 1e-4 : 1e-3);
-  KFB_TRY((ortho_check<TU, TD>(drecs, nrec, U_BACK, D_BACK, d, ldu, N, drift_tol, s)));
+  KFB_TRY((ortho_check<TU, TD>(drecs, nrec, U_BACK, D_BACK, d, ldu, N, drift_tol(PR), s)));
   return KFB_OK;
 }
 
@@ -811,6 +815,92 @@ int run_correct(const Rec* drecs, const CorrPlan& cp, int k, int64_t ldx, hipStr
   return KFB_OK;
 }
 
+// Re-orthonormalisation of a representation whose basis has drifted
+// (Rayleigh-Ritz on its own span): U = Q R by CholeskyQR, so that
+// U D U^T = Q (R D R^T) Q^T; the k x k core R D R^T, with the square factor
+// R diag(sqrt(D)), goes through the core eigensolver, W Lambda W^T, and the
+// state becomes (Q W, Lambda): the same matrix on an orthonormal basis.
+template <int PR>
+int run_reorth(const Rec* drecs, const UpdPlan& p, int64_t oDs, hipStream_t s) {
+  typedef Ty<PR> T;
+  typedef typename T::U TU; typedef typename T::Z TZ; typedef typename T::P TP; typedef typename T::G TG;
+  typedef typename T::Core TC; typedef typename T::W TW; typedef typename T::D TD; typedef typename T::Acc TA;
+  const int64_t d = p.d;
+  const int k = p.n;
+  int64_t oQ, oR;
+  {
+    StageTimer st("reorth_qr", s, 3 + thin_qr_launches(PR, p.ksG));
+    KFB_TRY((copy2d<TZ, TU>(drecs, 1, op(WS, p.oZ, 1, d), op(U_FRONT, 0, 1, p.ldu), (int)d, k, s)));
+    const int rc = thin_qr<PR>(drecs, 1, p, p.oZ, p.oZb, &oQ, &oR, s);
+    if (rc != KFB_OK) return rc;
+    // R <- R diag(sqrt(D))
+    KFB_TRY((copy2d<TG, TD>(drecs, 1, op(WS, oDs, 1, k), op(D_FRONT, 0, 1, k), k, 1, s)));
+    KFB_TRY(sqrt_prefix<TG>(drecs, 1, WS, oDs, k, s));
+    ScaleArgs sc;
+    sc.m = k; sc.n = k; sc.X = op(WS, oR, 1, k); sc.row_slot = -1; sc.row_off = 0;
+    sc.col_slot = WS; sc.col_off = oDs; sc.extra_mode = 0;
+    KFB_TRY((scale2d<TG, TG>(drecs, 1, sc, s)));
+  }
+  CoreArgs co;
+  co.r = 0; co.n = k; co.N = k; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = -1;
+  co.off_R = oR; co.off_B = p.oB; co.off_V = p.oV;
+  {
+    StageTimer st("core", s, 2);
+    KFB_TRY((assemble_core<TC, TP, TG, TD>(drecs, 1, co, s)));
+    KFB_TRY(zero_words(drecs, 1, WS, p.oCnt, MAX_SWEEPS, s));
+  }
+  {
+    const int rc = core_evd<PR>(drecs, 1, p, s);
+    if (rc != KFB_OK) return rc;
+  }
+  StageTimer st("reorth_rotate", s, 2);
+  GemmArgs ro;
+  ro.A = op(WS, oQ, 1, d); ro.B = op(WS, p.oW, 1, k); ro.C = op(U_BACK, 0, 1, p.ldu);
+  ro.m = (int)d; ro.n = k; ro.k = k;
+  KFB_TRY((mm<PR, 1, TZ, TW, TU, TU, TA>(drecs, 1, ro, s)));
+  KFB_TRY((ortho_check<TU, TD>(drecs, 1, U_BACK, D_BACK, d, p.ldu, k, drift_tol(PR), s)));
+  return KFB_OK;
+}
+
+int dispatch_reorth(kfb_state_t st, void* workspace, size_t ws_bytes, hipStream_t s, size_t* need_only) {
+  if (!st) return KFB_EINVAL;
+  const int k = st->k_valid;
+  if (k <= 0) return KFB_EEMPTY;
+  if (k > MAX_QR_COLS) return KFB_EINVAL;
+  UpdPlan p;
+  bool ok = false;
+  if (st->prec == KFB_FP64) ok = make_upd_plan<KFB_FP64>(st->d, st->ldu, st->d, 0, k, 1, &p);
+  else if (st->prec == KFB_FP32) ok = make_upd_plan<KFB_FP32>(st->d, st->ldu, st->d, 0, k, 1, &p);
+  else ok = make_upd_plan<KFB_BF16_MIXED>(st->d, st->ldu, st->d, 0, k, 1, &p);
+  if (!ok) return KFB_EINVAL;
+  const int64_t oDs = (int64_t)p.per_problem;  // sqrt(D) in the Gram type (8 bytes suffice for all forms)
+  const size_t head = align256(sizeof(Rec));
+  const size_t need = head + p.per_problem + align256((size_t)k * 8);
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!workspace) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  Rec host;
+  memset(&host, 0, sizeof(Rec));
+  host.p[U_FRONT] = st->buf + st->off_U[st->front];
+  host.p[U_BACK] = st->buf + st->off_U[1 - st->front];
+  host.p[WS] = (char*)workspace + head;
+  host.p[D_FRONT] = st->buf + st->off_D[st->front];
+  host.p[D_BACK] = st->buf + st->off_D[1 - st->front];
+  host.p[STATUS] = st->buf + st->off_status;
+  host.s[0] = 0.0;  // the core is the square factor alone: no decayed modes,
+  host.s[1] = 1.0;  // unit weight
+  Rec* dev = (Rec*)workspace;
+  if (upload_recs(&host, 1, dev, s) != hipSuccess) return KFB_EHIP;
+  int rc;
+  if (st->prec == KFB_FP64) rc = run_reorth<KFB_FP64>(dev, p, oDs, s);
+  else if (st->prec == KFB_FP32) rc = run_reorth<KFB_FP32>(dev, p, oDs, s);
+  else rc = run_reorth<KFB_BF16_MIXED>(dev, p, oDs, s);
+  if (rc != KFB_OK) return rc;
+  st->front = 1 - st->front;
+  return KFB_OK;
+}
+
 inline int upd_r_eff(kfb_state_t st) { return st->k_valid < st->r ? st->k_valid : st->r; }
 
 int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, int64_t ldm, int32_t n,
@@ -1152,6 +1242,7 @@ extern "C" {
 
 size_t kfb_state_bytes(int64_t d, int32_t r, int32_t n_max, int32_t prec) {
   if (d <= 0 || r < 0 || n_max <= 0 || (int64_t)r + n_max > d) return 0;
+  if (n_max > MAX_QR_COLS || (int64_t)r + n_max > MAX_CORE) return 0;
   if (prec < KFB_FP64 || prec > KFB_BF16_MIXED) return 0;
   const int64_t cap = (int64_t)r + n_max;
   const size_t ub = align256((size_t)ldu_for(d, prec) * cap * u_elem(prec));
@@ -1367,13 +1458,50 @@ int kfb_state_load(kfb_state_t st, const void* U, int64_t ldu, const void* D, in
   hipStream_t s = (hipStream_t)stream;
   const size_t ue = u_elem(st->prec), de = d_elem(st->prec);
   if (k > 0) {
-    KFB_TRY(hipMemcpy2DAsync(st->buf + st->off_U[st->front], (size_t)st->ldu * ue, U, (size_t)ldu * ue,
-                             (size_t)st->d * ue, (size_t)k, hipMemcpyDeviceToDevice, s));
-    KFB_TRY(hipMemcpyAsync(st->buf + st->off_D[st->front], D, (size_t)k * de, hipMemcpyDeviceToDevice, s));
+    // the eigenvalues must be finite, non-negative and descending (truncation
+    // keeps the leading modes): read back and checked before anything is written
+    std::vector<double> h((size_t)k);
+    if (de == 8) {
+      KFB_TRY(hipMemcpyAsync(h.data(), D, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+      KFB_TRY(hipStreamSynchronize(s));
+    } else {
+      std::vector<float> f((size_t)k);
+      KFB_TRY(hipMemcpyAsync(f.data(), D, (size_t)k * 4, hipMemcpyDeviceToHost, s));
+      KFB_TRY(hipStreamSynchronize(s));
+      for (int i = 0; i < k; ++i) h[(size_t)i] = (double)f[(size_t)i];
+    }
+    for (int i = 0; i < k; ++i) {
+      const double v = h[(size_t)i];
+      if (!(v >= 0.0) || !(v <= 1.7976931348623157e308)) return KFB_EINVAL;
+      if (i > 0 && v > h[(size_t)i - 1]) return KFB_EINVAL;
+    }
+    char* Uf = st->buf + st->off_U[st->front];
+    char* Df = st->buf + st->off_D[st->front];
+    KFB_TRY(hipMemcpy2DAsync(Uf, (size_t)st->ldu * ue, U, (size_t)ldu * ue, (size_t)st->d * ue, (size_t)k,
+                             hipMemcpyDeviceToDevice, s));
+    KFB_TRY(hipMemcpyAsync(Df, D, (size_t)k * de, hipMemcpyDeviceToDevice, s));
+    // unit column norms (the cheap half of orthonormality), as the drift detector
+    uint32_t* status = (uint32_t*)(st->buf + st->off_status);
+    const double tol = drift_tol(st->prec);
+    hipError_t e;
+    if (st->prec == KFB_FP64) e = loaded_norms<double, double>((const double*)Uf, st->ldu, st->d, k, (const double*)Df, tol, status, s);
+    else if (st->prec == KFB_FP32) e = loaded_norms<float, float>((const float*)Uf, st->ldu, st->d, k, (const float*)Df, tol, status, s);
+    else e = loaded_norms<float, double>((const float*)Uf, st->ldu, st->d, k, (const double*)Df, tol, status, s);
+    KFB_TRY(e);
   }
   st->k_valid = k;
   st->step = step;
   return KFB_OK;
+}
+
+size_t kfb_reorth_workspace_bytes(kfb_state_t st) {
+  size_t need = 0;
+  if (dispatch_reorth(st, nullptr, 0, nullptr, &need) != KFB_OK) return 0;
+  return need;
+}
+
+int kfb_reorthonormalize(kfb_state_t st, void* workspace, size_t ws_bytes, kfb_stream_t stream) {
+  return dispatch_reorth(st, workspace, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream) {

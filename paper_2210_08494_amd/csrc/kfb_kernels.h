@@ -4,6 +4,12 @@
 
 namespace kfb {
 
+// Size limits of the per-problem stages, checked by the host entry points
+// before anything is enqueued: the CholeskyQR factorisation kernels take at
+// most MAX_QR_COLS columns, the eigensolver's finalize at most MAX_CORE modes.
+constexpr int MAX_QR_COLS = 2048;
+constexpr int MAX_CORE = 4096;
+
 // ---- generic strided GEMM:  C = alpha * A(m x k) B(k x n) + beta * C0 -----
 // TA/TB/TC/TC0: element types of the operands; TAcc: accumulation type.
 // With g.ksplit > 1 the k range is cut into chunks whose partial products go
@@ -126,6 +132,13 @@ hipError_t scale2d(const Rec* recs, int nrec, const ScaleArgs& a, hipStream_t s)
 template <typename T, typename TD>
 hipError_t ortho_check(const Rec* recs, int nrec, int slot, int dslot, int64_t d, int64_t ld, int ncols, double tol,
                        hipStream_t s);
+
+// KFB_EV_ORTHO_DRIFT into *status when a column j < k of U (d x k, leading
+// dimension ld) with D[j] > 0 has |sum_i u_ij^2 - 1| > tol (plain pointers:
+// checks a representation handed in by the caller)
+template <typename T, typename TD>
+hipError_t loaded_norms(const T* U, int64_t ld, int64_t d, int k, const TD* D, double tol, uint32_t* status,
+                        hipStream_t s);
 
 // x_i <- sqrt(max(x_i, 0)), i < count, for the vector at rec.p[slot] + off
 template <typename T>

@@ -66,7 +66,7 @@ __device__ __forceinline__ To cvt(From x) { return static_cast<To>(x); }
 // never influence the update or the inverse application).
 // ---------------------------------------------------------------------------
 constexpr int CHOL_NT = 1024;
-constexpr int CHOL_MAXN = 2048;
+constexpr int CHOL_MAXN = MAX_QR_COLS;
 
 template <typename T>
 __global__ __launch_bounds__(CHOL_NT) void chol_inv_kernel(const Rec* __restrict__ recs, CholArgs a) {
@@ -1809,7 +1809,7 @@ hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, 
 // (one wave per column, the eigenvalue estimate stored unsorted in place),
 // then one workgroup per problem ranks them.
 // ---------------------------------------------------------------------------
-constexpr int FIN_MAXN = 4096;
+constexpr int FIN_MAXN = MAX_CORE;
 
 template <typename TCore>
 __global__ __launch_bounds__(256) void fin_norms_kernel(const Rec* __restrict__ recs, FinArgs a) {
@@ -1926,12 +1926,17 @@ __global__ __launch_bounds__(256) void precond_coefs_kernel(const Rec* __restric
     lams[1] = lA0;
     double mG = 0.0, mA = 0.0;
     if (a.flags & KFB_SPECTRUM_CONTINUATION) {
-      mG = a.kG > 0 ? (double)DG[0] : 0.0;
-      for (int i = 1; i < a.kG; ++i) mG = fmin(mG, (double)DG[i]);
-      mA = a.kA > 0 ? (double)DA[0] : 0.0;
-      for (int i = 1; i < a.kA; ++i) mA = fmin(mA, (double)DA[i]);
-      mG = fmax(mG, 0.0);
-      mA = fmax(mA, 0.0);
+      // smallest positive eigenvalue: a mode of eigenvalue exactly 0 is an
+      // empty slot (a dropped null direction of the residual, or the zero
+      // padding of an uneven-width batch) with a zero column in U
+      mG = INFINITY;
+      for (int i = 0; i < a.kG; ++i)
+        if ((double)DG[i] > 0.0) mG = fmin(mG, (double)DG[i]);
+      mA = INFINITY;
+      for (int i = 0; i < a.kA; ++i)
+        if ((double)DA[i] > 0.0) mA = fmin(mA, (double)DA[i]);
+      if (!(mG < INFINITY)) mG = 0.0;
+      if (!(mA < INFINITY)) mA = 0.0;
     }
     mins[0] = mG;
     mins[1] = mA;
@@ -2107,6 +2112,35 @@ hipError_t correct_permute(const Rec* recs, int nrec, const PermuteArgs& a, hipS
   return hipGetLastError();
 }
 
+// Check of a caller-supplied representation (kfb_state_load): one wave per
+// column j < k of U (d x k, leading dimension ld) flags KFB_EV_ORTHO_DRIFT in
+// *status when |sum_i u_ij^2 - 1| > tol (columns of eigenvalue 0 excepted).
+template <typename T, typename TD>
+__global__ __launch_bounds__(256) void loaded_norms_kernel(const T* __restrict__ U, int64_t ld, int64_t d, int k,
+                                                            const TD* __restrict__ D, double tol,
+                                                            uint32_t* status) {
+  const int j = blockIdx.x * 4 + threadIdx.x / 64, l = threadIdx.x % 64;
+  if (j >= k || !((double)D[j] > 0.0)) return;
+  const T* u = U + (int64_t)j * ld;
+  double sum = 0.0;
+  for (int64_t i = l; i < d; i += 64) {
+    const double v = (double)u[i];
+    sum = fma(v, v, sum);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (l == 0 && !(fabs(sum - 1.0) <= tol)) atomicOr(status, (uint32_t)KFB_EV_ORTHO_DRIFT);
+}
+
+template <typename T, typename TD>
+hipError_t loaded_norms(const T* U, int64_t ld, int64_t d, int k, const TD* D, double tol, uint32_t* status,
+                        hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL((loaded_norms_kernel<T, TD>), dim3((k + 3) / 4), dim3(256), 0, s, U, ld, d, k, D, tol,
+                     status);
+  return hipGetLastError();
+}
+
 // Drift detector: one wave per column, FP64 sum of squares
 // (columns of zero eigenvalue, left by a rank-deficient batch, are not checked)
 template <typename T, typename TD>
@@ -2139,6 +2173,12 @@ hipError_t ortho_check(const Rec* recs, int nrec, int slot, int dslot, int64_t d
 template hipError_t ortho_check<double, double>(const Rec*, int, int, int, int64_t, int64_t, int, double, hipStream_t);
 template hipError_t ortho_check<float, float>(const Rec*, int, int, int, int64_t, int64_t, int, double, hipStream_t);
 template hipError_t ortho_check<float, double>(const Rec*, int, int, int, int64_t, int64_t, int, double, hipStream_t);
+template hipError_t loaded_norms<double, double>(const double*, int64_t, int64_t, int, const double*, double,
+                                                 uint32_t*, hipStream_t);
+template hipError_t loaded_norms<float, float>(const float*, int64_t, int64_t, int, const float*, double, uint32_t*,
+                                               hipStream_t);
+template hipError_t loaded_norms<float, double>(const float*, int64_t, int64_t, int, const double*, double,
+                                                uint32_t*, hipStream_t);
 template hipError_t gather_cols<double>(const Rec*, int, const GatherArgs&, hipStream_t);
 template hipError_t gather_cols<float>(const Rec*, int, const GatherArgs&, hipStream_t);
 template hipError_t correct_merge<double, double>(const Rec*, int, const MergeArgs&, hipStream_t);

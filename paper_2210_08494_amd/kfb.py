@@ -63,6 +63,8 @@ _SIGS = {
     "kfb_state_front": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), ctypes.POINTER(_vp)]),
     "kfb_state_load": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i64, _vp]),
     "kfb_state_status": (ctypes.c_int, [_vp, ctypes.POINTER(_u32), _vp]),
+    "kfb_reorth_workspace_bytes": (_sz, [_vp]),
+    "kfb_reorthonormalize": (ctypes.c_int, [_vp, _vp, _sz, _vp]),
     "kfb_tune_set_jacobi": (ctypes.c_int, [_i32, _i32, _i32]),
     "kfb_tune_get_jacobi": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "kfb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -182,8 +184,7 @@ class Factor:
     def update(self, M, ws: Workspace | None = None):
         """M: device tensor of shape (n, d) (= column-major d x n), dtype per precision."""
         lib = load()
-        assert M.is_cuda and M.dim() == 2 and M.shape[1] == self.d and M.dtype == self.mdtype
-        assert M.stride(1) == 1
+        _batch_check(M, self, "update")
         n = int(M.shape[0])
         need = lib.kfb_update_workspace_bytes(self.handle, n)
         if need == 0:
@@ -212,6 +213,10 @@ class Factor:
     def load_state(self, U, D, step: int = 1):
         """Overwrite with (U: d x k device tensor in the state's dtype, D: k)."""
         lib = load()
+        if not (U.is_cuda and D.is_cuda and U.dim() == 2 and U.shape[0] == self.d and D.dim() == 1
+                and D.shape[0] == U.shape[1] and U.dtype == _dtype_of(self.prec) and D.dtype == _ddtype_of(self.prec)):
+            raise KfbError(f"load_state: expected U ({self.d}, k) {_dtype_of(self.prec)} and D (k,) "
+                           f"{_ddtype_of(self.prec)} device tensors")
         Uc = U.t().contiguous()  # k x d rows = columns of U
         k = int(Uc.shape[0])
         Dc = D.contiguous()
@@ -220,17 +225,52 @@ class Factor:
         import torch
         torch.cuda.current_stream().synchronize()
 
+    def reorthonormalize(self, ws: Workspace | None = None):
+        """Drift recovery: the same matrix on an orthonormal basis (Rayleigh-Ritz on span(U))."""
+        lib = load()
+        need = lib.kfb_reorth_workspace_bytes(self.handle)
+        if need == 0:
+            raise KfbError("kfb_reorth_workspace_bytes rejected the state (no modes, or more than 2048)")
+        w = (ws or self.ws).get(need)
+        _check(lib.kfb_reorthonormalize(self.handle, _ptr(w), int(w.numel()), _stream()), "kfb_reorthonormalize")
+
     def status(self) -> int:
         ev = _u32()
         _check(load().kfb_state_status(self.handle, ctypes.byref(ev), _stream()), "kfb_state_status")
         return ev.value
 
 
+def _batch_check(M, f: "Factor", what: str):
+    """A batch (or gradient factor) of the state f: (n, d) on f's device (the device of its state
+    buffer), f's batch dtype, rows contiguous."""
+    if not (M.dim() == 2 and M.shape[1] == f.d and M.dtype == f.mdtype and M.stride(1) == 1
+            and M.shape[0] >= 1 and M.device == f.buf.device):
+        raise KfbError(f"{what}: expected a ({'n'}, {f.d}) {f.mdtype} tensor with unit column stride on "
+                       f"{f.buf.device}, got {tuple(M.shape)} {M.dtype} strides {tuple(M.stride())} on {M.device}")
+
+
+def _grad_check(X, fg: "Factor", fa: "Factor", what: str):
+    """A layer gradient or step: (d_out, d_in) = (fg.d, fa.d), rows contiguous, on the states'
+    device, double in the FP64 form and float otherwise."""
+    dt = _dtype_of(fg.prec)
+    if not (X.dim() == 2 and tuple(X.shape) == (fg.d, fa.d) and X.stride(1) == 1
+            and X.stride(0) >= fa.d and X.dtype == dt and X.device == fg.buf.device):
+        raise KfbError(f"{what}: expected a ({fg.d}, {fa.d}) {dt} tensor with unit column stride on "
+                       f"{fg.buf.device}, got {tuple(X.shape)} {X.dtype} strides {tuple(X.stride())} on {X.device}")
+
+
+def _pair_check(fg: "Factor", fa: "Factor", what: str):
+    if fg is fa or fg.prec != fa.prec or fg.buf.device != fa.buf.device:
+        raise KfbError(f"{what}: the two sides must be distinct states of one precision form on one device")
+
+
 def precondition(fg: Factor, fa: Factor, G, S, lam_g: float, lam_a: float, flags: int = 0,
                  ws: Workspace | None = None):
     """S = (Gamma~ + lam_g I)^{-1} G (A~ + lam_a I)^{-1}; G, S row-major (d_out, d_in) device tensors."""
     lib = load()
-    assert G.shape == (fg.d, fa.d) and S.shape == G.shape and G.stride(1) == 1 and S.stride(1) == 1
+    _pair_check(fg, fa, "precondition")
+    _grad_check(G, fg, fa, "precondition (G)")
+    _grad_check(S, fg, fa, "precondition (S)")
     need = lib.kfb_precondition_workspace_bytes(fg.handle, fa.handle)
     if need == 0:
         raise KfbError("kfb_precondition_workspace_bytes rejected the states")
@@ -257,6 +297,8 @@ def update_batched(factors, Ms, ws: Workspace):
     lib = load()
     cnt = len(factors)
     _same_layout(Ms, "update_batched", cnt)
+    for f, M in zip(factors, Ms):
+        _batch_check(M, f, "update_batched")
     hs = (_vp * cnt)(*[f.handle.value for f in factors])
     ms = (_vp * cnt)(*[m.data_ptr() for m in Ms])
     n = int(Ms[0].shape[0])
@@ -273,6 +315,8 @@ def update_batched_widths(factors, Ms, widths, ws: Workspace):
     lib = load()
     cnt = len(factors)
     _same_layout(Ms, "update_batched_widths", cnt)
+    for f, M in zip(factors, Ms):
+        _batch_check(M, f, "update_batched_widths")
     if len(widths) != cnt:
         raise KfbError(f"update_batched_widths: {len(widths)} widths for {cnt} problems")
     hs = (_vp * cnt)(*[f.handle.value for f in factors])
@@ -294,6 +338,10 @@ def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):
     _same_layout(Ss, "precondition_batched (S)", cnt)
     if len(fas) != cnt or len(lam_g) != cnt or len(lam_a) != cnt:
         raise KfbError("precondition_batched: one A state and one lambda per side for every layer")
+    for fg, fa, G, S in zip(fgs, fas, Gs, Ss):
+        _pair_check(fg, fa, "precondition_batched")
+        _grad_check(G, fg, fa, "precondition_batched (G)")
+        _grad_check(S, fg, fa, "precondition_batched (S)")
     hg = (_vp * cnt)(*[f.handle.value for f in fgs])
     ha = (_vp * cnt)(*[f.handle.value for f in fas])
     gp = (_vp * cnt)(*[g.data_ptr() for g in Gs])
@@ -309,8 +357,8 @@ def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):
            "kfb_precondition_batched")
 
 
-def _factor_arg(X, f: "Factor"):
-    assert X.is_cuda and X.dim() == 2 and X.shape[1] == f.d and X.dtype == f.mdtype and X.stride(1) == 1
+def _factor_arg(X, f: "Factor", what: str = "gradient factor"):
+    _batch_check(X, f, what)
     return int(X.shape[0]), int(X.stride(0))
 
 
@@ -321,9 +369,12 @@ def precondition_factored(fg: Factor, fa: Factor, Gk, Ak, S, lam_g: float, lam_a
     Gk: (n, d_out) and Ak: (n, d_in) device tensors (= d x n column-major), the
     state's batch dtype; S row-major (d_out, d_in)."""
     lib = load()
-    n, ldgk = _factor_arg(Gk, fg)
-    n2, ldak = _factor_arg(Ak, fa)
-    assert n == n2 and S.shape == (fg.d, fa.d) and S.stride(1) == 1
+    _pair_check(fg, fa, "precondition_factored")
+    n, ldgk = _factor_arg(Gk, fg, "precondition_factored (G_k)")
+    n2, ldak = _factor_arg(Ak, fa, "precondition_factored (A_k)")
+    if n != n2:
+        raise KfbError(f"precondition_factored: G_k has {n} columns, A_k {n2}")
+    _grad_check(S, fg, fa, "precondition_factored (S)")
     need = lib.kfb_precondition_factored_workspace_bytes(fg.handle, fa.handle, n)
     if need == 0:
         raise KfbError("kfb_precondition_factored_workspace_bytes rejected the states")
@@ -336,8 +387,20 @@ def precondition_factored(fg: Factor, fa: Factor, Gk, Ak, S, lam_g: float, lam_a
 def precondition_factored_batched(fgs, fas, Gks, Aks, Ss, lam_g, lam_a, flags, ws: Workspace):
     lib = load()
     cnt = len(fgs)
+    _same_layout(Gks, "precondition_factored_batched (G_k)", cnt)
+    _same_layout(Aks, "precondition_factored_batched (A_k)", cnt)
+    _same_layout(Ss, "precondition_factored_batched (S)", cnt)
+    if len(fas) != cnt or len(lam_g) != cnt or len(lam_a) != cnt:
+        raise KfbError("precondition_factored_batched: one A state and one lambda per side for every layer")
+    for fg, fa, Gk, Ak, S in zip(fgs, fas, Gks, Aks, Ss):
+        _pair_check(fg, fa, "precondition_factored_batched")
+        _batch_check(Gk, fg, "precondition_factored_batched (G_k)")
+        _batch_check(Ak, fa, "precondition_factored_batched (A_k)")
+        _grad_check(S, fg, fa, "precondition_factored_batched (S)")
     n, ldgk = _factor_arg(Gks[0], fgs[0])
-    _, ldak = _factor_arg(Aks[0], fas[0])
+    n2, ldak = _factor_arg(Aks[0], fas[0])
+    if n != n2:
+        raise KfbError(f"precondition_factored_batched: G_k has {n} columns, A_k {n2}")
     hg = (_vp * cnt)(*[f.handle.value for f in fgs])
     ha = (_vp * cnt)(*[f.handle.value for f in fas])
     gp = (_vp * cnt)(*[g.data_ptr() for g in Gks])
@@ -354,6 +417,14 @@ def precondition_factored_batched(fgs, fas, Gks, Aks, Ss, lam_g, lam_a, flags, w
            "kfb_precondition_factored_batched")
 
 
+def _dense_check(X, f: "Factor", what: str):
+    dt = _dtype_of(f.prec)
+    if not (X.dim() == 2 and tuple(X.shape) == (f.d, f.d) and X.stride(1) == 1
+            and X.stride(0) >= f.d and X.dtype == dt and X.device == f.buf.device):
+        raise KfbError(f"{what}: expected a ({f.d}, {f.d}) {dt} dense factor on {f.buf.device}, got "
+                       f"{tuple(X.shape)} {X.dtype} on {X.device}")
+
+
 def dense_factor(f: Factor, device="cuda"):
     """A zeroed dense EA factor for the state f (d x d; row j of the tensor is column j)."""
     import torch
@@ -363,8 +434,8 @@ def dense_factor(f: Factor, device="cuda"):
 def dense_update(f: Factor, X, M, first: bool, ws: Workspace | None = None):
     """X <- rho X + (1 - rho)/n M M^T (first: M M^T / n), B-R-KFAC's dense EA factor of f."""
     lib = load()
-    assert X.is_cuda and X.dim() == 2 and X.shape == (f.d, f.d) and X.stride(1) == 1 and X.dtype == _dtype_of(f.prec)
-    n, ldm = _factor_arg(M, f)
+    _dense_check(X, f, "dense_update")
+    n, ldm = _factor_arg(M, f, "dense_update (M)")
     w = (ws or f.ws).get(lib.kfb_dense_update_workspace_bytes())
     _check(lib.kfb_dense_update(f.handle, _ptr(X), int(X.stride(0)), _ptr(M), ldm, n, 1 if first else 0, _ptr(w),
                                 int(w.numel()), _stream()), "kfb_dense_update")
@@ -373,9 +444,11 @@ def dense_update(f: Factor, X, M, first: bool, ws: Workspace | None = None):
 def rsvd_overwrite(f: Factor, X, Omega, oversample: int, power_its: int, ws: Workspace | None = None):
     """(U, D) of f <- the rank-r randomized SVD of X with the sketch Omega ((r + oversample, d) tensor)."""
     lib = load()
-    assert X.is_cuda and X.shape == (f.d, f.d) and X.stride(1) == 1 and X.dtype == _dtype_of(f.prec)
-    assert Omega.is_cuda and Omega.dim() == 2 and Omega.shape[1] == f.d and Omega.stride(1) == 1
-    assert Omega.dtype == X.dtype and Omega.shape[0] == f.r + oversample
+    _dense_check(X, f, "rsvd_overwrite")
+    if not (Omega.is_cuda and Omega.dim() == 2 and tuple(Omega.shape) == (f.r + oversample, f.d)
+            and Omega.stride(1) == 1 and Omega.dtype == X.dtype and Omega.device == X.device):
+        raise KfbError(f"rsvd_overwrite: Omega must be a ({f.r + oversample}, {f.d}) {X.dtype} tensor "
+                       f"with unit column stride on {X.device}")
     need = lib.kfb_rsvd_workspace_bytes(f.handle, int(oversample))
     if need == 0:
         raise KfbError("kfb_rsvd_workspace_bytes rejected the sizes")
@@ -388,7 +461,7 @@ def rsvd_overwrite(f: Factor, X, Omega, oversample: int, power_its: int, ws: Wor
 def light_correction(f: Factor, X, col_idx, ws: Workspace | None = None):
     """B-KFAC-C (Algorithm 6): correct the modes col_idx (host ints) of f against the dense EA factor X."""
     lib = load()
-    assert X.is_cuda and X.shape == (f.d, f.d) and X.stride(1) == 1 and X.dtype == _dtype_of(f.prec)
+    _dense_check(X, f, "light_correction")
     idx = [int(i) for i in col_idx]
     arr = (_i32 * len(idx))(*idx)
     need = lib.kfb_correct_workspace_bytes(f.handle, len(idx))

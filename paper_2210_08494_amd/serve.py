@@ -32,8 +32,15 @@ Scheduling (host side; all arithmetic runs in the HIP library):
 * groups go round-robin onto several default-priority HIP streams, each first
   waiting on the completion events of the last operations on its states, so
   work on different states overlaps on the device while per-state order holds;
+* a request's inputs may still be in production on the submitter's stream
+  (a backward pass enqueues M or G there and submits at once): ``submit``
+  records an event on the current stream, and the group that carries the
+  request waits on it before its first launch;
 * completion is observed by polling the group's event; latency is completion
-  minus arrival on the host clock.
+  minus arrival on the host clock.  Completed requests are handed to the
+  caller through ``sink`` (a list the caller owns, e.g. for one measured run)
+  and kept only in a bounded ``done_log`` otherwise, so a long-running server
+  holds no references to the tensors of old requests.
 """
 from __future__ import annotations
 
@@ -54,6 +61,7 @@ class UpdateRequest:
     t_done: float = 0.0
     rid: int = -1
     error: str = ""
+    ready: object = None      # event on the submitter's stream, recorded at submit
 
 
 @dataclass
@@ -68,6 +76,7 @@ class PrecondRequest:
     t_done: float = 0.0
     rid: int = -1
     error: str = ""
+    ready: object = None      # event on the submitter's stream, recorded at submit
 
 
 @dataclass
@@ -89,7 +98,6 @@ class ServerStats:
     preconds: int = 0
     groups: int = 0
     grouped_problems: int = 0
-    latencies: list = field(default_factory=list)
     max_inflight_bytes: int = 0
     rejected: int = 0
 
@@ -97,7 +105,7 @@ class ServerStats:
 class Server:
     def __init__(self, layers, n_max: int, rho: float = 0.95, prec: int = kfb.KFB_BF16_MIXED,
                  streams: int = 4, byte_budget: int = 8 << 30, max_group: int = 64, device="cuda",
-                 max_inflight: int | None = None, pad_updates: bool = False):
+                 max_inflight: int | None = None, pad_updates: bool = False, done_log_max: int = 1024):
         """layers: list of (d_in, d_out, r_A, r_G)."""
         import torch
         self.torch = torch
@@ -121,9 +129,11 @@ class Server:
         self.stats = ServerStats()
         self.hooks_before_issue = None   # optional callback(kind, reqs, stream), enqueued before the group
         self.hooks_after_issue = None    # optional callback(kind, reqs, stream), enqueued before its event
-        self.failed = []
-        self.done_log = []               # every completed request, in retirement order
+        self.failed = collections.deque(maxlen=done_log_max)
+        self.done_log = collections.deque(maxlen=done_log_max)   # the latest completions
+        self.sink = None                 # optional caller-owned list receiving every completion
         self._next_rid = 0
+        self._rest_prefix = 0
         self._lib = kfb.load()
 
     # ------------------------------------------------------------------ API
@@ -131,7 +141,12 @@ class Server:
         return self.fa[layer] if side == "A" else self.fg[layer]
 
     def submit(self, req, t_arrival: float | None = None):
+        """Queue a request.  Its tensors may still be being written on the caller's
+        current stream: the group that runs it waits for that work first."""
         req.t_arrival = time.perf_counter() if t_arrival is None else t_arrival
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.device))
+        req.ready = ev
         req.rid = self._next_rid
         self._next_rid += 1
         self.pending.append(req)
@@ -149,9 +164,11 @@ class Server:
             if g.event.query():
                 for r in g.reqs:
                     r.t_done = now
-                    self.stats.latencies.append(now - r.t_arrival)
+                    r.ready = None
                     done.append(r)
                     self.done_log.append(r)
+                    if self.sink is not None:
+                        self.sink.append(r)
                 self.inflight_bytes -= g.nbytes
                 self.stats.completed += len(g.reqs)
             else:
@@ -176,8 +193,13 @@ class Server:
                     issued += 1
                 else:
                     leftover.extend(chunk)
-        if leftover:  # back into the queue in arrival order (keeps per-state FIFO)
-            self.pending = collections.deque(sorted(list(self.pending) + leftover, key=lambda r: r.rid))
+        if leftover:
+            # back into the queue in arrival order (keeps per-state FIFO): they are
+            # older than every request the admission scan did not reach, so only the
+            # scanned prefix of the queue needs merging
+            head = [self.pending.popleft() for _ in range(min(self._rest_prefix, len(self.pending)))]
+            merged = sorted(head + leftover, key=lambda r: r.rid)
+            self.pending.extendleft(reversed(merged))
         return issued
 
     def drain(self, timeout_s: float = 120.0):
@@ -227,7 +249,11 @@ class Server:
         budget_left = self.byte_budget - self.inflight_bytes
         rest = collections.deque()
         est = {}
-        while self.pending:
+        # look at the oldest requests only: enough to fill every free slot with a
+        # full group several times over (a long backlog is not rescanned each tick)
+        scan = max(256, 4 * self.max_group * self.max_inflight)
+        while self.pending and scan > 0:
+            scan -= 1
             r = self.pending.popleft()
             sts = [f.handle.value for f in self._states_of(r)]
             if any(s in blocked or s in used for s in sts):
@@ -252,6 +278,7 @@ class Server:
             budget_left -= need
             used.update(sts)
             groups.setdefault(key, []).append(r)
+        self._rest_prefix = len(rest)
         rest.extend(self.pending)
         self.pending = rest
         return groups
@@ -263,6 +290,8 @@ class Server:
         nbytes = self._bytes_for(key, reqs)
         with torch.cuda.stream(stream):
             for r in reqs:
+                if r.ready is not None:          # inputs produced on the submitter's stream
+                    stream.wait_event(r.ready)
                 for f in self._states_of(r):
                     ev = self.last_event.get(f.handle.value)
                     if ev is not None:
@@ -321,16 +350,21 @@ def poisson_run(server: Server, make_request, rate: float, n_requests: int, seed
     import numpy as np
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n_requests)
-    t0 = time.perf_counter()
-    arrivals = t0 + np.cumsum(gaps)
-    start = len(server.done_log)
-    i = 0
-    while i < n_requests or server.busy():
-        now = time.perf_counter()
-        while i < n_requests and arrivals[i] <= now:
-            server.submit(make_request(i, rng), t_arrival=float(arrivals[i]))
-            i += 1
-        server.step()
-        if now - t0 > timeout_s:
-            raise TimeoutError("poisson run did not finish")
-    return time.perf_counter() - t0, server.done_log[start:]
+    done = []
+    prev_sink, server.sink = server.sink, done
+    try:
+        t0 = time.perf_counter()
+        arrivals = t0 + np.cumsum(gaps)
+        i = 0
+        while i < n_requests or server.busy():
+            now = time.perf_counter()
+            while i < n_requests and arrivals[i] <= now:
+                server.submit(make_request(i, rng), t_arrival=float(arrivals[i]))
+                i += 1
+            server.step()
+            if now - t0 > timeout_s:
+                raise TimeoutError("poisson run did not finish")
+        wall = time.perf_counter() - t0
+    finally:
+        server.sink = prev_sink
+    return wall, done

@@ -32,7 +32,10 @@ def tune_jacobi(prec: int, d: int, r: int, n: int, count: int = 8, reps: int = 3
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
     k = torch.arange(1, d + 1, device=dev, dtype=torch.float32)
-    Ms = [(torch.relu(torch.randn(n, d, generator=g, device=dev) * k ** -1.0)).to(mdt) for _ in range(count)]
+    # a fresh batch for every update: a batch already absorbed lies in span(U), its
+    # residual vanishes and the core degenerates, which would flatter the eigensolver
+    sets = [[(torch.relu(torch.randn(n, d, generator=g, device=dev) * k ** -1.0)).to(mdt) for _ in range(count)]
+            for _ in range(reps + 2)]
     ws = kfb.Workspace(dev)
     timings = {}
     for bw in candidates:
@@ -41,13 +44,13 @@ def tune_jacobi(prec: int, d: int, r: int, n: int, count: int = 8, reps: int = 3
         except kfb.KfbError:
             continue
         states = [kfb.Factor(d, r, n, 0.95, prec, device=dev) for _ in range(count)]
-        kfb.update_batched(states, Ms, ws)      # -> n modes
-        kfb.update_batched(states, Ms, ws)      # -> r + n modes (the tuned N)
+        kfb.update_batched(states, sets[0], ws)      # -> n modes
+        kfb.update_batched(states, sets[1], ws)      # -> r + n modes (the tuned N)
         torch.cuda.synchronize()
         ts = []
-        for _ in range(reps):
+        for j in range(reps):
             t0 = time.perf_counter()
-            kfb.update_batched(states, Ms, ws)
+            kfb.update_batched(states, sets[2 + j], ws)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         timings[bw] = sorted(ts)[len(ts) // 2]

@@ -83,3 +83,57 @@ def test_grouped_call_layout_checks():
                      ([a, torch.zeros(4, 8, dtype=torch.float64)], 2), ([a], 2), ([a[:, ::2]], 1)):
         with pytest.raises(kfb.KfbError):
             kfb._same_layout(bad, "t", cnt)
+
+
+def test_size_limits_rejected_up_front(lib):
+    # the CholeskyQR kernels take at most 2048 columns, the eigensolver at most
+    # 4096 modes: such states cannot be created, so no call can reach the device
+    assert lib.kfb_state_bytes(65536, 0, 2048, kfb.KFB_BF16_MIXED) > 0
+    assert lib.kfb_state_bytes(65536, 0, 2049, kfb.KFB_BF16_MIXED) == 0
+    assert lib.kfb_state_bytes(65536, 2048, 2048, kfb.KFB_FP64) > 0
+    assert lib.kfb_state_bytes(65536, 2049, 2048, kfb.KFB_FP64) == 0
+    h = ctypes.c_void_p()
+    rc = lib.kfb_state_create(ctypes.byref(h), 65536, 0, 4096, 0.95, kfb.KFB_FP64, ctypes.c_void_p(256),
+                              1 << 40, None)
+    assert rc == 1
+    # workspace queries on a null handle
+    assert lib.kfb_reorth_workspace_bytes(None) == 0
+    assert lib.kfb_reorthonormalize(None, None, 0, None) == 1
+    assert lib.kfb_update_workspace_bytes(None, 16) == 0
+
+
+def _fake_factor(torch, d, prec):
+    # the binding's checks read d, prec, the batch dtype and the state buffer's device
+    from types import SimpleNamespace
+    return SimpleNamespace(d=d, prec=prec, mdtype=kfb._mdtype_of(prec), buf=torch.zeros(4, dtype=torch.uint8))
+
+
+def test_binding_checks_every_tensor_against_its_state():
+    import torch
+    fa, fg = _fake_factor(torch, 8, kfb.KFB_FP32), _fake_factor(torch, 6, kfb.KFB_FP32)
+    kfb._batch_check(torch.zeros(3, 8), fa, "t")
+    for bad in (torch.zeros(3, 8, dtype=torch.float64),      # dtype of another form
+                torch.zeros(3, 7),                            # wrong width
+                torch.zeros(8, 3).t(),                        # columns not contiguous
+                torch.zeros(0, 8),                            # no columns
+                torch.zeros(3, 8, dtype=torch.bfloat16)):
+        with pytest.raises(kfb.KfbError):
+            kfb._batch_check(bad, fa, "t")
+    kfb._grad_check(torch.zeros(6, 8), fg, fa, "t")
+    for bad in (torch.zeros(8, 6), torch.zeros(6, 8, dtype=torch.float64), torch.zeros(5, 8),
+                torch.zeros(8, 6).t()):
+        with pytest.raises(kfb.KfbError):
+            kfb._grad_check(bad, fg, fa, "t")
+    # an FP64 pair wants double gradients
+    f64a, f64g = _fake_factor(torch, 8, kfb.KFB_FP64), _fake_factor(torch, 6, kfb.KFB_FP64)
+    kfb._grad_check(torch.zeros(6, 8, dtype=torch.float64), f64g, f64a, "t")
+    with pytest.raises(kfb.KfbError):
+        kfb._grad_check(torch.zeros(6, 8), f64g, f64a, "t")
+    # the two sides: distinct states of one form
+    with pytest.raises(kfb.KfbError):
+        kfb._pair_check(fa, fa, "t")
+    with pytest.raises(kfb.KfbError):
+        kfb._pair_check(f64g, fa, "t")
+    kfb._dense_check(torch.zeros(8, 8), fa, "t")
+    with pytest.raises(kfb.KfbError):
+        kfb._dense_check(torch.zeros(8, 8, dtype=torch.float64), fa, "t")

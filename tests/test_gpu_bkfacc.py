@@ -84,7 +84,7 @@ def test_fp64_bkfacc_trajectory(kfb):
     print(f"fp64 B-KFAC-C d={d} r={r} n={n} n_crc={int(phi * r)} T={Tc}", flush=True)
     f, w = _trajectory(kfb, kfb.KFB_FP64, d, r, n, phi, Tc, steps, cfg=91)
     assert w["corr"] <= TOL[0] and w["upd"] <= TOL[0] and w["orth"] <= TOL[0]
-    assert max(w["gain"]) <= 1.0 + 1e-12     # a correction never increases the error (Section 3.5)
+    assert max(w["gain"]) <= 1.0 + 1e-12     # a correction never increases the error (Section 3.4)
     assert f.status() == 0
 
 

@@ -77,6 +77,7 @@ def test_fp64_factored_equals_dense_definition(kfb, flags, nk):
     S_ref = oracle.precondition_dense(XG, XA, J, lgx, lax)
     Sg = S.cpu().numpy()
     assert oracle.e_S(Sg, S_ref) <= 1e-10
+    assert oracle.e_S_proj(Sg, S_ref, UG, UA) <= 1e-10
     assert np.max(np.abs(Sg - S_ref)) <= 1e-10 * np.max(np.abs(S_ref))
     assert oracle.e_S(Sg, S2.cpu().numpy()) <= 1e-10
 
@@ -104,8 +105,9 @@ def test_fp32_factored_realistic_width(kfb):
                                          DA.astype(np.float64), Gk.T.astype(np.float64), Ak.T.astype(np.float64),
                                          lam, lam)
     es = oracle.e_S(S.cpu().numpy(), S_ref)
-    print(f"  e_S {es:.3e}", flush=True)
-    assert es <= 1e-5
+    ep = oracle.e_S_proj(S.cpu().numpy(), S_ref, bg.U, ba.U)
+    print(f"  e_S {es:.3e} e_S_proj {ep:.3e}", flush=True)
+    assert es <= 1e-5 and ep <= 1e-5
 
 
 @pytest.mark.parametrize("flags", [0, 1])
@@ -134,8 +136,9 @@ def test_mixed_factored_headline_shape(kfb, flags):
     S_ref = oracle.precondition_factored(UG.astype(np.float64), DG, UA.astype(np.float64), DA, Gk.T, Ak.T,
                                          lgx, lax)
     es = oracle.e_S(S.cpu().numpy(), S_ref)
-    print(f"  e_S {es:.3e}", flush=True)
-    assert es <= 2e-2
+    ep = oracle.e_S_proj(S.cpu().numpy(), S_ref, bg.U, ba.U)
+    print(f"  e_S {es:.3e} e_S_proj {ep:.3e}", flush=True)
+    assert es <= 2e-2 and ep <= 2e-2
 
 
 def test_factored_batched_equals_single(kfb):

@@ -73,7 +73,9 @@ def test_fp64_layer_trajectory_vs_dense_definition(kfb):
             kfb.precondition(fg, fa, Gd, S, lam, lam)
             torch.cuda.synchronize()
             S_ref = oracle.precondition_dense(og.X, oa.X, G, lam, lam)
-            worst["S"] = max(worst["S"], oracle.e_S(S.cpu().numpy(), S_ref))
+            VG, VA = og.modes()[0], oa.modes()[0]
+            worst["S"] = max(worst["S"], oracle.e_S(S.cpu().numpy(), S_ref),
+                             oracle.e_S_proj(S.cpu().numpy(), S_ref, VG, VA))
     _announce(f"  worst: {worst}")
     assert worst["rec"] <= 1e-10 and worst["D"] <= 1e-10 and worst["S"] <= 1e-10
     assert worst["orth"] <= 1e-11
@@ -203,6 +205,7 @@ def test_fp64_precondition_on_loaded_state(kfb, flags):
     S_ref = oracle.precondition_dense(XG, XA, G, lgx, lax)
     Sg = S.cpu().numpy()
     assert oracle.e_S(Sg, S_ref) <= 1e-10
+    assert oracle.e_S_proj(Sg, S_ref, UG, UA) <= 1e-10
     assert np.max(np.abs(Sg - S_ref)) <= 1e-10 * np.max(np.abs(S_ref))
 
 
@@ -254,8 +257,9 @@ def test_fp32_realistic_width_with_bias(kfb):
     torch.cuda.synchronize()
     S_ref = oracle.precondition_lowrank(og.U, og.D, oa.U, oa.D, G.astype(np.float64), lam, lam)
     es = oracle.e_S(S.cpu().numpy(), S_ref)
-    _announce(f"  e_S {es:.3e}")
-    assert es <= TOL[1]
+    ep = oracle.e_S_proj(S.cpu().numpy(), S_ref, og.U, oa.U)
+    _announce(f"  e_S {es:.3e} e_S_proj {ep:.3e}")
+    assert es <= TOL[1] and ep <= TOL[1]
 
 
 # ----------------------------------------------------------------------------
@@ -372,8 +376,9 @@ def test_mixed_precondition_on_loaded_state(kfb, flags):
     S_ref = oracle.precondition_lowrank(UG32.astype(np.float64), DG, UA32.astype(np.float64), DA,
                                         G.astype(np.float64), lgx, lax)
     es = oracle.e_S(S.cpu().numpy(), S_ref)
-    _announce(f"  e_S {es:.3e}")
-    assert es <= TOL[2]
+    ep = oracle.e_S_proj(S.cpu().numpy(), S_ref, bg.U, ba.U)
+    _announce(f"  e_S {es:.3e} e_S_proj {ep:.3e}")
+    assert es <= TOL[2] and ep <= TOL[2]
 
 
 def test_mixed_wide_layer_spot(kfb):
@@ -465,8 +470,68 @@ def test_ortho_drift_is_reported(kfb, prec):
     b = _oracle_state(d, r, n, rho, 3, 13, "A")
     g = kfb.Factor(d, r, n, rho, prec)
     g.load_state(_to_dev(1.01 * b.U, udt), _to_dev(b.D, ddt), step=3)
+    assert g.status() & kfb.KFB_EV_ORTHO_DRIFT          # the load's own column-norm check
     g.update(_to_dev(_batch(13, 3, "A", n, d, prec=prec), mdt))
+    assert g.status() & kfb.KFB_EV_ORTHO_DRIFT          # carried into the updated basis
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_drift_recovery(kfb, prec):
+    # a drifted basis (columns off unit norm and slightly mixed) is re-orthonormalised
+    # without changing the matrix it stands for: against the oracle's Rayleigh-Ritz
+    # of the same representation, orthonormal to the form's precision, and the next
+    # update tracks Oracle-B started from the recovered state
+    import torch
+    d, r, n, rho = 320, 48, 32, 0.95
+    mdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[prec]
+    udt = torch.float64 if prec == 0 else torch.float32
+    ddt = torch.float32 if prec == 1 else torch.float64
+    orth_tol = {0: 1e-13, 1: 1e-5, 2: 1e-4}[prec]
+    _announce(f"drift recovery prec={prec}")
+    b = _oracle_state(d, r, n, rho, 3, 15, "A")
+    k = b.U.shape[1]
+    mix = np.eye(k) + 0.01 * np.random.default_rng(16).standard_normal((k, k))
+    Ud = (b.U @ mix).astype(np.float32 if prec else np.float64).astype(np.float64)
+    Dd = b.D.astype(np.float32).astype(np.float64) if prec == 1 else b.D
+    g = kfb.Factor(d, r, n, rho, prec)
+    g.load_state(_to_dev(Ud, udt), _to_dev(Dd, ddt), step=3)
     assert g.status() & kfb.KFB_EV_ORTHO_DRIFT
+    g.reorthonormalize()
+    U, D = _front_np(g)
+    Uo, Do = oracle.reorthonormalize(Ud, Dd)
+    e = oracle.e_rec_lowrank(U, D, Uo, Do)
+    _announce(f"  e_rec {e:.3e} e_D {oracle.e_D(D, Do):.3e} orth {oracle.e_orth(U):.3e}")
+    assert e <= TOL[prec] and oracle.e_D(D, Do) <= TOL[prec]
+    assert oracle.e_orth(U) <= orth_tol
+    assert g.status() == 0
+    assert g.info()["k_valid"] == k and g.info()["step"] == 3
+    o = oracle.BrandFactor(d, r, rho)
+    o.U, o.D, o.k = Uo, Do, 3
+    M = _batch(15, 3, "A", n, d, prec=prec)
+    g.update(_to_dev(M, mdt))
+    o.update(M.T)
+    U, D = _front_np(g)
+    assert oracle.e_rec_lowrank(U, D, o.U, o.D) <= TOL[prec]
+    assert g.status() == 0
+
+
+def test_state_load_rejects_bad_eigenvalues(kfb):
+    import torch
+    d, r, n = 128, 8, 8
+    f = kfb.Factor(d, r, n, 0.95, kfb.KFB_FP64)
+    f.update(_to_dev(_batch(17, 0, "A", n, d), torch.float64))
+    torch.cuda.synchronize()
+    U0, D0 = _front_np(f)
+    Q = np.linalg.qr(np.random.default_rng(3).standard_normal((d, 4)))[0]
+    for bad in ([1.0, 2.0, 0.5, 0.1], [2.0, 1.0, -0.5, -1.0], [2.0, np.nan, 1.0, 0.5], [np.inf, 1.0, 0.5, 0.1]):
+        with pytest.raises(kfb.KfbError):
+            f.load_state(_to_dev(Q, torch.float64), _to_dev(np.array(bad), torch.float64), step=9)
+    # the state is untouched by a rejected load
+    U1, D1 = _front_np(f)
+    assert f.info()["k_valid"] == n and f.info()["step"] == 1
+    assert np.array_equal(U0, U1) and np.array_equal(D0, D1)
+    f.load_state(_to_dev(Q, torch.float64), _to_dev(np.array([2.0, 1.0, 1.0, 0.0]), torch.float64), step=9)
+    assert f.info()["k_valid"] == 4 and f.status() == 0
 
 
 def test_batched_widths_argument_errors(kfb):
@@ -516,4 +581,4 @@ def test_batched_uneven_widths_equal_unpadded(kfb, prec):
     assert worst <= tol
     for f in padded:
         assert f.status() & kfb.KFB_EV_CHOL_DEFICIENT == 0
-        assert f.info()["k_valid"] == r + nmax
+        assert f.info()["k_valid"] == r + nmax     # the padded slots stay until the next truncation

@@ -527,3 +527,119 @@ def test_error_metrics():
     T = rng.standard_normal((5, 7))
     T -= np.sum(T * S) / np.sum(S * S) * S
     assert abs(e_angle(S, T) - 1.0) <= 1e-14
+
+
+# ----------------------------------------------------------------------------
+# The comparison metrics themselves: known non-zero answers, so that a wrong
+# formula (a norm difference instead of the norm of the difference, a missing
+# sort, an off-diagonal-only check) fails here rather than weakening every GPU
+# parity assertion that relies on it.
+# ----------------------------------------------------------------------------
+from oracle import e_S_proj, reorthonormalize  # noqa: E402
+
+
+def test_e_S_known_values():
+    rng = np.random.default_rng(70)
+    S = rng.standard_normal((6, 9))
+    E = rng.standard_normal((6, 9))
+    eps = 1e-3
+    # relative Frobenius norm of the difference, not a difference of norms
+    assert e_S(S + eps * E, S) == pytest.approx(eps * np.linalg.norm(E) / np.linalg.norm(S), rel=1e-12)
+    assert e_S(-S, S) == pytest.approx(2.0, rel=1e-15)
+    # a perturbation orthogonal to S keeps ||S1|| ~ ||S2|| to first order but not e_S
+    T = E - np.sum(E * S) / np.sum(S * S) * S
+    T *= 0.5 * np.linalg.norm(S) / np.linalg.norm(T)
+    assert e_S(S + T, S) == pytest.approx(0.5, rel=1e-12)
+    assert e_S(S, S) == 0.0
+
+
+def test_e_D_known_values():
+    # unsorted inputs are compared sorted descending; max gap over the largest
+    assert e_D([3.0, 1.0, 2.0], [2.5, 2.0, 1.0]) == pytest.approx(0.5 / 2.5, rel=1e-15)
+    assert e_D([1.0, 3.0, 2.0], [3.0, 2.0, 1.0]) == 0.0
+    # zero padding of the shorter vector: a missing mode counts fully
+    assert e_D([4.0, 1.0], [4.0, 1.0, 0.5]) == pytest.approx(0.5 / 4.0, rel=1e-15)
+    assert e_D([4.0, 2.0, 1.0], [4.0, 1.0]) == pytest.approx(1.0 / 4.0, rel=1e-15)
+
+
+def test_e_orth_known_values():
+    rng = np.random.default_rng(71)
+    Q, _ = np.linalg.qr(rng.standard_normal((20, 5)))
+    assert e_orth(Q) <= 1e-15
+    delta = 1e-3
+    U = Q.copy()
+    U[:, 2] *= 1.0 + delta                 # diagonal entry (1 + delta)^2 - 1
+    assert e_orth(U) == pytest.approx(2 * delta + delta ** 2, rel=1e-9)
+    # an off-diagonal defect: columns 0 and 1 at cos(angle) = s
+    s = 0.01
+    V = Q.copy()
+    V[:, 1] = s * Q[:, 0] + np.sqrt(1 - s * s) * Q[:, 1]
+    assert e_orth(V) == pytest.approx(s, rel=1e-9)
+    # the floor restricts the check to columns with a large enough eigenvalue
+    Dv = np.array([1.0, 1e-12, 0.5, 0.3, 0.2])
+    assert e_orth(V, Dv, rel_floor=1e-6) == pytest.approx(0.0, abs=1e-15)
+
+
+def test_e_S_proj_known_values():
+    rng = np.random.default_rng(72)
+    dG, dA, NG, NA = 30, 40, 6, 5
+    UG, _ = np.linalg.qr(rng.standard_normal((dG, NG)))
+    UA, _ = np.linalg.qr(rng.standard_normal((dA, NA)))
+    S = rng.standard_normal((dG, dA))
+    core = UG.T @ S @ UA
+    # an error inside span(UG) x span(UA): exactly its relative size there
+    E = rng.standard_normal((NG, NA))
+    S1 = S + 1e-2 * UG @ E @ UA.T
+    assert e_S_proj(S1, S, UG, UA) == pytest.approx(1e-2 * np.linalg.norm(E) / np.linalg.norm(core), rel=1e-10)
+    # an error in the complement: invisible to the projected metric, not to e_S
+    Cg = np.eye(dG) - UG @ UG.T
+    S2 = S + 0.3 * Cg @ rng.standard_normal((dG, dA))
+    assert e_S_proj(S2, S, UG, UA) <= 1e-14
+    assert e_S(S2, S) > 0.05
+    # the case it exists for: eigenvalues of both factors scaled by 1.1 at a small
+    # lambda change S by little in Frobenius norm but a lot inside the modes' span
+    DG = np.sort(rng.uniform(0.5, 2.0, NG))[::-1]
+    DA = np.sort(rng.uniform(0.5, 2.0, NA))[::-1]
+    lam = 0.01
+    ref = precondition_lowrank(UG, DG, UA, DA, S, lam, lam)
+    bad = precondition_lowrank(UG, 1.1 * DG, UA, 1.1 * DA, S, lam, lam)
+    assert e_S(bad, ref) < 0.02 < 0.1 < e_S_proj(bad, ref, UG, UA)
+
+
+def test_continuation_skips_empty_slots():
+    # a mode of eigenvalue 0 with a zero column is an empty slot: the shift is the
+    # smallest positive eigenvalue and the operator is that of the slot-free state
+    d, N, lam = 25, 5, 0.1
+    U, D = _lowrank(d, N, 73)
+    Uz = np.concatenate([U, np.zeros((d, 2))], axis=1)
+    Dz = np.concatenate([D, [0.0, 0.0]])
+    D2, lam2 = spectrum_continuation(D, lam)
+    Dz2, lamz2 = spectrum_continuation(Dz, lam)
+    assert lamz2 == lam2 == pytest.approx(lam + D.min())
+    assert np.array_equal(Dz2[:N], D2) and np.all(Dz2[N:] == 0.0)
+    Y = np.random.default_rng(74).standard_normal((d, 3))
+    assert np.allclose(lowrank_inverse_apply(Uz, Dz2, lamz2, Y), lowrank_inverse_apply(U, D2, lam2, Y),
+                       atol=1e-14)
+    # no positive eigenvalue at all: no shift
+    assert spectrum_continuation(np.zeros(3), lam)[1] == lam
+
+
+def test_reorthonormalize_keeps_the_matrix():
+    rng = np.random.default_rng(75)
+    d, k = 40, 8
+    Q, _ = np.linalg.qr(rng.standard_normal((d, k)))
+    D = np.sort(rng.uniform(0.1, 3.0, k))[::-1]
+    # a drifted basis: columns scaled off unit norm and slightly mixed
+    U = Q @ (np.eye(k) + 0.02 * rng.standard_normal((k, k)))
+    X = (U * D) @ U.T
+    U2, D2 = reorthonormalize(U, D)
+    assert e_orth(U2) <= 1e-14
+    assert e_rec_dense(U2, D2, X) <= 1e-13
+    assert np.all(np.diff(D2) <= 0)
+    # the eigenvalues are those of the represented matrix (library eigensolver)
+    ev = np.sort(np.linalg.eigvalsh(X))[::-1][:k]
+    assert np.allclose(D2, ev, rtol=1e-12, atol=1e-13 * ev[0])
+    # an orthonormal basis is left as it is (up to signs / order)
+    U3, D3 = reorthonormalize(Q, D)
+    assert np.allclose(D3, D, rtol=1e-13)
+    assert np.allclose(U3 @ U3.T, Q @ Q.T, atol=1e-13)
