@@ -220,8 +220,9 @@ def serve_mixed_leg(torch, kfb, dev, args):
     ranks: widths w_0..w_24 drawn from {512, ..., 8192} (layer l: d_in = w_l,
     d_out = w_{l+1}), r per factor drawn from {64, ..., 512} and clamped to d - 256,
     n per update request drawn from {64, 128, 256}; 70% updates (uniform over layer
-    and factor), 30% preconditionings (uniform layer), BF16-mixed.  Updates of one
-    factor shape but uneven batch widths are grouped by zero-padding to n_max."""
+    and factor), 30% preconditionings (uniform layer), BF16-mixed.  Updates of every
+    factor that keeps the same number of modes share a group whatever its width and
+    batch width (kfb_brand_update_grouped pads them on the device)."""
     import numpy as np
     from paper_2210_08494_amd import serve
     L = args.layers
@@ -233,12 +234,21 @@ def serve_mixed_leg(torch, kfb, dev, args):
               for l in range(L)]
     srv = serve.Server(layers, n_max=nmax, rho=RHO, prec=kfb.KFB_BF16_MIXED, streams=4,
                        byte_budget=24 << 30, max_group=48, pad_updates=True)
-    pool = {}
+    # per factor a ring of distinct 256-sample batches; a request of width n takes
+    # the first n samples of the next one
+    ring = 16
+    pool, nxt = {}, {}
     for l, (d_in, d_out, _, _) in enumerate(layers):
         for s_i, (side, d) in enumerate((("A", d_in), ("G", d_out))):
-            for n in (64, 128, 256):
-                pool[(l, side, n)] = _gen_batches(torch, dev, 2, n, d, seed=7000 + 6 * l + 3 * s_i + n // 128,
-                                                  dtype=torch.bfloat16)[s_i]
+            pool[(l, side)] = [b for j, b in enumerate(_gen_batches(torch, dev, 2 * ring, nmax, d,
+                                                                    seed=7000 + 2 * l + s_i,
+                                                                    dtype=torch.bfloat16)) if j % 2 == s_i]
+            nxt[(l, side)] = 0
+
+    def take(l, side, n):
+        i = nxt[(l, side)]
+        nxt[(l, side)] = i + 1
+        return pool[(l, side)][i % ring][:n]
     gen = torch.Generator(device=dev)
     gen.manual_seed(12)
     grads = [torch.randn(d_out, d_in, generator=gen, device=dev) for (d_in, d_out, _, _) in layers]
@@ -247,7 +257,7 @@ def serve_mixed_leg(torch, kfb, dev, args):
     for j in range(2):  # every state to r + n modes
         for l in range(L):
             for side in ("A", "G"):
-                srv.submit(serve.UpdateRequest(l, side, pool[(l, side, 256)]))
+                srv.submit(serve.UpdateRequest(l, side, take(l, side, nmax)))
     srv.drain()
     torch.cuda.synchronize()
 
@@ -256,7 +266,7 @@ def serve_mixed_leg(torch, kfb, dev, args):
         if rng.random() < 0.7:
             side = "A" if rng.random() < 0.5 else "G"
             n = int(rng.choice([64, 128, 256]))
-            return serve.UpdateRequest(l, side, pool[(l, side, n)])
+            return serve.UpdateRequest(l, side, take(l, side, n))
         return serve.PrecondRequest(l, grads[l], outs[l], LAM, LAM)
 
     res = {"widths": widths, "ranks": [(a, g) for (_, _, a, g) in layers]}

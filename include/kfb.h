@@ -140,6 +140,29 @@ int kfb_brand_update_batched_widths(int32_t count, kfb_state_t const* states, co
                                     int64_t ldm, int32_t n, const int32_t* widths, void* workspace,
                                     size_t ws_bytes, kfb_stream_t stream);
 
+/* Grouped update across factor shapes (one launch sequence for the updates
+ * of many factors, Algorithm 4 per factor: the factors are independent).  The
+ * states share the precision form and the number of kept modes
+ * r_eff = min(k_valid, r) but may differ in width d_i, rank r, capacity n_max
+ * and batch width: batch i is d_i x widths[i], column-major with leading
+ * dimension ldms[i] >= d_i (HOST arrays of count values).  Every problem runs
+ * at the group's shape, d = max d_i (rounded up to 64) and n = max widths[i]
+ * (which must not exceed any state's n_max): the state's U and its batch are
+ * copied into zero-padded workspace buffers, the update runs on them (the
+ * zero rows stay zero through every stage) and the first d_i rows of the new
+ * basis go to the state's back buffer.  Each problem takes the weight of its
+ * own width, as kfb_brand_update_batched_widths; afterwards every state holds
+ * r_eff + n modes, those beyond its own r_eff + widths[i] being empty slots
+ * (eigenvalue 0, zero column).  Results equal separate calls within rounding
+ * (the padded shape changes the blocking of the products).
+ * Errors: KFB_ESTATE (forms or r_eff differ, a state twice), KFB_EINVAL (a
+ * width outside 1..n_max of its state, n above some state's n_max, ldms[i] <
+ * d_i, null pointers), KFB_EWORKSPACE. */
+size_t kfb_update_grouped_workspace_bytes(int32_t count, kfb_state_t const* states, const int32_t* widths);
+int kfb_brand_update_grouped(int32_t count, kfb_state_t const* states, const void* const* Ms,
+                             const int64_t* ldms, const int32_t* widths, void* workspace, size_t ws_bytes,
+                             kfb_stream_t stream);
+
 /* Workspace bytes for kfb_precondition on this pair of states. */
 size_t kfb_precondition_workspace_bytes(kfb_state_t st_gamma, kfb_state_t st_a);
 

@@ -309,8 +309,18 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
     q.m = (int)d; q.n = n; q.k = n;
     q.b_upper = 1;  // R^-1 is upper triangular
     q.c_vec = 1;    // Q in the workspace
-    if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {
-      KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));  // Q = Z R^-1 on FP32 MFMA
+    if constexpr (sizeof(TZ) == 4 && sizeof(TA) == 4) {  // Q = Z R^-1 on FP32 MFMA
+      if constexpr (sizeof(TG) == 8) {
+        // R^-1 rounded to FP32 once (the FP32 product would round its operand on
+        // every tile load): half the operand bytes.  The copy goes to oRt, which
+        // no pass reads or writes (the product of the passes' factors lands
+        // there only after the last pass), so it aliases nothing in flight.
+        KFB_TRY((copy2d<float, TG>(drecs, nrec, op(WS, p.oRt, 1, n), op(WS, oX[pass & 1], 1, n), n, n, s)));
+        q.B = op(WS, p.oRt, 1, n);
+        KFB_TRY((gemm_f32_mfma<float, TZ>(drecs, nrec, q, s)));
+      } else {
+        KFB_TRY((gemm_f32_mfma<TG, TZ>(drecs, nrec, q, s)));
+      }
     } else {
       KFB_TRY((gemm<TZ, TG, TZ, TZ, TA>(drecs, nrec, q, s)));
     }
@@ -336,7 +346,8 @@ int thin_qr(const Rec* drecs, int nrec, const UpdPlan& p, int64_t srcZ, int64_t 
 // launches of one thin_qr (for the stage counters)
 inline int thin_qr_launches(int prec, int ksG) {
   const int passes = prec == KFB_FP32 ? 3 : 2, kl = ksG > 1 ? 2 : 1;
-  return passes * (kl + 2) + passes - 1;
+  const int copies = prec == KFB_BF16_MIXED ? passes : 0;  // FP32 copy of R^-1 per pass
+  return passes * (kl + 2) + passes - 1 + copies;
 }
 
 // Jacobi eigensolve of the assembled core (B, V in the plan's workspace) and
@@ -975,6 +986,109 @@ int dispatch_update(int count, kfb_state_t const* sts, const void* const* Ms, in
   return KFB_OK;
 }
 
+// Cross-shape grouped update: states of one precision form and one kept rank
+// r_eff but different widths d_i, batches of different widths n_i.  Every
+// problem runs at the group's shape (dp = max d_i rounded up to 64, n = max
+// n_i): its U and batch are copied into zero-padded workspace buffers, the
+// update runs on them (zero rows stay zero through every stage: projection,
+// residual, CholeskyQR Gram, rotation), and the first d_i rows of the new basis
+// are copied into the state's back buffer.  The zero columns of a narrower
+// batch are the padding of kfb_brand_update_batched_widths.
+template <int PR>
+int run_update_cross(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
+  typedef Ty<PR> T;
+  {
+    StageTimer st("pad", s, 1);
+    KFB_TRY((pad_in<typename T::U, typename T::M>(drecs, nrec, p.d, p.r, p.n, s)));
+  }
+  const int rc = run_update<PR>(drecs, nrec, p, s);
+  if (rc != KFB_OK) return rc;
+  StageTimer st("pad", s, 1);
+  KFB_TRY((crop_out<typename T::U>(drecs, nrec, p.d, p.N, s)));
+  return KFB_OK;
+}
+
+int dispatch_update_cross(int count, kfb_state_t const* sts, const void* const* Ms, const int64_t* ldms,
+                          const int32_t* widths, void* workspace, size_t ws_bytes, hipStream_t s,
+                          size_t* need_only) {
+  if (count <= 0 || !sts || !widths || !sts[0]) return KFB_EINVAL;
+  const int prec = sts[0]->prec;
+  const int r_eff = upd_r_eff(sts[0]);
+  int64_t dmax = 0;
+  int n = 0, nmax_min = 1 << 30;
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t st = sts[i];
+    if (!st) return KFB_EINVAL;
+    if (st->prec != prec || upd_r_eff(st) != r_eff) return KFB_ESTATE;
+    for (int j = 0; j < i; ++j)
+      if (sts[j] == st) return KFB_ESTATE;
+    if (widths[i] < 1 || widths[i] > st->n_max) return KFB_EINVAL;
+    if (st->d > dmax) dmax = st->d;
+    if (widths[i] > n) n = widths[i];
+    if (st->n_max < nmax_min) nmax_min = st->n_max;
+  }
+  // every state holds r_eff + n modes afterwards: n must fit each state's capacity
+  if (n > nmax_min) return KFB_EINVAL;
+  const int64_t dp = ((dmax + 63) / 64) * 64;
+  UpdPlan p;
+  bool ok = false;
+  if (prec == KFB_FP64) ok = make_upd_plan<KFB_FP64>(dp, dp, dp, r_eff, n, count, &p);
+  else if (prec == KFB_FP32) ok = make_upd_plan<KFB_FP32>(dp, dp, dp, r_eff, n, count, &p);
+  else ok = make_upd_plan<KFB_BF16_MIXED>(dp, dp, dp, r_eff, n, count, &p);
+  if (!ok) return KFB_EINVAL;
+  // the padded copies after the update's own workspace
+  const int64_t oUin = (int64_t)p.per_problem;
+  const int64_t oMin = oUin + (int64_t)align256((size_t)dp * (r_eff > 0 ? r_eff : 1) * u_elem(prec));
+  const int64_t oUout = oMin + (int64_t)align256((size_t)dp * n * m_elem(prec));
+  const size_t per = (size_t)oUout + align256((size_t)dp * p.N * u_elem(prec));
+  const size_t head = align256(sizeof(Rec) * (size_t)count);
+  const size_t need = head + per * (size_t)count;
+  if (need_only) { *need_only = need; return KFB_OK; }
+  if (!Ms || !ldms || !workspace) return KFB_EINVAL;
+  if (ws_bytes < need) return KFB_EWORKSPACE;
+  if (((uintptr_t)workspace) & 255) return KFB_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!Ms[i] || ldms[i] < sts[i]->d) return KFB_EINVAL;
+  std::vector<Rec> host((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t st = sts[i];
+    Rec* rc = &host[(size_t)i];
+    memset(rc, 0, sizeof(Rec));
+    char* ws = (char*)workspace + head + per * (size_t)i;
+    rc->p[WS] = ws;
+    rc->p[U_FRONT] = ws + oUin;
+    rc->p[M_IN] = ws + oMin;
+    rc->p[U_BACK] = ws + oUout;
+    rc->p[D_FRONT] = st->buf + st->off_D[st->front];
+    rc->p[D_BACK] = st->buf + st->off_D[1 - st->front];
+    rc->p[STATUS] = st->buf + st->off_status;
+    rc->p[X_UF] = st->buf + st->off_U[st->front];
+    rc->p[X_M] = const_cast<void*>(Ms[i]);
+    rc->p[X_UB] = st->buf + st->off_U[1 - st->front];
+    const int nw = widths[i];
+    rc->s[0] = st->k_valid > 0 ? st->rho : 0.0;
+    rc->s[1] = st->k_valid > 0 ? (1.0 - st->rho) / nw : 1.0 / nw;
+    rc->s[2] = (double)nw;
+    rc->z[0] = st->d;
+    rc->z[1] = st->ldu;
+    rc->z[2] = ldms[i];
+  }
+  Rec* dev = (Rec*)workspace;
+  if (upload_recs(host.data(), count, dev, s) != hipSuccess) return KFB_EHIP;
+  int rc;
+  if (prec == KFB_FP64) rc = run_update_cross<KFB_FP64>(dev, count, p, s);
+  else if (prec == KFB_FP32) rc = run_update_cross<KFB_FP32>(dev, count, p, s);
+  else rc = run_update_cross<KFB_BF16_MIXED>(dev, count, p, s);
+  if (rc != KFB_OK) return rc;
+  for (int i = 0; i < count; ++i) {
+    kfb_state_t st = sts[i];
+    st->front = 1 - st->front;
+    st->k_valid = r_eff + n;   // <= r + n_max <= d; the padded modes are empty slots
+    st->step += 1;
+  }
+  return KFB_OK;
+}
+
 int pre_modes(kfb_state_t st, uint32_t flags) {
   int k = st->k_valid;
   if ((flags & KFB_TRUNCATE_AFTER) && k > st->r) k = st->r;
@@ -1422,6 +1536,17 @@ size_t kfb_correct_workspace_bytes(kfb_state_t st, int32_t n_crc) {
 int kfb_light_correction(kfb_state_t st, const void* X, int64_t ldx, const int32_t* col_idx, int32_t n_crc,
                          void* workspace, size_t ws_bytes, kfb_stream_t stream) {
   return dispatch_correct(st, X, ldx, col_idx, n_crc, workspace, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+size_t kfb_update_grouped_workspace_bytes(int32_t count, kfb_state_t const* states, const int32_t* widths) {
+  size_t need = 0;
+  if (dispatch_update_cross(count, states, nullptr, nullptr, widths, nullptr, 0, nullptr, &need) != KFB_OK) return 0;
+  return need;
+}
+
+int kfb_brand_update_grouped(int32_t count, kfb_state_t const* states, const void* const* Ms, const int64_t* ldms,
+                             const int32_t* widths, void* workspace, size_t ws_bytes, kfb_stream_t stream) {
+  return dispatch_update_cross(count, states, Ms, ldms, widths, workspace, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int kfb_brand_update_batched_widths(int32_t count, kfb_state_t const* states, const void* const* Ms,

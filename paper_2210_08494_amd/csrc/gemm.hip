@@ -234,6 +234,60 @@ hipError_t copy2d(const Rec* recs, int nrec, OpRef dst, OpRef src, int m, int n,
   return hipGetLastError();
 }
 
+template <typename TU, typename TM>
+__global__ __launch_bounds__(256) void pad_in_kernel(const Rec* __restrict__ recs, int64_t dp, int r, int n) {
+  const Rec& rec = recs[blockIdx.y];
+  const int64_t d = rec.z[0], ldu = rec.z[1], ldm = rec.z[2];
+  const int nreal = rec.s[2] > 0.0 ? (int)rec.s[2] : n;
+  const TU* Us = at<const TU>(rec, X_UF, 0);
+  const TM* Ms = at<const TM>(rec, X_M, 0);
+  TU* Ud = at<TU>(rec, U_FRONT, 0);
+  TM* Md = at<TM>(rec, M_IN, 0);
+  const int64_t nu = dp * r, tot = nu + dp * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nu) {
+      const int64_t i = e % dp, j = e / dp;
+      Ud[e] = i < d ? Us[i + j * ldu] : TU(0);
+    } else {
+      const int64_t f = e - nu, i = f % dp, j = f / dp;
+      Md[f] = (i < d && j < nreal) ? Ms[i + j * ldm] : TM(0.0f);
+    }
+  }
+}
+
+template <typename TU, typename TM>
+hipError_t pad_in(const Rec* recs, int nrec, int64_t dp, int r, int n, hipStream_t s) {
+  const int64_t tot = dp * (r + n);
+  if (tot <= 0 || nrec <= 0) return hipSuccess;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL((pad_in_kernel<TU, TM>), dim3(blocks, nrec), dim3(256), 0, s, recs, dp, r, n);
+  return hipGetLastError();
+}
+
+template <typename TU>
+__global__ __launch_bounds__(256) void crop_out_kernel(const Rec* __restrict__ recs, int64_t dp, int N) {
+  const Rec& rec = recs[blockIdx.y];
+  const int64_t d = rec.z[0], ldu = rec.z[1];
+  const TU* Us = at<const TU>(rec, U_BACK, 0);
+  TU* Ud = at<TU>(rec, X_UB, 0);
+  const int64_t tot = d * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % d, j = e / d;
+    Ud[i + j * ldu] = Us[i + j * dp];
+  }
+}
+
+template <typename TU>
+hipError_t crop_out(const Rec* recs, int nrec, int64_t dp, int N, hipStream_t s) {
+  const int64_t tot = dp * N;
+  if (tot <= 0 || nrec <= 0) return hipSuccess;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL((crop_out_kernel<TU>), dim3(blocks, nrec), dim3(256), 0, s, recs, dp, N);
+  return hipGetLastError();
+}
+
 __global__ void zero_words_kernel(const Rec* __restrict__ recs, int slot, int64_t off, int nwords) {
   int32_t* p = at<int32_t>(recs[blockIdx.y], slot, off);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x) p[i] = 0;
@@ -250,6 +304,12 @@ hipError_t zero_words(const Rec* recs, int nrec, int slot, int64_t off, int nwor
 // ---------------------------------------------------------------------------
 // explicit instantiations used by the host orchestration
 // ---------------------------------------------------------------------------
+template hipError_t pad_in<double, double>(const Rec*, int, int64_t, int, int, hipStream_t);
+template hipError_t pad_in<float, float>(const Rec*, int, int64_t, int, int, hipStream_t);
+template hipError_t pad_in<float, bf16>(const Rec*, int, int64_t, int, int, hipStream_t);
+template hipError_t crop_out<double>(const Rec*, int, int64_t, int, hipStream_t);
+template hipError_t crop_out<float>(const Rec*, int, int64_t, int, hipStream_t);
+
 #define KFB_GEMM(TA, TB, TC, TC0, TACC) \
   template hipError_t gemm<TA, TB, TC, TC0, TACC>(const Rec*, int, const GemmArgs&, hipStream_t);
 KFB_GEMM(double, double, double, double, double)

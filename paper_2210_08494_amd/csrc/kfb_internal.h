@@ -21,6 +21,7 @@ constexpr int REC_SLOTS = 10;
 struct Rec {
   void* p[REC_SLOTS];
   double s[4];
+  int64_t z[4];  // per-problem sizes of the cross-shape grouped update (width d, ld of U, ld of M)
 };
 
 // Slots used by the Brand update.
@@ -32,6 +33,10 @@ enum PreSlot { PU_G = 0, PD_G = 1, PU_A = 2, PD_A = 3, P_G = 4, P_S = 5, PWS = 6
 // Slots of the B-R-KFAC calls (with the update's slots): the dense EA factor
 // and the Gaussian sketch of the randomized SVD.
 enum DenseSlot { B_X = 7, B_OMEGA = 8 };
+// Slots of the cross-shape grouped update (with the update's slots, which then
+// point at zero-padded copies in the workspace): the state's own front U, the
+// caller's batch, the state's own back U.
+enum CrossSlot { X_UF = 7, X_M = 8, X_UB = 9 };
 
 // A matrix operand resolved per record: element (i, j) of the logical matrix
 // lives at base + i*rs + j*cs, with base = rec.p[slot] + off (bytes).  When

@@ -35,6 +35,15 @@ hipError_t upload_recs(const Rec* host, int nrec, Rec* dev, hipStream_t s);
 template <typename TD, typename TS>
 hipError_t copy2d(const Rec* recs, int nrec, OpRef dst, OpRef src, int m, int n, hipStream_t s);
 
+// Cross-shape grouped update.  pad_in: U_FRONT (dp x r, ld dp) <- the state's
+// front U (X_UF: z[0] x r, ld z[1]) and M_IN (dp x n, ld dp) <- the batch (X_M:
+// z[0] x s[2] columns, ld z[2]), zero elsewhere.  crop_out: the state's back U
+// (X_UB, ld z[1]) <- rows 0..z[0]-1 of U_BACK (dp x N, ld dp).
+template <typename TU, typename TM>
+hipError_t pad_in(const Rec* recs, int nrec, int64_t dp, int r, int n, hipStream_t s);
+template <typename TU>
+hipError_t crop_out(const Rec* recs, int nrec, int64_t dp, int N, hipStream_t s);
+
 // fill int32 counters with zero (graph-safe, no memset nodes)
 hipError_t zero_words(const Rec* recs, int nrec, int slot, int64_t off, int nwords, hipStream_t s);
 

@@ -35,6 +35,9 @@ _SIGS = {
                                                 _vp, _sz, _vp]),
     "kfb_brand_update_batched_widths": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64, _i32,
                                                        ctypes.POINTER(_i32), _vp, _sz, _vp]),
+    "kfb_update_grouped_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_i32)]),
+    "kfb_brand_update_grouped": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                ctypes.POINTER(_i64), ctypes.POINTER(_i32), _vp, _sz, _vp]),
     "kfb_precondition_workspace_bytes": (_sz, [_vp, _vp]),
     "kfb_precondition": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _dbl, _dbl, _u32, _vp, _sz, _vp]),
     "kfb_precondition_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
@@ -329,6 +332,27 @@ def update_batched_widths(factors, Ms, widths, ws: Workspace):
     w = ws.get(need)
     _check(lib.kfb_brand_update_batched_widths(cnt, hs, ms, int(Ms[0].stride(0)), n, ws_, _ptr(w), int(w.numel()),
                                                _stream()), "kfb_brand_update_batched_widths")
+
+
+def update_grouped(factors, Ms, ws: Workspace):
+    """One grouped launch sequence over factors of different widths (same precision form and
+    kept rank); Ms[i]: (n_i, d_i) batch of factors[i] in its dtype, rows contiguous."""
+    lib = load()
+    cnt = len(factors)
+    if len(Ms) != cnt or cnt < 1:
+        raise KfbError(f"update_grouped: {len(Ms)} batches for {cnt} problems")
+    for f, M in zip(factors, Ms):
+        _batch_check(M, f, "update_grouped")
+    hs = (_vp * cnt)(*[f.handle.value for f in factors])
+    ms = (_vp * cnt)(*[m.data_ptr() for m in Ms])
+    lds = (_i64 * cnt)(*[int(m.stride(0)) for m in Ms])
+    wd = (_i32 * cnt)(*[int(m.shape[0]) for m in Ms])
+    need = lib.kfb_update_grouped_workspace_bytes(cnt, hs, wd)
+    if need == 0:
+        raise KfbError("kfb_update_grouped_workspace_bytes rejected the group")
+    w = ws.get(need)
+    _check(lib.kfb_brand_update_grouped(cnt, hs, ms, lds, wd, _ptr(w), int(w.numel()), _stream()),
+           "kfb_brand_update_grouped")
 
 
 def precondition_batched(fgs, fas, Gs, Ss, lam_g, lam_a, flags, ws: Workspace):

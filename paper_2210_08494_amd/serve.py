@@ -20,15 +20,17 @@ Scheduling (host side; all arithmetic runs in the HIP library):
   are taken, arriving requests wait and are fused into larger groups when a
   slot frees (this is what lets throughput approach the grouped closed loop
   under load instead of flooding the device with groups of one);
-* with ``pad_updates``, updates of one factor shape (d, r) but uneven batch
-  widths share a bucket: each batch is padded with zero columns to the widest
-  batch of its group and the group runs as ``kfb_brand_update_batched_widths``
-  (each problem weighted by its own width, so the result is the exact update
-  by its real columns; the padded modes carry eigenvalue 0, so spectrum
-  continuation sees a minimum eigenvalue of 0 until the next truncation drops
-  them).  This trades extra work per update for larger groups when widths
-  vary; results are then no longer bit-identical to a request run alone, only
-  equal within rounding;
+* with ``pad_updates``, updates of every factor that keeps the same number of
+  modes r_eff = min(k_valid, r) share a bucket, whatever its width d and the
+  batch width: the group runs as ``kfb_brand_update_grouped``, which pads each
+  problem on the device to the group's widest factor and batch (zero rows and
+  columns; each problem weighted by its own batch width, so the result is the
+  exact update by its real columns, and the padded modes are empty slots that
+  add nothing to the inverse and that spectrum continuation skips).  This
+  trades extra work per update for much larger groups when the layers'
+  shapes vary: the core eigensolve, whose cost does not depend on d, then
+  runs for many problems per launch.  Results are no longer bit-identical to
+  a request run alone, only equal within rounding;
 * groups go round-robin onto several default-priority HIP streams, each first
   waiting on the completion events of the last operations on its states, so
   work on different states overlaps on the device while per-state order holds;
@@ -222,7 +224,7 @@ class Server:
             info = f.info()
             r_eff = min(info["k_valid"], f.r)
             if self.pad_updates:
-                return ("U", f.d, f.r, r_eff, self.n_max, f.d)
+                return ("U", r_eff)
             return ("U", f.d, f.r, r_eff, int(r.M.shape[0]), int(r.M.stride(0)))
         fg, fa = self.fg[r.layer], self.fa[r.layer]
         kg, ka = fg.info()["k_valid"], fa.info()["k_valid"]
@@ -232,11 +234,10 @@ class Server:
         lib = self._lib
         if key[0] == "U":
             hs = (ctypes.c_void_p * len(reqs))(*[self.factor(r.layer, r.side).handle.value for r in reqs])
-            nbytes = int(lib.kfb_update_batched_workspace_bytes(len(reqs), hs, key[4]))
-            if self.pad_updates:  # zero-padded copies of the batches (bounded by n_max columns)
-                nbytes += sum(key[4] * int(r.M.shape[1]) * r.M.element_size() for r in reqs
-                              if r.M.shape[0] != key[4] or r.M.stride(0) != r.M.shape[1])
-            return nbytes
+            if self.pad_updates:   # the padded copies live in the call's workspace
+                wd = (ctypes.c_int32 * len(reqs))(*[int(r.M.shape[0]) for r in reqs])
+                return int(lib.kfb_update_grouped_workspace_bytes(len(reqs), hs, wd))
+            return int(lib.kfb_update_batched_workspace_bytes(len(reqs), hs, key[4]))
         hg = (ctypes.c_void_p * len(reqs))(*[self.fg[r.layer].handle.value for r in reqs])
         ha = (ctypes.c_void_p * len(reqs))(*[self.fa[r.layer].handle.value for r in reqs])
         return int(lib.kfb_precondition_batched_workspace_bytes(len(reqs), hg, ha))
@@ -303,16 +304,7 @@ class Server:
             if key[0] == "U":
                 factors = [self.factor(r.layer, r.side) for r in reqs]
                 if self.pad_updates:
-                    n = max(int(r.M.shape[0]) for r in reqs)   # pad to the widest batch of the group
-                    keep = []
-                    for r in reqs:
-                        if r.M.shape[0] == n and r.M.stride(0) == r.M.shape[1]:
-                            keep.append(r.M)
-                        else:
-                            Mp = torch.zeros((n, r.M.shape[1]), dtype=r.M.dtype, device=self.device)
-                            Mp[:r.M.shape[0]].copy_(r.M)
-                            keep.append(Mp)
-                    kfb.update_batched_widths(factors, keep, [int(r.M.shape[0]) for r in reqs], ws)
+                    kfb.update_grouped(factors, [r.M for r in reqs], ws)
                 else:
                     kfb.update_batched(factors, [r.M for r in reqs], ws)
                 self.stats.updates += len(reqs)

@@ -582,3 +582,52 @@ def test_batched_uneven_widths_equal_unpadded(kfb, prec):
     for f in padded:
         assert f.status() & kfb.KFB_EV_CHOL_DEFICIENT == 0
         assert f.info()["k_valid"] == r + nmax     # the padded slots stay until the next truncation
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_cross_shape_grouped_update(kfb, prec):
+    # factors of widths 512 / 1536 / 2048 / 1000 and ranks 128 / 128 / 200 / 96 in one
+    # grouped call per step (batches of widths 128, 64, 100, 32), against the same
+    # updates run one by one and against Oracle-B; the group's kept rank agrees at
+    # every step (r_eff = min(k_valid, r)), the widths and batch widths do not
+    import torch
+    rho = 0.95
+    shapes = [(512, 128, 128), (1536, 128, 128), (2048, 128, 128), (1000, 96, 128)]   # (d, r, n_max)
+    widths = [128, 64, 100, 32]
+    mdt = torch.float64 if prec == 0 else torch.bfloat16
+    _announce(f"cross-shape grouped update prec={prec}")
+    grouped = [kfb.Factor(d, r, nm, rho, prec) for d, r, nm in shapes]
+    alone = [kfb.Factor(d, r, nm, rho, prec) for d, r, nm in shapes]
+    orc = [oracle.BrandFactor(d, r, rho) for d, r, nm in shapes]
+    ws = kfb.Workspace()
+    worst = dict(alone=0.0, oracle=0.0)
+    for k in range(4):
+        # one grouped call per kept rank r_eff = min(k_valid, r): the three rank-128
+        # factors of different widths share it from the second step on
+        Ms, Md = [], []
+        for i, (d, r, nm) in enumerate(shapes):
+            M = _batch(19, 10 * k + i, "A" if i % 2 else "G", widths[i], d, prec=prec)
+            Ms.append(M)
+            Md.append(_to_dev(M, mdt))
+        buckets = {}
+        for i, f in enumerate(grouped):
+            buckets.setdefault(min(f.info()["k_valid"], f.r), []).append(i)
+        if k > 0:
+            assert sorted(len(v) for v in buckets.values()) == [1, 3]
+        for idx in buckets.values():
+            kfb.update_grouped([grouped[i] for i in idx], [Md[i] for i in idx], ws)
+        for f, o, M, Mh in zip(alone, orc, Md, Ms):
+            f.update(M)
+            o.update(Mh.T)
+        for g, a, o in zip(grouped, alone, orc):
+            Ug, Dg = _front_np(g)
+            Ua, Da = _front_np(a)
+            worst["alone"] = max(worst["alone"], oracle.e_rec_lowrank(Ug, Dg, Ua, Da))
+            worst["oracle"] = max(worst["oracle"], oracle.e_rec_lowrank(Ug, Dg, o.U, o.D))
+            keep = Dg > 0
+            assert oracle.e_orth(Ug[:, keep]) <= TOL[prec]
+    _announce(f"  {worst}")
+    assert worst["oracle"] <= TOL[prec]
+    assert worst["alone"] <= (1e-10 if prec == 0 else 1e-4)
+    for g in grouped:
+        assert g.status() & (kfb.KFB_EV_CHOL_DEFICIENT | kfb.KFB_EV_NONFINITE | kfb.KFB_EV_ORTHO_DRIFT) == 0

@@ -285,6 +285,7 @@ def test_inputs_produced_on_the_submitters_stream(kfb):
     twin = kfb.Factor(512, 64, n, 0.95, kfb.KFB_BF16_MIXED, device=dev)
     for j in range(2):
         srv.submit(serve.UpdateRequest(0, "A", ins[(0, "A")][j]))
+        srv.submit(serve.UpdateRequest(0, "G", ins[(0, "G")][j]))
         twin.update(ins[(0, "A")][j])
     srv.drain()
     torch.cuda.synchronize()
