@@ -114,6 +114,21 @@ size_t kfb_update_workspace_bytes(kfb_state_t st, int32_t n);
 int kfb_brand_update(kfb_state_t st, const void* M, int64_t ldm, int32_t n, void* workspace,
                      size_t ws_bytes, kfb_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as kfb_brand_update with no workspace argument.  Its workspace is a
+ * library-owned device array of kfb_scratch_bytes() bytes (64 MiB), one per
+ * GPU, held until the process ends; the call allocates nothing.  Every call
+ * on one GPU shares that array: calls that overlap in time on one GPU (on
+ * different streams, or from different host threads) race and must be
+ * serialised by the caller.  The device is the current HIP device, which must
+ * be the one holding the state.  Errors as kfb_brand_update, plus
+ * KFB_EWORKSPACE when the update needs more than kfb_scratch_bytes() (then
+ * nothing is enqueued) and KFB_EHIP when the array's address cannot be
+ * resolved. */
+size_t kfb_scratch_bytes(void);
+int kfb_brand_update_scratch(kfb_state_t st, const void* M, int64_t ldm, int32_t n, kfb_stream_t stream);
+
 /* Grouped form: `count` independent updates in one set of launches.  All
  * states must share d, r, precision and current k_valid, and all batches the
  * same n and ldm (one shape bucket); results equal `count` separate calls. */

@@ -1350,9 +1350,48 @@ int dispatch_correct(kfb_state_t st, const void* X, int64_t ldx, const int32_t* 
   return KFB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free update: the workspace is a file-scope device array, one copy
+// per GPU, resolved to a device address once per device (the array's name in
+// host code is not a device address).
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+__device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // indexed by device ordinal
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return KFB_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[(size_t)dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KFB_EHIP;
+    g_scratch_ptr[(size_t)dev] = p;
+  }
+  *out = g_scratch_ptr[(size_t)dev];
+  return KFB_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t kfb_scratch_bytes(void) { return SCRATCH_BYTES; }
+
+int kfb_brand_update_scratch(kfb_state_t st, const void* M, int64_t ldm, int32_t n, kfb_stream_t stream) {
+  if (!st || !M) return KFB_EINVAL;
+  size_t need = 0;
+  int rc = dispatch_update(1, &st, nullptr, ldm, n, nullptr, 0, nullptr, &need);
+  if (rc != KFB_OK) return rc;
+  if (need > SCRATCH_BYTES) return KFB_EWORKSPACE;
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws)) != KFB_OK) return rc;
+  const void* Ms[1] = {M};
+  return dispatch_update(1, &st, Ms, ldm, n, ws, SCRATCH_BYTES, (hipStream_t)stream, nullptr);
+}
 
 size_t kfb_state_bytes(int64_t d, int32_t r, int32_t n_max, int32_t prec) {
   if (d <= 0 || r < 0 || n_max <= 0 || (int64_t)r + n_max > d) return 0;

@@ -30,6 +30,8 @@ _SIGS = {
     "kfb_destroy": (ctypes.c_int, [_vp]),
     "kfb_update_workspace_bytes": (_sz, [_vp, _i32]),
     "kfb_brand_update": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "kfb_scratch_bytes": (_sz, []),
+    "kfb_brand_update_scratch": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp]),
     "kfb_update_batched_workspace_bytes": (_sz, [_i32, ctypes.POINTER(_vp), _i32]),
     "kfb_brand_update_batched": (ctypes.c_int, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i64, _i32,
                                                 _vp, _sz, _vp]),
