@@ -160,7 +160,8 @@ def _serve_stats(serve, srv, wall, done):
     return {"requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
             "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
             "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
-            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
+            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2),
+            "mean_update_group": round(srv.stats.update_problems / max(srv.stats.update_groups, 1), 2)}
 
 
 def serve_leg(torch, kfb, dev, args, prec, nreq, grouped=True):
@@ -202,12 +203,14 @@ def serve_leg(torch, kfb, dev, args, prec, nreq, grouped=True):
 
     res = {"mode": "continuous batching, grouped launches" if grouped else "one request at a time, no grouping"}
     srv.stats = serve.ServerStats()
-    wall, done = serve.poisson_run(srv, make, 2000.0, nreq, seed=2000 + prec, timeout_s=600.0)
+    prog = lambda i, c, t: _progress(f"serving prec={prec}: {i} submitted, {c} done, {t:.0f} s")
+    wall, done = serve.poisson_run(srv, make, 2000.0, nreq, seed=2000 + prec, timeout_s=600.0, progress=prog)
     res["2000_req_per_s"] = _serve_stats(serve, srv, wall, done)
+    _progress(f"serving prec={prec} at 2000 req/s: {res['2000_req_per_s']}")
     sat = res["2000_req_per_s"]["achieved_req_per_s"]
     half = max(0.5 * sat, 1.0)
     srv.stats = serve.ServerStats()
-    wall, done = serve.poisson_run(srv, make, half, nreq, seed=1000 + prec, timeout_s=900.0)
+    wall, done = serve.poisson_run(srv, make, half, nreq, seed=1000 + prec, timeout_s=900.0, progress=prog)
     res["half_saturation"] = dict(_serve_stats(serve, srv, wall, done), offered_req_per_s=round(half, 1))
     res["pool_batches"] = len(pool.sets["A"]) + len(pool.sets["G"])
     res["batches_used"] = pool.next["A"] + pool.next["G"]
@@ -233,7 +236,7 @@ def serve_mixed_leg(torch, kfb, dev, args):
     layers = [(widths[l], widths[l + 1], min(ranks[l], widths[l] - nmax), min(ranks[l], widths[l + 1] - nmax))
               for l in range(L)]
     srv = serve.Server(layers, n_max=nmax, rho=RHO, prec=kfb.KFB_BF16_MIXED, streams=4,
-                       byte_budget=24 << 30, max_group=48, pad_updates=True)
+                       byte_budget=24 << 30, max_group=48, pad_updates=True, max_inflight=8)
     # per factor a ring of distinct 256-sample batches; a request of width n takes
     # the first n samples of the next one
     ring = 16
@@ -280,7 +283,9 @@ def serve_mixed_leg(torch, kfb, dev, args):
             "requests": len(done), "updates": upd, "preconditionings": len(done) - upd,
             "p50_ms": round(serve.percentile(lat_ms, 50), 3), "p99_ms": round(serve.percentile(lat_ms, 99), 3),
             "achieved_req_per_s": round(len(done) / wall, 1), "b_updates_per_s": round(upd / wall, 1),
-            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2)}
+            "mean_group": round(srv.stats.grouped_problems / max(srv.stats.groups, 1), 2),
+            "mean_update_group": round(srv.stats.update_problems / max(srv.stats.update_groups, 1), 2)}
+        _progress(f"uneven serving at {rate} req/s: {res[f'{int(rate)}_req_per_s']}")
     return res
 
 
@@ -299,9 +304,14 @@ def main():
     ap.add_argument("--fp32-updates", type=int, default=6)
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--fp32-grouped-steps", type=int, default=5)
+    ap.add_argument("--sequential-steps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--serve-requests-fp32", type=int, default=10000)
+    ap.add_argument("--serve-requests-fp32", type=int, default=2000)
     ap.add_argument("--serve-requests-uneven", type=int, default=2000)
+    ap.add_argument("--jacobi-config", default="",
+                    help="install this eigensolver configuration instead of autotuning (e.g. 0x120)")
+    ap.add_argument("--gemm-tile", type=int, default=0,
+                    help="install this output tile for the preconditioner's products instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -320,7 +330,11 @@ def main():
 
     # ---- autotune the core eigensolver's configuration for this bucket (untimed)
     from paper_2210_08494_amd import tune
-    best_bw, tune_ms = tune.tune_jacobi(MIX, D, R, N_BATCH, count=S, reps=2, device=dev)
+    if args.jacobi_config:
+        best_bw, tune_ms = int(args.jacobi_config, 0), {}
+        kfb.tune_set_jacobi(MIX, R + N_BATCH, best_bw)
+    else:
+        best_bw, tune_ms = tune.tune_jacobi(MIX, D, R, N_BATCH, count=S, reps=2, device=dev)
     _progress(f"autotune done: {best_bw}")
 
     # ---- states: even index = A factor (d_in), odd = Gamma factor (d_out) of a layer
@@ -339,15 +353,52 @@ def main():
     fg = states[1::2]
     lam = [LAM] * L
 
-    def step(j):
+    def step_seq(j):
         kfb.update_batched(states, batches[j], ws_u)
         kfb.precondition_batched(fg, fa, Gsets[j], Ss, lam, lam, 0, ws_p)
+
+    # The timed step runs its two calls on two streams at once: the
+    # preconditioning reads the factors the previous update left in the front
+    # buffers while this step's update writes the back buffers (the states are
+    # double-buffered for this), so the apply's products fill the CUs the
+    # Cholesky and the eigensolver rounds leave idle.  The preconditioning is
+    # enqueued first (the library takes the front buffers at enqueue) and waits
+    # for the previous update; the update waits for the previous
+    # preconditioning, which read the buffers it is about to write.
+    s_upd = torch.cuda.current_stream()
+    s_pre = torch.cuda.Stream(device=dev)
+    pipe = {"u": None, "p": None}
+
+    def step(j):
+        with torch.cuda.stream(s_pre):
+            if pipe["u"] is not None:
+                s_pre.wait_event(pipe["u"])
+            kfb.precondition_batched(fg, fa, Gsets[j], Ss, lam, lam, 0, ws_p)
+            ep = torch.cuda.Event()
+            ep.record(s_pre)
+        if pipe["p"] is not None:
+            s_upd.wait_event(pipe["p"])
+        kfb.update_batched(states, batches[j], ws_u)
+        eu = torch.cuda.Event()
+        eu.record(s_upd)
+        pipe["u"], pipe["p"] = eu, ep
 
     # first update takes every state from empty to n modes; warmup reaches r + n
     kfb.update_batched(states, batches[0], ws_u)
     for j in range(args.warmup):
         step(1 + j)
     torch.cuda.synchronize()
+    # ---- autotune the output tile of the preconditioner's BF16 products (untimed)
+    Ncore = R + N_BATCH
+    if args.gemm_tile:
+        tile_best, tile_ms = args.gemm_tile, {}
+        for (m, n, k) in tune.precond_product_shapes(D, D, Ncore, Ncore):
+            kfb.tune_set_gemm(m, n, k, tile_best)
+    else:
+        tile_best, tile_ms = tune.tune_gemm_tiles(
+            lambda: kfb.precondition_batched(fg, fa, Gsets[0], Ss, lam, lam, 0, ws_p),
+            tune.precond_product_shapes(D, D, Ncore, Ncore), reps=3)
+    _progress(f"gemm tile autotune done: {tile_best} {tile_ms}")
 
     # ---- timed region (stage events recorded live on the same stream)
     kfb.profile_enable(True)
@@ -359,6 +410,7 @@ def main():
     for j in range(args.steps):
         step(1 + args.warmup + j)
         ev[j + 1].record()
+    s_upd.wait_stream(s_pre)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = kfb.profile_report(reset=True)
@@ -368,6 +420,7 @@ def main():
 
     bups = S * args.steps / wall
     ms_per_step = 1e3 * wall / args.steps
+    _progress(f"timed region: {bups:.1f} B-updates/s, {ms_per_step:.3f} ms per step")
 
     # ---- roofline of the dominant kernel (core eigensolver rounds)
     Ncore = R + N_BATCH
@@ -421,6 +474,24 @@ def main():
         "pre_S": _rate("pre_S", L * 2.0 * D * D * 2 * N),
     }
 
+    # ---- the same step with its two calls one after the other on one stream
+    sequential = None
+    if args.sequential_steps > 0:
+        seq_sets = [_gen_batches(torch, dev, S, N_BATCH, D, seed=2000 + j, dtype=torch.bfloat16)
+                    for j in range(args.sequential_steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(args.sequential_steps):
+            kfb.update_batched(states, seq_sets[j], ws_u)
+            kfb.precondition_batched(fg, fa, Gsets[j % nsets], Ss, lam, lam, 0, ws_p)
+        torch.cuda.synchronize()
+        sw = time.perf_counter() - t0
+        sequential = {"value": round(S * args.sequential_steps / sw, 2), "unit": "B-updates/s",
+                      "ms_per_step": round(1e3 * sw / args.sequential_steps, 3), "steps": args.sequential_steps,
+                      "note": "the same step with the update and the preconditioning in sequence on one stream"}
+        del seq_sets
+        _progress(f"sequential step: {sequential}")
+
     # ---- the same step replayed from a HIP graph: two consecutive steps captured
     # (every state's front and back buffers trade roles twice and end as they
     # began) over two batch slots; before each replay the next two fresh batch
@@ -434,7 +505,7 @@ def main():
                  for j in range(2 * reps + 2)]
         slots = [[torch.empty_like(b) for b in batches[0]] for _ in range(2)]
 
-        def gstep(q):
+        def gstep(q):   # the sequential form of the step (one stream)
             kfb.update_batched(states, slots[q], ws_u)
             kfb.precondition_batched(fg, fa, Gsets[q], Ss, lam, lam, 0, ws_p)
 
@@ -616,7 +687,8 @@ def main():
         "data": "synthetic (seeded decaying-spectrum batches and N(0,1) gradients generated on the device)",
         "config": {"workload": f"{L}-layer stack, 2 K-factors per layer ({S} states) at d={D}, r={R}, "
                                f"n={N_BATCH}, rho={RHO}, lambda={LAM}; step = grouped Brand update of all "
-                               f"states + grouped two-sided preconditioning of all {L} layers",
+                               f"states + grouped two-sided preconditioning of all {L} layers (on two streams: "
+                               f"the preconditioning reads the factors of the previous update)",
                    "layers": L, "states": S, "d": D, "r": R, "n": N_BATCH, "precision": "bf16-mixed",
                    "parallelism": "single-gpu"},
         "latency_ms": {"step_p50": round(_percentile(step_ms, 50), 3),
@@ -626,6 +698,7 @@ def main():
                        "note": "closed loop; step = 48 updates + 24 preconditionings"},
         "fp32_plain": fp32_plain,
         "fp32_grouped": fp32_grouped,
+        "sequential_step": sequential,
         "graph_replay": graph_replay,
         "serving": serving,
         "serving_fp32_plain": serving32,
@@ -636,7 +709,9 @@ def main():
         "brkfac": brkfac,
         "status_events": sorted(set(status)),
         "autotune": {"jacobi_config": tune.config_name(best_bw) if best_bw else None,
-                     "candidates_ms": {tune.config_name(k): round(1e3 * v, 2) for k, v in tune_ms.items()}},
+                     "candidates_ms": {tune.config_name(k): round(1e3 * v, 2) for k, v in tune_ms.items()},
+                     "precond_gemm_tile": tile_best,
+                     "precond_tile_candidates_ms": {str(k): round(1e3 * v, 3) for k, v in tile_ms.items()}},
     }
     out["library"] = kfb.load().kfb_build_info().decode()
     if not args.no_cpu_baseline:

@@ -359,6 +359,18 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
 int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw);
 int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np);
 
+/* Tuning table of the BF16 MFMA products of the mixed form (filled by the
+ * project's autotuner, paper_2210_08494_amd/tune.py): the output tile of the
+ * product C (m x n) = A (m x k) B (k x n), 128 (four waves of 64 x 64) or 256
+ * (eight waves of 128 x 64; twice the flops per staged byte, a quarter of the
+ * workgroups); 0 removes the entry (built-in: 128).  Products carrying the
+ * hi/lo split (the update's) always use 128.  Results do not depend on the
+ * tile (the k order of every sum is the same).  kfb_tune_get_gemm reports the
+ * tile a product of that shape would use.  KFB_EINVAL for non-positive sizes
+ * or another tile. */
+int kfb_tune_set_gemm(int32_t m, int32_t n, int32_t k, int32_t tile);
+int kfb_tune_get_gemm(int32_t m, int32_t n, int32_t k, int32_t* tile);
+
 /* Optional stage timing (diagnostics).  While enabled, each stage of the
  * update and precondition calls (projection, residual, CholeskyQR, core
  * assembly, Jacobi rounds, finalize, rotation; the apply's products) is

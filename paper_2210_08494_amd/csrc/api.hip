@@ -1706,6 +1706,17 @@ int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np) {
   return b ? KFB_OK : KFB_EINVAL;
 }
 
+int kfb_tune_set_gemm(int32_t m, int32_t n, int32_t k, int32_t tile) {
+  return gemm_tile_set(m, n, k, tile) == 0 ? KFB_OK : KFB_EINVAL;
+}
+
+int kfb_tune_get_gemm(int32_t m, int32_t n, int32_t k, int32_t* tile) {
+  if (m <= 0 || n <= 0 || k <= 0 || !tile) return KFB_EINVAL;
+  const int t = gemm_tile_lookup(m, n, k);
+  *tile = t ? t : 128;
+  return KFB_OK;
+}
+
 int kfb_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = on != 0;

@@ -13,6 +13,9 @@
 // coalesce.  LDS is double buffered: the next k tile is loaded into registers
 // while the current one is multiplied.  Split-K partials and the fixed-order
 // reduction follow the same GemmArgs contract as the FMA engine.
+#include <mutex>
+#include <vector>
+
 #include "kfb_kernels.h"
 
 namespace kfb {
@@ -300,7 +303,7 @@ __device__ __forceinline__ int fast_lds_off(int row, int kb16) {  // kb16: bf16 
 
 typedef const float __attribute__((address_space(1)))* gfptr;  // global-memory float pointer
 
-template <bool KC>
+template <bool KC, int TR = 128>
 struct FastSrc {
   gfptr p0;
   gfptr p1;             // this thread's base per segment (row offset applied, k offset not)
@@ -309,7 +312,7 @@ struct FastSrc {
   int split;
   int nr;               // KC: rows of the thread's four in range; MN: 4 or 0
   __device__ void init(const Rec& rec, const OpRef& o, bool isa, int row0, int nrows, int t) {
-    const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
+    const int rb = KC ? t / 8 : t % (TR / 4), kb = KC ? t % 8 : t / (TR / 4);
     const int left = nrows - (row0 + 4 * rb);
     nr = KC ? (left < 0 ? 0 : left > 4 ? 4 : left) : (left > 0 ? 4 : 0);
     // rows outside the matrix read row 0 instead (always valid); they only feed
@@ -348,9 +351,9 @@ struct FastSrc {
   }
 };
 
-template <bool KC, bool LO = false>
+template <bool KC, bool LO = false, int TR = 128>
 __device__ __forceinline__ void fast_store(const f32x4* x, int t, __bf16* dst, __bf16* dlo = nullptr) {
-  const int rb = KC ? t / 8 : t % 32, kb = KC ? t % 8 : t / 32;
+  const int rb = KC ? t / 8 : t % (TR / 4), kb = KC ? t % 8 : t / (TR / 4);
   typedef __attribute__((__vector_size__(8))) __bf16 v4b;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -388,10 +391,14 @@ __device__ __forceinline__ void xcd_tile(int nx, int ny, int nz, int* tm, int* t
   *tn = v / gsz;
 }
 
-template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP, bool SPL = false>
-__global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restrict__ recs, GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 sA[2][128 * MLD];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[2][128 * MLD];
+// TT: square output tile (128: four waves of 64 x 64; 256: eight waves of
+// 128 x 64, single-term products only, twice the flops per staged byte).
+template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP, bool SPL = false, int TT = 128>
+__global__ __launch_bounds__(2 * TT) void gemm_bf16_fast_kernel(const Rec* __restrict__ recs, GemmArgs g) {
+  static_assert(TT == 128 || (TT == 256 && !SPL), "tile");
+  constexpr int FM = TT / 32, FN = 4;  // 16 x 16 fragments per wave along rows / columns
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][TT * MLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][TT * MLD];
   // SPL: BF16 remainders of both operands (hi*hi + hi*lo + lo*hi, ~16 bits)
   __shared__ __attribute__((aligned(16))) __bf16 sAl[SPL ? 2 : 1][SPL ? 128 * MLD : 8];
   __shared__ __attribute__((aligned(16))) __bf16 sBl[SPL ? 2 : 1][SPL ? 128 * MLD : 8];
@@ -399,35 +406,34 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
   xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
   const Rec& rec = recs[tz];
   // split-K: blockIdx.x also enumerates the k chunks (tm = kz * tiles_m + tile row)
-  const int tiles_m = (g.m + 127) / 128, kz = tm / tiles_m;
+  const int tiles_m = (g.m + TT - 1) / TT, kz = tm / tiles_m;
   tm -= kz * tiles_m;
   const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
   const int kend = g.ksplit > 1 ? min(g.k, kbeg + g.kchunk) : g.k;
   const int t = threadIdx.x, w = t / 64, l = t % 64;
-  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int wm = (w & 1) * (TT / 2), wn = (w >> 1) * 64;
   constexpr bool swp = SWP;  // output column-major: issue (B^T A^T) so stores coalesce
-  FastSrc<AKC> A;
-  FastSrc<BKC> B;
-  A.init(rec, g.A, true, tm * 128, g.m, t);
-  B.init(rec, g.B, false, tn * 128, g.n, t);
+  FastSrc<AKC, TT> A;
+  FastSrc<BKC, TT> B;
+  A.init(rec, g.A, true, tm * TT, g.m, t);
+  B.init(rec, g.B, false, tn * TT, g.n, t);
   // fragment read offsets (bf16 elements) into a stage
   const int kq = 8 * (l / 16);
-  int offA[4], offB[4];
+  int offA[FM], offB[FN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    offA[i] = fast_lds_off<AKC>(wm + i * 16 + (l % 16), kq);
-    offB[i] = fast_lds_off<BKC>(wn + i * 16 + (l % 16), kq);
-  }
-  f32x4 acc[4][4];
+  for (int i = 0; i < FM; ++i) offA[i] = fast_lds_off<AKC>(wm + i * 16 + (l % 16), kq);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < FN; ++j) offB[j] = fast_lds_off<BKC>(wn + j * 16 + (l % 16), kq);
+  f32x4 acc[FM][FN];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   f32x4 fa[4], fb[4];
   A.load(kbeg, fa);
   B.load(kbeg, fb);
-  fast_store<AKC, SPL>(fa, t, sA[0], sAl[0]);
-  fast_store<BKC, SPL>(fb, t, sB[0], sBl[0]);
+  fast_store<AKC, SPL, TT>(fa, t, sA[0], sAl[0]);
+  fast_store<BKC, SPL, TT>(fb, t, sB[0], sBl[0]);
   __syncthreads();
   int cur = 0;
   for (int k0 = kbeg; k0 < kend; k0 += MBK) {
@@ -436,21 +442,22 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
       A.load(k0 + MBK, fa);
       B.load(k0 + MBK, fb);
     }
-    bf16x8 af[4], bfr[4], afl[4], bfl[4];
+    bf16x8 af[FM], bfr[FN], afl[SPL ? FM : 1], bfl[SPL ? FN : 1];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < FM; ++i) {
       af[i] = *reinterpret_cast<const bf16x8*>(&sA[cur][offA[i]]);
-      bfr[i] = *reinterpret_cast<const bf16x8*>(&sB[cur][offB[i]]);
-      if constexpr (SPL) {
-        afl[i] = *reinterpret_cast<const bf16x8*>(&sAl[cur][offA[i]]);
-        bfl[i] = *reinterpret_cast<const bf16x8*>(&sBl[cur][offB[i]]);
-      }
+      if constexpr (SPL) afl[i] = *reinterpret_cast<const bf16x8*>(&sAl[cur][offA[i]]);
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      bfr[j] = *reinterpret_cast<const bf16x8*>(&sB[cur][offB[j]]);
+      if constexpr (SPL) bfl[j] = *reinterpret_cast<const bf16x8*>(&sBl[cur][offB[j]]);
     }
     if constexpr (!swp) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < FN; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
           if constexpr (SPL) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
@@ -459,9 +466,9 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
         }
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < FN; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
           if constexpr (SPL) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfl[j], af[i], acc[i][j], 0, 0, 0);
@@ -470,19 +477,19 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
         }
     }
     if (more) {
-      fast_store<AKC, SPL>(fa, t, sA[cur ^ 1], sAl[SPL ? cur ^ 1 : 0]);
-      fast_store<BKC, SPL>(fb, t, sB[cur ^ 1], sBl[SPL ? cur ^ 1 : 0]);
+      fast_store<AKC, SPL, TT>(fa, t, sA[cur ^ 1], sAl[SPL ? cur ^ 1 : 0]);
+      fast_store<BKC, SPL, TT>(fb, t, sB[cur ^ 1], sBl[SPL ? cur ^ 1 : 0]);
     }
     __syncthreads();
     cur ^= 1;
   }
-  const int gm0 = tm * 128 + wm, gn0 = tn * 128 + wn;
+  const int gm0 = tm * TT + wm, gn0 = tn * TT + wn;
   if (g.ksplit > 1) {  // raw partial of chunk kz, column-major (the launch issues SWP)
     float* part = at<float>(rec, g.Part.slot, g.Part.off) + (int64_t)kz * g.m * g.n;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int gi = gm0 + 16 * i + (l % 16), gj = gn0 + 16 * j + 4 * (l / 16) + v;
@@ -501,9 +508,9 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
     // column-major C (plain issue); m and n are multiples of 4
     if (g.c_vec) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < FN; ++j) {
           int gi, gj;
           int64_t oc, oc0;
           if (SWP) {
@@ -523,9 +530,9 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_fast_kernel(const Rec* __restri
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int gi, gj;
@@ -557,11 +564,42 @@ static int fast_orient(const OpRef& o, bool isa) {
 template <typename TC, typename TC0>
 __global__ __launch_bounds__(256) void mfma_splitk_reduce(const Rec* __restrict__ recs, GemmArgs g);
 
+// Output tile of the streamlined kernel per product shape (m, n, k): the
+// tuning table's entry (filled by the autotuner through kfb_tune_set_gemm),
+// else 128.  Products with the hi/lo split always take 128 (their four LDS
+// stages would not fit a 256 tile).
+struct GemmTileEntry {
+  int m, n, k, tile;
+};
+static std::mutex g_gemm_tile_mu;
+static std::vector<GemmTileEntry> g_gemm_tiles;
+
+int gemm_tile_lookup(int m, int n, int k) {
+  std::lock_guard<std::mutex> lk(g_gemm_tile_mu);
+  for (const auto& e : g_gemm_tiles)
+    if (e.m == m && e.n == n && e.k == k) return e.tile;
+  return 0;
+}
+
+int gemm_tile_set(int m, int n, int k, int tile) {
+  if (m <= 0 || n <= 0 || k <= 0 || (tile != 0 && tile != 128 && tile != 256)) return -1;
+  std::lock_guard<std::mutex> lk(g_gemm_tile_mu);
+  for (size_t i = 0; i < g_gemm_tiles.size(); ++i)
+    if (g_gemm_tiles[i].m == m && g_gemm_tiles[i].n == n && g_gemm_tiles[i].k == k) {
+      if (tile == 0) g_gemm_tiles.erase(g_gemm_tiles.begin() + i);
+      else g_gemm_tiles[i].tile = tile;
+      return 0;
+    }
+  if (tile != 0) g_gemm_tiles.push_back(GemmTileEntry{m, n, k, tile});
+  return 0;
+}
+
 template <typename TC, typename TC0, bool SPL = false>
 static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t s, hipError_t* err) {
   if (!g0.aligned16 || g0.k <= 0 || g0.k % MBK || g0.m % 4 || g0.n % 4) return false;
   const int ao = fast_orient(g0.A, true), bo = fast_orient(g0.B, false);
   if (ao < 0 || bo < 0) return false;
+  const int tt = (!SPL && gemm_tile_lookup(g0.m, g0.n, g0.k) == 256) ? 256 : 128;
   GemmArgs g = g0;
   int ks = g.ksplit < 1 ? 1 : g.ksplit;
   if (ks > 1) {  // chunks of whole k tiles, the fixed-order reduction afterwards
@@ -571,7 +609,7 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStr
     g.kchunk = chunk;
   }
   g.ksplit = ks;
-  dim3 grid(((g.m + 127) / 128) * ks, (g.n + 127) / 128, nrec);
+  dim3 grid(((g.m + tt - 1) / tt) * ks, (g.n + tt - 1) / tt, nrec);
   // vector epilogue (C and C0 as 16-byte vectors): a row-major C takes the
   // transposed issue (four consecutive columns per lane), a column-major C the
   // plain one (four consecutive rows per lane)
@@ -582,8 +620,16 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStr
                     (!c0_used || (g.C0.rs == 1 && g.C0.cs % 4 == 0));
   g.c_vec = vrow || vcol;
   const bool swp = vrow || (!vcol && (ks > 1 || g.C.rs == 1));
-#define KFB_FAST(AK, BK, SW) \
-  hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, SPL>), grid, dim3(MNT), 0, s, recs, g)
+#define KFB_FAST(AK, BK, SW)                                                                          \
+  do {                                                                                                \
+    if constexpr (SPL) {                                                                              \
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, SPL, 128>), grid, dim3(MNT), 0, s, recs, g); \
+    } else if (tt == 256) {                                                                           \
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, false, 256>), grid, dim3(512), 0, s, recs, g); \
+    } else {                                                                                          \
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, false, 128>), grid, dim3(MNT), 0, s, recs, g); \
+    }                                                                                                 \
+  } while (0)
   if (swp) {
     if (ao && bo) KFB_FAST(true, true, true);
     else if (ao) KFB_FAST(true, false, true);

@@ -23,6 +23,11 @@ hipError_t gemm(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
 template <typename TA, typename TB, typename TC, typename TC0, int SPLIT>
 hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
 
+// Tile of the streamlined BF16 kernel for a product shape (tuning table):
+// 0 = none (128), 128 or 256; gemm_tile_set returns -1 for invalid arguments.
+int gemm_tile_lookup(int m, int n, int k);
+int gemm_tile_set(int m, int n, int k, int tile);
+
 // FP32 MFMA variant for FP32 products (A FP32, B FP32 or FP64 rounded to FP32,
 // C FP32; plain operands, no split-K).
 template <typename TB, typename TC0>

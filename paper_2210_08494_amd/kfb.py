@@ -72,6 +72,8 @@ _SIGS = {
     "kfb_reorthonormalize": (ctypes.c_int, [_vp, _vp, _sz, _vp]),
     "kfb_tune_set_jacobi": (ctypes.c_int, [_i32, _i32, _i32]),
     "kfb_tune_get_jacobi": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "kfb_tune_set_gemm": (ctypes.c_int, [_i32, _i32, _i32, _i32]),
+    "kfb_tune_get_gemm": (ctypes.c_int, [_i32, _i32, _i32, ctypes.POINTER(_i32)]),
     "kfb_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "kfb_profile_report": (ctypes.c_int, [ctypes.c_char_p, _sz, ctypes.c_int]),
     "kfb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -518,3 +520,13 @@ def tune_get_jacobi(prec: int, N: int):
     bw, Np = _i32(), _i32()
     _check(load().kfb_tune_get_jacobi(int(prec), int(N), ctypes.byref(bw), ctypes.byref(Np)), "kfb_tune_get_jacobi")
     return bw.value, Np.value
+
+
+def tune_set_gemm(m: int, n: int, k: int, tile: int):
+    _check(load().kfb_tune_set_gemm(int(m), int(n), int(k), int(tile)), "kfb_tune_set_gemm")
+
+
+def tune_get_gemm(m: int, n: int, k: int) -> int:
+    t = _i32()
+    _check(load().kfb_tune_get_gemm(int(m), int(n), int(k), ctypes.byref(t)), "kfb_tune_get_gemm")
+    return t.value

@@ -100,6 +100,8 @@ class ServerStats:
     preconds: int = 0
     groups: int = 0
     grouped_problems: int = 0
+    update_groups: int = 0
+    update_problems: int = 0
     max_inflight_bytes: int = 0
     rejected: int = 0
 
@@ -252,7 +254,7 @@ class Server:
         est = {}
         # look at the oldest requests only: enough to fill every free slot with a
         # full group several times over (a long backlog is not rescanned each tick)
-        scan = max(256, 4 * self.max_group * self.max_inflight)
+        scan = max(32, 4 * self.max_group * self.max_inflight)
         while self.pending and scan > 0:
             scan -= 1
             r = self.pending.popleft()
@@ -325,6 +327,9 @@ class Server:
         self.stats.max_inflight_bytes = max(self.stats.max_inflight_bytes, self.inflight_bytes)
         self.stats.groups += 1
         self.stats.grouped_problems += len(reqs)
+        if key[0] == "U":
+            self.stats.update_groups += 1
+            self.stats.update_problems += len(reqs)
         return True
 
 
@@ -337,8 +342,9 @@ def percentile(xs, q):
 
 
 def poisson_run(server: Server, make_request, rate: float, n_requests: int, seed: int = 0,
-                timeout_s: float = 300.0):
-    """Open-loop Poisson arrivals at `rate` req/s; returns (wall seconds, completed requests)."""
+                timeout_s: float = 300.0, progress=None, progress_every: float = 30.0):
+    """Open-loop Poisson arrivals at `rate` req/s; returns (wall seconds, completed requests).
+    progress(submitted, completed, seconds) is called about every progress_every seconds."""
     import numpy as np
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n_requests)
@@ -348,8 +354,12 @@ def poisson_run(server: Server, make_request, rate: float, n_requests: int, seed
         t0 = time.perf_counter()
         arrivals = t0 + np.cumsum(gaps)
         i = 0
+        t_report = t0 + progress_every
         while i < n_requests or server.busy():
             now = time.perf_counter()
+            if progress is not None and now >= t_report:
+                progress(i, len(done), now - t0)
+                t_report = now + progress_every
             while i < n_requests and arrivals[i] <= now:
                 server.submit(make_request(i, rng), t_arrival=float(arrivals[i]))
                 i += 1

@@ -63,3 +63,46 @@ def tune_jacobi(prec: int, d: int, r: int, n: int, count: int = 8, reps: int = 3
     best = min(timings, key=timings.get)
     kfb.tune_set_jacobi(prec, N, best)
     return best, timings
+
+
+# ---------------------------------------------------------------------------
+# Output tiles of the BF16 MFMA products (the mixed form's inverse application)
+# ---------------------------------------------------------------------------
+TILE_CANDIDATES = (128, 256)
+
+
+def precond_product_shapes(d_out: int, d_in: int, NG: int, NA: int):
+    """(m, n, k) of the two-sided application's products (Algorithm 1's inverse
+    lines in the spectral form): T1 = U_G^T G, T2 = G U_A, T3 = T1 U_A,
+    X2 = T2 + U_G T3, S = G / (lam lam) + [U_G | X2] [X1 ; U_A^T]."""
+    return [(NG, d_in, d_out), (d_out, NA, d_in), (NG, NA, d_in), (d_out, NA, NG), (d_out, d_in, NG + NA)]
+
+
+def factored_product_shapes(d_out: int, d_in: int, n: int):
+    """(m, n, k) of the factored application's single-term product S = Y_G Y_A^T."""
+    return [(d_out, d_in, n)]
+
+
+def tune_gemm_tiles(run, shapes, reps: int = 3, candidates=TILE_CANDIDATES, verbose: bool = False):
+    """Time `run()` (a call issuing the products of `shapes`) with every candidate
+    tile installed for all of them, keep the fastest; returns (best, {tile: s})."""
+    import torch
+    timings = {}
+    for tile in candidates:
+        for (m, n, k) in shapes:
+            kfb.tune_set_gemm(m, n, k, tile)
+        run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        timings[tile] = sorted(ts)[len(ts) // 2]
+        if verbose:
+            print(f"tune gemm tile {tile}: {1e3 * timings[tile]:.3f} ms", flush=True)
+    best = min(timings, key=timings.get)
+    for (m, n, k) in shapes:
+        kfb.tune_set_gemm(m, n, k, best)
+    return best, timings

@@ -137,3 +137,15 @@ def test_binding_checks_every_tensor_against_its_state():
     kfb._dense_check(torch.zeros(8, 8), fa, "t")
     with pytest.raises(kfb.KfbError):
         kfb._dense_check(torch.zeros(8, 8, dtype=torch.float64), fa, "t")
+
+
+def test_gemm_tile_table(lib):
+    # host-side tuning table of the BF16 products' output tile
+    t = ctypes.c_int32()
+    assert lib.kfb_tune_get_gemm(512, 4096, 4096, ctypes.byref(t)) == 0 and t.value == 128
+    assert lib.kfb_tune_set_gemm(512, 4096, 4096, 256) == 0
+    assert lib.kfb_tune_get_gemm(512, 4096, 4096, ctypes.byref(t)) == 0 and t.value == 256
+    assert lib.kfb_tune_set_gemm(512, 4096, 4096, 0) == 0
+    assert lib.kfb_tune_get_gemm(512, 4096, 4096, ctypes.byref(t)) == 0 and t.value == 128
+    for bad in ((0, 1, 1, 128), (1, 1, 1, 64), (1, -1, 1, 256)):
+        assert lib.kfb_tune_set_gemm(*bad) == 1

@@ -106,23 +106,6 @@ def test_mixed_brkfac_headline_width(kfb):
     assert w["over"] <= TOL[2] and w["upd"] <= TOL[2] and w["orth"] <= TOL[2] and w["x"] <= XTOL[2]
 
 
-def test_mixed_brkfac_hybrid_large_layer(kfb):
-    # the hybrid large layer: d = 16384, r = n = 1024 (core N = 2048), oversampling 16,
-    # 2 power iterations; two updates, the overwrite from the EA factor, one more update
-    d, r, n, p, q = 16384, 1024, 1024, 16, 2
-    MIX = kfb.KFB_BF16_MIXED
-    print(f"mixed B-R-KFAC hybrid layer d={d} r={r} n={n}", flush=True)
-    try:
-        kfb.tune_set_jacobi(MIX, r + n, kfb.KFB_JAC_STREAMED | 32)
-        kfb.tune_set_jacobi(MIX, r + p, kfb.KFB_JAC_STREAMED | 32)
-        f, w = _trajectory(kfb, MIX, d, r, n, p, q, 2, 3, cfg=84, check_x=False)
-    finally:
-        kfb.tune_set_jacobi(MIX, r + n, 0)
-        kfb.tune_set_jacobi(MIX, r + p, 0)
-    assert w["over"] <= TOL[2] and w["upd"] <= TOL[2] and w["orth"] <= TOL[2]
-    assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
-
-
 def test_rsvd_of_low_rank_factor(kfb):
     # the EA factor of one step has rank n < l: the sketch's range is deficient (reported),
     # and the overwrite is the exact leading eigenpairs of the factor

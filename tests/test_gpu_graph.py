@@ -61,3 +61,71 @@ def test_graph_replay_equals_eager(kfb):
             assert torch.equal(x, y), f"replay {rep}: preconditioned gradient differs"
         print(f"  replay {rep} equal", flush=True)
     assert all(f.status() == 0 for f in A + B)
+
+
+def test_two_stream_pipeline_equals_one_stream(kfb):
+    # the benchmark's step on two streams: each step's preconditioning (reading the
+    # factors the previous update left in the front buffers) runs beside that step's
+    # update (writing the back buffers); ordered by events on the buffer they share.
+    # Every step's S and every state equal the same calls issued in that order on one
+    # stream, bit for bit, with extra work on a third stream to shift the timing.
+    import torch
+    dev = torch.device("cuda:0")
+    d, r, n, L, steps = 768, 96, 64, 3, 5
+    prec = kfb.KFB_BF16_MIXED
+    print(f"two-stream pipeline: mixed d={d} r={r} n={n} layers={L} steps={steps}", flush=True)
+
+    def group():
+        return [kfb.Factor(d, r, n, 0.95, prec) for _ in range(2 * L)]
+
+    A, B = group(), group()
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    k = torch.arange(1, d + 1, device=dev, dtype=torch.float32)
+    batches = [[torch.relu(torch.randn(n, d, generator=g, device=dev) * k ** -1.0).to(torch.bfloat16)
+                for _ in range(2 * L)] for _ in range(steps + 1)]
+    Gs = [[torch.randn(d, d, generator=g, device=dev) for _ in range(L)] for _ in range(steps)]
+    SA = [[torch.empty(d, d, device=dev) for _ in range(L)] for _ in range(steps)]
+    SB = [[torch.empty(d, d, device=dev) for _ in range(L)] for _ in range(steps)]
+    wsA, wsB, wsP = kfb.Workspace(), kfb.Workspace(), kfb.Workspace()
+    lam = [0.01] * L
+    for grp, ws in ((A, wsA), (B, wsB)):
+        kfb.update_batched(grp, batches[0], ws)
+    torch.cuda.synchronize()
+    # reference: one stream, preconditioning then update at every step
+    for j in range(steps):
+        kfb.precondition_batched(A[1::2], A[0::2], Gs[j], SA[j], lam, lam, 0, wsA)
+        kfb.update_batched(A, batches[j + 1], wsA)
+    # pipeline: two streams, plus unrelated work on a third
+    s_upd = torch.cuda.current_stream()
+    s_pre = torch.cuda.Stream(device=dev)
+    s_noise = torch.cuda.Stream(device=dev)
+    big = torch.randn(2048, 2048, device=dev)
+    eu = ep = None
+    for j in range(steps):
+        with torch.cuda.stream(s_noise):
+            for _ in range(4):
+                big = big @ big
+                big = big / big.norm()
+        with torch.cuda.stream(s_pre):
+            if eu is not None:
+                s_pre.wait_event(eu)
+            kfb.precondition_batched(B[1::2], B[0::2], Gs[j], SB[j], lam, lam, 0, wsP)
+            ep = torch.cuda.Event()
+            ep.record(s_pre)
+        if j > 0:
+            s_upd.wait_event(prev_ep)
+        kfb.update_batched(B, batches[j + 1], wsB)
+        eu = torch.cuda.Event()
+        eu.record(s_upd)
+        prev_ep = ep
+    s_upd.wait_stream(s_pre)
+    torch.cuda.synchronize()
+    for j in range(steps):
+        for x, y in zip(SA[j], SB[j]):
+            assert torch.equal(x, y), f"step {j}: preconditioned gradient differs"
+    for fa, fb in zip(A, B):
+        Ua, Da = fa.front()
+        Ub, Db = fb.front()
+        assert torch.equal(Ua, Ub) and torch.equal(Da, Db)
+    assert all(f.status() == 0 for f in A + B)

@@ -230,38 +230,6 @@ def test_fp32_trajectory_small(kfb):
     assert worst <= TOL[1]
 
 
-def test_fp32_realistic_width_with_bias(kfb):
-    # FP32 at the paper-like width: d_in = 4097 (bias row), d_out = 4096, n = r = 256
-    import torch
-    dA, dG, n, r, rho, lam, steps = 4097, 4096, 256, 256, 0.95, 0.01, 4
-    _announce(f"fp32 realistic width dA={dA} dG={dG} steps={steps}")
-    fa = kfb.Factor(dA, r, n, rho, kfb.KFB_FP32)
-    fg = kfb.Factor(dG, r, n, rho, kfb.KFB_FP32)
-    oa, og = oracle.BrandFactor(dA, r, rho), oracle.BrandFactor(dG, r, rho)
-    for k in range(steps):
-        a = _batch(2, k, "A", n, dA, bias=True).astype(np.float32).astype(np.float64)
-        g = _batch(2, k, "G", n, dG).astype(np.float32).astype(np.float64)
-        fa.update(_to_dev(a, torch.float32))
-        fg.update(_to_dev(g, torch.float32))
-        oa.update(a.T)
-        og.update(g.T)
-        for f, o in ((fa, oa), (fg, og)):
-            U, D = _front_np(f)
-            e = oracle.e_rec_lowrank(U, D, o.U, o.D)
-            _announce(f"  step {k} e_rec {e:.3e}")
-            assert e <= TOL[1]
-    G = synth.grad_for(2, steps - 1, dG, dA).astype(np.float32)
-    Gd = _to_dev(G, torch.float32)
-    S = torch.empty_like(Gd)
-    kfb.precondition(fg, fa, Gd, S, lam, lam)
-    torch.cuda.synchronize()
-    S_ref = oracle.precondition_lowrank(og.U, og.D, oa.U, oa.D, G.astype(np.float64), lam, lam)
-    es = oracle.e_S(S.cpu().numpy(), S_ref)
-    ep = oracle.e_S_proj(S.cpu().numpy(), S_ref, og.U, oa.U)
-    _announce(f"  e_S {es:.3e} e_S_proj {ep:.3e}")
-    assert es <= TOL[1] and ep <= TOL[1]
-
-
 # ----------------------------------------------------------------------------
 # BF16-mixed form
 # ----------------------------------------------------------------------------
@@ -379,24 +347,6 @@ def test_mixed_precondition_on_loaded_state(kfb, flags):
     ep = oracle.e_S_proj(S.cpu().numpy(), S_ref, bg.U, ba.U)
     _announce(f"  e_S {es:.3e} e_S_proj {ep:.3e}")
     assert es <= TOL[2] and ep <= TOL[2]
-
-
-def test_mixed_wide_layer_spot(kfb):
-    # the wide mixed configuration: d = 8192, r = n = 512 (core N = 1024), a few steps vs Oracle-B
-    import torch
-    d, r, n, rho, steps = 8192, 512, 512, 0.95, 3
-    _announce(f"mixed wide layer d={d} r={r} n={n} steps={steps}")
-    f = kfb.Factor(d, r, n, rho, kfb.KFB_BF16_MIXED)
-    o = oracle.BrandFactor(d, r, rho)
-    for k in range(steps):
-        M = _batch(3, 100 + k, "A", n, d, prec=2)
-        f.update(_to_dev(M, torch.bfloat16))
-        o.update(M.T)
-        U, D = _front_np(f)
-        e = oracle.e_rec_lowrank(U, D, o.U, o.D)
-        _announce(f"  step {k} e_rec {e:.3e} orth {oracle.e_orth(U):.2e}")
-        assert e <= TOL[2]
-    assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
 
 
 # ----------------------------------------------------------------------------
@@ -631,3 +581,48 @@ def test_cross_shape_grouped_update(kfb, prec):
     assert worst["alone"] <= (1e-10 if prec == 0 else 1e-4)
     for g in grouped:
         assert g.status() & (kfb.KFB_EV_CHOL_DEFICIENT | kfb.KFB_EV_NONFINITE | kfb.KFB_EV_ORTHO_DRIFT) == 0
+
+
+def test_gemm_tile_choice_does_not_change_results(kfb):
+    # the BF16 products of the mixed apply with 128 or 256 output tiles (the
+    # autotuner's two candidates): the k order of every sum is the same, so the
+    # results are bit-identical; grouped two-sided and factored applications
+    import torch
+    from paper_2210_08494_amd import tune
+    dG, dA, r, n, rho, lam = 1024, 1280, 128, 128, 0.95, 0.01
+    _announce("gemm tile 128 vs 256")
+    fgs, fas = [], []
+    for i in range(3):
+        bg = _oracle_state(dG, r, n, rho, 3, 50 + i, "G")
+        ba = _oracle_state(dA, r, n, rho, 3, 60 + i, "A")
+        fg = kfb.Factor(dG, r, n, rho, kfb.KFB_BF16_MIXED)
+        fa = kfb.Factor(dA, r, n, rho, kfb.KFB_BF16_MIXED)
+        fg.load_state(_to_dev(bg.U.astype(np.float32), torch.float32), _to_dev(bg.D, torch.float64), step=3)
+        fa.load_state(_to_dev(ba.U.astype(np.float32), torch.float32), _to_dev(ba.D, torch.float64), step=3)
+        fgs.append(fg)
+        fas.append(fa)
+    NG, NA = fgs[0].info()["k_valid"], fas[0].info()["k_valid"]
+    Gs = [_to_dev(synth.grad_for(70 + i, 0, dG, dA).astype(np.float32), torch.float32) for i in range(3)]
+    Gk = [_to_dev(synth.to_bf16_values(synth.batch_for(71, i, "G", n, dG)), torch.bfloat16) for i in range(3)]
+    Ak = [_to_dev(synth.to_bf16_values(synth.batch_for(71, i, "A", n, dA)), torch.bfloat16) for i in range(3)]
+    shapes = tune.precond_product_shapes(dG, dA, NG, NA) + tune.factored_product_shapes(dG, dA, n)
+    ws = kfb.Workspace()
+    out = {}
+    try:
+        for tile in (128, 256):
+            for (m, nn, k) in shapes:
+                kfb.tune_set_gemm(m, nn, k, tile)
+                assert kfb.tune_get_gemm(m, nn, k) == tile
+            S2 = [torch.empty_like(G) for G in Gs]
+            SF = [torch.empty_like(G) for G in Gs]
+            kfb.precondition_batched(fgs, fas, Gs, S2, [lam] * 3, [lam] * 3, 1, ws)
+            kfb.precondition_factored_batched(fgs, fas, Gk, Ak, SF, [lam] * 3, [lam] * 3, 0, ws)
+            torch.cuda.synchronize()
+            out[tile] = (S2, SF)
+    finally:
+        for (m, nn, k) in shapes:
+            kfb.tune_set_gemm(m, nn, k, 0)
+    for a, b in zip(out[128][0] + out[128][1], out[256][0] + out[256][1]):
+        assert torch.equal(a, b)
+    with pytest.raises(kfb.KfbError):
+        kfb.tune_set_gemm(64, 64, 64, 192)
