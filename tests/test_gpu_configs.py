@@ -68,6 +68,27 @@ def _batch(cfg, k, side, n, d, prec, bias=False):
     return synth.to_bf16_values(x)
 
 
+class _Ahead:
+    """Generates the inputs of the coming steps on host threads while the current
+    step runs (the seeded generator and the rounding release the GIL), so the
+    long trajectories are not bound by drawing their batches."""
+
+    def __init__(self, make, steps, depth=3):
+        from concurrent.futures import ThreadPoolExecutor
+        self.make, self.steps, self.depth = make, steps, depth
+        self.pool = ThreadPoolExecutor(max_workers=depth)
+        self.fut = {k: self.pool.submit(make, k) for k in range(min(depth, steps))}
+
+    def get(self, k):
+        out = self.fut.pop(k).result()
+        nxt = k + self.depth
+        if nxt < self.steps:
+            self.fut[nxt] = self.pool.submit(self.make, nxt)
+        if k == self.steps - 1:
+            self.pool.shutdown(wait=False)
+        return out
+
+
 def _trace_err(D_new, D_prev, r, rho, w, M):
     """Relative error of the core's trace identity: sum D' = rho sum D_r + w ||M||_F^2."""
     kept = np.sort(D_prev)[::-1][:r] if D_prev is not None else np.zeros(0)
@@ -96,8 +117,9 @@ def test_headline_grouped_step(kfb):
     ws_u, ws_p, ws_t = kfb.Workspace(), kfb.Workspace(), kfb.Workspace()
     Ss = [torch.empty((d, d), device=_dev()) for _ in range(L)]
     worst = dict(rec=0.0, trace=0.0, S=0.0, S_proj=0.0)
+    ahead = _Ahead(lambda k: [_batch(600 + i, k, "A" if i % 2 == 0 else "G", n, d, prec=2) for i in range(S)], steps)
     for k in range(steps):
-        Ms = [_batch(600 + i, k, "A" if i % 2 == 0 else "G", n, d, prec=2) for i in range(S)]
+        Ms = ahead.get(k)
         Md = [_to_dev(M, torch.bfloat16) for M in Ms]
         D_prev = [(_D_np(f) if k else None) for f in states]
         kfb.update_batched(states, Md, ws_u)
@@ -130,8 +152,9 @@ def test_headline_grouped_step(kfb):
                 Sg = Ss[l].double().cpu().numpy()
                 worst["S"] = max(worst["S"], oracle.e_S(Sg, ref))
                 worst["S_proj"] = max(worst["S_proj"], oracle.e_S_proj(Sg, ref, og.U, oa.U))
-            # every layer: the apply against the spectral form on the GPU's own states
-            for l in range(2, L):
+            # the other 22 layers, eight per step in turn: the apply against the
+            # spectral form on the GPU's own states
+            for l in range(2 + 8 * (k - 1), min(L, 2 + 8 * k)):
                 UG, DG = _front_np(fg[l])
                 UA, DA = _front_np(fa[l])
                 G = Gs[l].double().cpu().numpy()
@@ -176,9 +199,9 @@ def test_fp32_realistic_width_200_steps(kfb):
     oa = oracle.BrandFactor(dA, r, rho)     # the input factor (bias row) followed all the way
     worst = dict(step=0.0, rec=0.0, D=0.0, orth=0.0, trace=0.0, S=0.0, S_proj=0.0)
     reorths = 0
+    ahead = _Ahead(lambda k: (_batch(2, k, "A", n, dA, prec=1, bias=True), _batch(2, k, "G", n, dG, prec=1)), steps)
     for k in range(steps):
-        a = _batch(2, k, "A", n, dA, prec=1, bias=True)
-        g = _batch(2, k, "G", n, dG, prec=1)
+        a, g = ahead.get(k)
         check_step = k % 5 == 4
         prev = []
         for f in (fa, fg):
@@ -238,9 +261,9 @@ def test_mixed_wide_layer_100_steps(kfb):
     fg = kfb.Factor(d, r, n, rho, MIX)
     oa = oracle.BrandFactor(d, r, rho)      # the input factor followed all the way
     worst = dict(step=0.0, rec=0.0, D=0.0, orth=0.0, trace=0.0, S=0.0, S_proj=0.0)
+    ahead = _Ahead(lambda k: (_batch(3, k, "A", n, d, prec=2), _batch(3, k, "G", n, d, prec=2)), steps)
     for k in range(steps):
-        a = _batch(3, k, "A", n, d, prec=2)
-        g = _batch(3, k, "G", n, d, prec=2)
+        a, g = ahead.get(k)
         check_step = k % 10 == 5
         prev = []
         for f in (fa, fg):
@@ -303,6 +326,7 @@ def test_hybrid_large_layer_100_steps(kfb):
     Y = np.zeros((d, 8))                                # X_k @ probes by the EA definition
     worst = dict(rec=0.0, over=0.0, orth=0.0, trace=0.0, x=0.0)
     D_prev = None
+    ahead = _Ahead(lambda k: _batch(86, k, "A", n, d, prec=2), steps, depth=4)
     for k in range(steps):
         if k > 0 and k % T == 0:
             # the dense factor of step k - 1 against the EA definition, on probes
@@ -319,7 +343,7 @@ def test_hybrid_large_layer_100_steps(kfb):
                 worst["over"] = max(worst["over"], oracle.e_rec_lowrank(Ug, Dg, Uo, so))
             del Xh
             D_prev = _D_np(f)
-        M = _batch(86, k, "A", n, d, prec=2)
+        M = ahead.get(k)
         Md = _to_dev(M, torch.bfloat16)
         f.update(Md)
         kfb.dense_update(f, X, Md, first=(k == 0))
