@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--fp32-grouped-steps", type=int, default=5)
     ap.add_argument("--sequential-steps", type=int, default=5)
+    ap.add_argument("--one-stream", action="store_true",
+                    help="time the step with its two calls in sequence on one stream")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-requests-fp32", type=int, default=2000)
     ap.add_argument("--serve-requests-uneven", type=int, default=2000)
@@ -370,6 +372,9 @@ def main():
     pipe = {"u": None, "p": None}
 
     def step(j):
+        if args.one_stream:   # the sequential form (profiling runs: per-kernel durations without overlap)
+            step_seq(j)
+            return
         with torch.cuda.stream(s_pre):
             if pipe["u"] is not None:
                 s_pre.wait_event(pipe["u"])

@@ -37,49 +37,63 @@ def _grid(row):
         return _col(row, "Grid_Size")
 
 
-def pmc_main(argv):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("dir")
-    ap.add_argument("prefix")
-    ap.add_argument("--trace-dir", default="")
-    ap.add_argument("--trace-prefix", default="")
-    ap.add_argument("--cmd", action="append", default=[])
-    ap.add_argument("--top", type=int, default=20)
-    a = ap.parse_args(argv)
-    rows = list(csv.DictReader(open(os.path.join(a.dir, f"{a.prefix}_counter_collection.csv"))))
+def _counters(path):
+    """{dispatch id: (kernel name, total grid, {counter: value})} of a counter-collection CSV."""
     disp = {}
-    for r in rows:
+    for r in csv.DictReader(open(path)):
         did = int(_col(r, "Dispatch_Id", "Correlation_Id"))
-        d = disp.setdefault(did, {"name": re.sub(r"\(.*", "", _col(r, "Kernel_Name")), "grid": _grid(r), "c": {}})
+        d = disp.setdefault(did, (re.sub(r"\(.*", "", _col(r, "Kernel_Name")), r.get("Grid_Size", ""), {}))
         cn = _col(r, "Counter_Name")
-        d["c"][cn] = d["c"].get(cn, 0.0) + float(_col(r, "Counter_Value"))
-    order = sorted(disp)
-    last = disp[order[-1]]
+        d[2][cn] = d[2].get(cn, 0.0) + float(_col(r, "Counter_Value"))
+    return disp
+
+
+def pmc_main(argv):
+    """HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE run of the same
+    command, each scaled by what its counter reads for the command's last dispatch
+    (a plain device copy of --calib-mib MiB), with durations from a kernel trace of
+    the same command (dispatches matched by id: the command enqueues the same
+    sequence every run)."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True, help="counter_collection.csv of the FETCH_SIZE run")
+    ap.add_argument("--write", required=True, help="counter_collection.csv of the WRITE_SIZE run")
+    ap.add_argument("--trace", default="", help="kernel_trace.csv of the same command")
+    ap.add_argument("--calib-mib", type=float, default=256.0)
+    ap.add_argument("--cmd", action="append", default=[])
+    ap.add_argument("--top", type=int, default=24)
+    a = ap.parse_args(argv)
+    fe, wr = _counters(a.fetch), _counters(a.write)
+    last = max(fe)
+    kib = a.calib_mib * 1024.0
+    sf = kib / fe[last][2]["FETCH_SIZE"]
+    sw = kib / wr[max(wr)][2]["WRITE_SIZE"]
+    dur = {}
+    if a.trace:
+        for r in csv.DictReader(open(a.trace)):
+            dur[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     for c in a.cmd:
         print(f"command: {c}")
-    print(f"dispatches: {len(order)}; calibration (last dispatch): {last['name'][:60]} grid {last['grid']} "
-          + " ".join(f"{k}={v:.0f}" for k, v in last["c"].items()))
-    durs = {}
-    if a.trace_dir:
-        for r in csv.DictReader(open(os.path.join(a.trace_dir, f"{a.trace_prefix}_kernel_trace.csv"))):
-            key = (re.sub(r"\(.*", "", r["Kernel_Name"]), _grid(r))
-            durs.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print(f"dispatches: {len(fe)}; reference copy of {a.calib_mib:.0f} MiB (last dispatch): FETCH_SIZE "
+          f"{fe[last][2]['FETCH_SIZE']:.0f} KiB, WRITE_SIZE {wr[max(wr)][2]['WRITE_SIZE']:.0f} KiB -> "
+          f"scale fetch x{sf:.3f}, write x{sw:.3f}")
     agg = {}
-    for did in order[:-1]:
-        d = disp[did]
-        g = agg.setdefault((d["name"], d["grid"]), {"n": 0, "c": {}})
+    for did, (name, grid, c) in fe.items():
+        if did == last or did not in wr:
+            continue
+        g = agg.setdefault((name, grid), {"n": 0, "f": 0.0, "w": 0.0, "t": 0.0, "nt": 0})
         g["n"] += 1
-        for k, v in d["c"].items():
-            g["c"][k] = g["c"].get(k, 0.0) + v
-    names = sorted({k for g in agg.values() for k in g["c"]})
-    key0 = names[0] if names else ""
-    items = sorted(agg.items(), key=lambda kv: -kv[1]["c"].get(key0, 0.0))
-    print(f"{'n':>6} " + " ".join(f"{n + '/disp':>18}" for n in names) + f" {'avg_us':>9}  kernel  grid")
+        g["f"] += c.get("FETCH_SIZE", 0.0) * 1024.0 * sf
+        g["w"] += wr[did][2].get("WRITE_SIZE", 0.0) * 1024.0 * sw
+        if did in dur:
+            g["t"] += dur[did]
+            g["nt"] += 1
+    items = sorted(agg.items(), key=lambda kv: -(kv[1]["f"] + kv[1]["w"]))
+    print(f"{'n':>6} {'fetch_MB/disp':>14} {'write_MB/disp':>14} {'avg_us':>9} {'GB/s':>8}  kernel  (grid threads)")
     for (name, grid), g in items[:a.top]:
-        avg = {k: v / g["n"] for k, v in g["c"].items()}
-        ds = durs.get((name, grid))
-        us = sum(ds) / len(ds) if ds else float("nan")
-        print(f"{g['n']:6d} " + " ".join(f"{avg.get(n, 0.0):18.1f}" for n in names) + f" {us:9.2f}  {name[:90]}  {grid}")
+        f, w = g["f"] / g["n"], g["w"] / g["n"]
+        t = g["t"] / g["nt"] if g["nt"] else float("nan")
+        gbs = (f + w) / t / 1e9 if g["nt"] else float("nan")
+        print(f"{g['n']:6d} {f / 1e6:14.2f} {w / 1e6:14.2f} {t * 1e6:9.1f} {gbs:8.0f}  {name[:95]}  ({grid})")
 
 
 def main():
@@ -93,6 +107,8 @@ def main():
     ap.add_argument("--grid", action="append", default=[])
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--cmd", default="")
+    ap.add_argument("--last", type=int, default=0,
+                    help="also report the last N dispatches of the --kernel selections together")
     a = ap.parse_args()
     stats = list(csv.DictReader(open(os.path.join(a.dir, f"{a.prefix}_kernel_stats.csv"))))
     trace = list(csv.DictReader(open(os.path.join(a.dir, f"{a.prefix}_kernel_trace.csv"))))
@@ -105,16 +121,23 @@ def main():
         name = re.sub(r"\(.*", "", r["Name"])[:100]
         print(f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f} {int(r['Calls']):7d} "
               f"{float(r['AverageNs']) / 1e3:10.2f}  {name}")
+    chosen = []
     for i, k in enumerate(a.kernel):
         grid = a.grid[i] if i < len(a.grid) else ""
         sel = [r for r in trace if k in r["Kernel_Name"]]
         if grid:
             gx, gy = grid.split(",")
             sel = [r for r in sel if r["Grid_Size_X"] == gx and r["Grid_Size_Y"] == gy]
+        chosen += sel
         durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
         if durs:
             print(f"kernel '{k}' grid ({grid or 'any'}): {len(durs)} dispatches, avg {sum(durs) / len(durs):.2f} us, "
                   f"total {sum(durs) / 1e3:.3f} ms, min {min(durs):.2f} us, max {max(durs):.2f} us")
+    if a.last and chosen:
+        chosen.sort(key=lambda r: int(r["Dispatch_Id"]))
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in chosen[-a.last:]]
+        print(f"last {len(durs)} dispatches of the selections above: avg {sum(durs) / len(durs):.2f} us, "
+              f"total {sum(durs) / 1e3:.3f} ms")
 
 
 if __name__ == "__main__":
