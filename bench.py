@@ -236,7 +236,7 @@ def serve_mixed_leg(torch, kfb, dev, args):
     layers = [(widths[l], widths[l + 1], min(ranks[l], widths[l] - nmax), min(ranks[l], widths[l + 1] - nmax))
               for l in range(L)]
     srv = serve.Server(layers, n_max=nmax, rho=RHO, prec=kfb.KFB_BF16_MIXED, streams=4,
-                       byte_budget=24 << 30, max_group=48, pad_updates=True, max_inflight=8)
+                       byte_budget=24 << 30, max_group=48, pad_updates=True, max_inflight=args.uneven_inflight)
     # per factor a ring of distinct 256-sample batches; a request of width n takes
     # the first n samples of the next one
     ring = 16
@@ -310,6 +310,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-requests-fp32", type=int, default=2000)
     ap.add_argument("--serve-requests-uneven", type=int, default=2000)
+    ap.add_argument("--uneven-inflight", type=int, default=8, help="groups in flight in the uneven serving leg")
     ap.add_argument("--jacobi-config", default="",
                     help="install this eigensolver configuration instead of autotuning (e.g. 0x120)")
     ap.add_argument("--gemm-tile", type=int, default=0,

@@ -52,8 +52,8 @@ def pmc_main(argv):
     """HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE run of the same
     command, each scaled by what its counter reads for the command's last dispatch
     (a plain device copy of --calib-mib MiB), with durations from a kernel trace of
-    the same command (dispatches matched by id: the command enqueues the same
-    sequence every run)."""
+    the same command (the k-th dispatch of each kernel and grid matched with its
+    k-th in the trace)."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True, help="counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write", required=True, help="counter_collection.csv of the WRITE_SIZE run")
@@ -67,25 +67,34 @@ def pmc_main(argv):
     kib = a.calib_mib * 1024.0
     sf = kib / fe[last][2]["FETCH_SIZE"]
     sw = kib / wr[max(wr)][2]["WRITE_SIZE"]
+    # the k-th dispatch of a (kernel, grid) in the counter run is matched with the
+    # k-th dispatch of the same (kernel, grid) in the trace: robust to commands whose
+    # streams interleave their launches differently from run to run
     dur = {}
     if a.trace:
-        for r in csv.DictReader(open(a.trace)):
-            dur[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        seen = {}
+        for r in sorted(csv.DictReader(open(a.trace)), key=lambda r: int(r["Dispatch_Id"])):
+            key = (re.sub(r"\(.*", "", r["Kernel_Name"]),
+                   str(int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])))
+            k = seen.get(key, 0)
+            seen[key] = k + 1
+            dur[key + (k,)] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     for c in a.cmd:
         print(f"command: {c}")
     print(f"dispatches: {len(fe)}; reference copy of {a.calib_mib:.0f} MiB (last dispatch): FETCH_SIZE "
           f"{fe[last][2]['FETCH_SIZE']:.0f} KiB, WRITE_SIZE {wr[max(wr)][2]['WRITE_SIZE']:.0f} KiB -> "
           f"scale fetch x{sf:.3f}, write x{sw:.3f}")
     agg = {}
-    for did, (name, grid, c) in fe.items():
+    for did, (name, grid, c) in sorted(fe.items()):
         if did == last or did not in wr:
             continue
         g = agg.setdefault((name, grid), {"n": 0, "f": 0.0, "w": 0.0, "t": 0.0, "nt": 0})
+        key = (name, grid, g["n"])
         g["n"] += 1
         g["f"] += c.get("FETCH_SIZE", 0.0) * 1024.0 * sf
         g["w"] += wr[did][2].get("WRITE_SIZE", 0.0) * 1024.0 * sw
-        if did in dur:
-            g["t"] += dur[did]
+        if key in dur:
+            g["t"] += dur[key]
             g["nt"] += 1
     items = sorted(agg.items(), key=lambda kv: -(kv[1]["f"] + kv[1]["w"]))
     print(f"{'n':>6} {'fetch_MB/disp':>14} {'write_MB/disp':>14} {'avg_us':>9} {'GB/s':>8}  kernel  (grid threads)")
