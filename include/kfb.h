@@ -347,14 +347,18 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
  * form prec, use the configuration bw:
  *   4, 8, 16, 32             column blocks of that width, the block pair's
  *                            panel held in LDS (the LDS limit must admit it);
- *   KFB_JAC_STREAMED | 16/32 column blocks of that width, panels read from
- *                            global memory (FP64 core: the FP64 and
- *                            BF16-mixed forms; at least four blocks).
+ *   KFB_JAC_STREAMED | 32     32-column blocks, panels read from global
+ *                            memory, on FP64 MFMA (FP64 core: the FP64 and
+ *                            BF16-mixed forms) or FP32 MFMA (the FP32 form);
+ *   KFB_JAC_STREAMED | 16     16-column blocks, panels read from global
+ *                            memory (FP64 core only);
+ * streamed configurations need at least four blocks.
  * Inadmissible values give KFB_EINVAL.  bw = 0 removes the entry, restoring
- * the built-in choice (the widest LDS block that fits).  Affects calls made
- * after it returns; results of a given table are deterministic.
- * kfb_tune_get_jacobi reports the configuration and padded size a call would
- * use. */
+ * the built-in choice: KFB_JAC_STREAMED | 32 for N >= 256 (and for the
+ * new-direction block solve of an update), else the widest LDS block that
+ * fits.  Affects calls made after it returns; results of a given table are
+ * deterministic.  kfb_tune_get_jacobi reports the configuration and padded
+ * size a core of size N would use. */
 #define KFB_JAC_STREAMED 0x100
 int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw);
 int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np);

@@ -111,6 +111,22 @@ int tuned_bw(int prec, int N) {
   return 0;
 }
 
+// Eigensolver configuration for a core of size N (element size es): the tuning
+// table's entry, else, where streamed panels are preferred (cores of N >= 256;
+// the new-direction block solve always), 64-column panels streamed from global
+// memory (the autotuner's pick at the headline core in FP64 and FP32), else the
+// widest LDS panel.  Writes the padded size; returns 0 if nothing fits.
+int pick_jacobi(int prec, int N, int es, bool prefer_streamed, int* Np) {
+  int cfg = tuned_bw(prec, N);
+  if (!cfg && prefer_streamed) cfg = JAC_STREAMED | 32;
+  const int np = cfg ? jacobi_block_fits(N, es, cfg) : 0;
+  if (np) {
+    *Np = np;
+    return cfg;
+  }
+  return jacobi_pick_block(N, es, Np);
+}
+
 inline size_t u_elem(int prec) { return prec == KFB_FP64 ? 8 : 4; }
 inline size_t d_elem(int prec) { return prec == KFB_FP32 ? 4 : 8; }
 inline size_t m_elem(int prec) { return prec == KFB_FP64 ? 8 : (prec == KFB_FP32 ? 4 : 2); }
@@ -170,18 +186,7 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   // the CholeskyQR kernels and the eigensolver's finalize bound the widths
   if (n < 1 || r < 0 || n > MAX_QR_COLS || r + n > MAX_CORE) return false;
   p->d = d; p->ldu = ldu; p->ldm = ldm; p->r = r; p->n = n; p->N = r + n;
-  // the tuning table's entry for N, else (FP64 cores of N >= 256) 64-column
-  // panels streamed from global memory, the autotuner's pick at the headline
-  // core, else the widest LDS panel
-  int tbw = tuned_bw(PR, p->N);
-  if (!tbw && sizeof(typename T::Core) == 8 && p->N >= 256) tbw = JAC_STREAMED | 32;
-  const int tNp = tbw ? jacobi_block_fits(p->N, (int)sizeof(typename T::Core), tbw) : 0;
-  if (tNp) {
-    p->bw = tbw;
-    p->Np = tNp;
-  } else {
-    p->bw = jacobi_pick_block(p->N, (int)sizeof(typename T::Core), &p->Np);
-  }
+  p->bw = pick_jacobi(PR, p->N, (int)sizeof(typename T::Core), p->N >= 256, &p->Np);
   if (p->bw == 0) return false;
   auto ks_for = [&](int m, int nn, int64_t k) {
     // split depends on the problem's own shape only, never on its batch-mates
@@ -215,18 +220,7 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   p->oCnt = take((size_t)MAX_SWEEPS * 4);
   p->pre = r > 0 && n >= PRE_MIN_N;
   if (p->pre) {
-    // the tuning table's entry for N = n, else (FP64 core) 64-column panels
-    // streamed from global memory, else the widest LDS panel
-    const int es = (int)sizeof(typename T::Core);
-    int tb = tuned_bw(PR, n);
-    if (!tb && es == 8) tb = JAC_STREAMED | 32;
-    const int tNp = tb ? jacobi_block_fits(n, es, tb) : 0;
-    if (tNp) {
-      p->prebw = tb;
-      p->preNp = tNp;
-    } else {
-      p->prebw = jacobi_pick_block(n, es, &p->preNp);
-    }
+    p->prebw = pick_jacobi(PR, n, (int)sizeof(typename T::Core), true, &p->preNp);
     if (p->prebw == 0) p->pre = false;
   }
   if (p->pre) {
@@ -245,13 +239,17 @@ inline OpRef op(int slot, int64_t off, int64_t rs, int64_t cs) {
 }
 
 // Product dispatch: the mixed form runs its FP32 products on BF16 MFMA
-// (SPLIT = 1: operands carried as BF16 hi + lo terms), the other forms on the
-// FP64 / FP32 FMA engine.
+// (SPLIT = 1: operands carried as BF16 hi + lo terms), the FP32 form its
+// products on FP32 MFMA (FP32 operands and accumulation), the FP64 form on the
+// FP64 FMA engine.
 template <int PR, int SPLIT, typename TA, typename TB, typename TC, typename TC0, typename TAcc>
 hipError_t mm(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
   if constexpr (PR == KFB_BF16_MIXED && sizeof(TA) == 4 && sizeof(TC) == 4 && sizeof(TAcc) == 4 &&
                 (sizeof(TB) == 4 || sizeof(TB) == 2)) {
     return gemm_bf16<TA, TB, TC, TC0, SPLIT>(recs, nrec, g, s);
+  } else if constexpr (PR == KFB_FP32 && sizeof(TA) == 4 && sizeof(TB) == 4 && sizeof(TC) == 4 &&
+                       sizeof(TC0) == 4 && sizeof(TAcc) == 4) {
+    return gemm_f32_mfma<TB, TC0>(recs, nrec, g, s);
   } else {
     return gemm<TA, TB, TC, TC0, TAcc>(recs, nrec, g, s);
   }
@@ -1698,9 +1696,8 @@ int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw) {
 int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np) {
   if (prec < KFB_FP64 || prec > KFB_BF16_MIXED || N <= 0) return KFB_EINVAL;
   const int eb = prec == KFB_FP32 ? 4 : 8;
-  int b = tuned_bw(prec, N), np = 0;
-  if (b) np = jacobi_block_fits(N, eb, b);
-  if (!np) b = jacobi_pick_block(N, eb, &np);
+  int np = 0;
+  const int b = pick_jacobi(prec, N, eb, N >= 256, &np);
   if (bw) *bw = b;
   if (Np) *Np = np;
   return b ? KFB_OK : KFB_EINVAL;

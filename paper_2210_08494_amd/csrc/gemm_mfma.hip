@@ -706,13 +706,18 @@ hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t 
 
 // ---------------------------------------------------------------------------
 // FP32 products on FP32 MFMA (v_mfma_f32_16x16x4f32): FP32 operands (B may be
-// FP64, rounded to FP32 on load, as the FMA engine does), FP32 accumulation.
+// FP64, rounded to FP32 on load, as the FMA engine does), FP32 accumulation:
+// the FP32 form's products, and Q = Z R^-1 of the mixed form's CholeskyQR.
 // 128 x 128 tiles of four waves (64 x 64 each), k in steps of 16 staged in LDS
 // (k-major rows, so a wave's fragment reads are consecutive words), the next
 // step's operands loaded while the current one is multiplied; XCD-aware tile
-// order; column-major outputs issue (B^T A^T) so the stores coalesce.  Plain
-// operands only (no segment split, no split-K); with b_upper the k loop of a
-// tile stops at its last column (the skipped terms are exact zeros).
+// order; column-major outputs issue (B^T A^T) so the stores coalesce.  Each
+// operand is read along its contiguous dimension (consecutive threads take
+// consecutive elements in memory) and may be a two-segment block matrix
+// (A = [A1 | A2] split at column `split`, B = [B1 ; B2] split at row `split`,
+// both segments of one orientation); split-K partials go to the fixed-order
+// reduction.  With b_upper the k loop of a tile stops at its last column (the
+// skipped terms are exact zeros).
 // ---------------------------------------------------------------------------
 constexpr int F32_BK = 16, F32_LD = 128 + 4;
 
@@ -723,31 +728,56 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restric
   int tm, tn, tz;
   xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
   const Rec& rec = recs[tz];
+  // split-K: blockIdx.x also enumerates the k chunks (tm = kz * tiles_m + tile row)
+  const int tiles_m = (g.m + 127) / 128, kz = tm / tiles_m;
+  tm -= kz * tiles_m;
   const float* A = at<const float>(rec, g.A.slot, g.A.off);
+  const float* A2 = g.A.slot2 >= 0 ? at<const float>(rec, g.A.slot2, g.A.off2) : nullptr;
   const TB* B = at<const TB>(rec, g.B.slot, g.B.off);
+  const TB* B2 = g.B.slot2 >= 0 ? at<const TB>(rec, g.B.slot2, g.B.off2) : nullptr;
+  const int asplit = A2 ? g.A.split : 0x7fffffff, bsplit = B2 ? g.B.split : 0x7fffffff;
+  // contiguous dimension of each operand: A along k (row-major A) or along i;
+  // B along j (row-major B) or along k
+  const bool a_k = g.A.cs == 1 && g.A.rs != 1, b_j = g.B.cs == 1 && g.B.rs != 1;
   const int t = threadIdx.x, w = t / 64, l = t % 64;
   const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
   const int m0 = tm * 128, n0 = tn * 128;
-  // staging: A element e = t + 256 q -> (row e % 128, k e / 128); B element -> (k e % 16, col e / 16)
+  const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
+  int kend = g.ksplit > 1 ? min(g.k, kbeg + g.kchunk) : g.k;
+  // an upper-triangular B contributes nothing below the tile's last column
+  if (g.b_upper) kend = min(kend, n0 + 128);
+  // staging: element e = t + 256 q of the 128 x 16 A tile is (i, k) = (e % 128, e / 128),
+  // or (e / 16, e % 16) when A runs along k; of the 16 x 128 B tile (k, j) = (e % 16, e / 16),
+  // or (e / 128, e % 128) when B runs along j
   float ra[8], rb[8];
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = t + 256 * q;
-      const int ia = e % 128, ka = e / 128;
+      const int ia = a_k ? e / F32_BK : e % 128, ka = a_k ? e % F32_BK : e / 128;
       const int gi = m0 + ia, gk = k0 + ka;
-      ra[q] = (gi < g.m && gk < g.k) ? A[(int64_t)gi * g.A.rs + (int64_t)gk * g.A.cs] : 0.f;
-      const int kb = e % F32_BK, jb = e / F32_BK;
+      float va = 0.f;
+      if (gi < g.m && gk < kend)
+        va = gk < asplit ? A[(int64_t)gi * g.A.rs + (int64_t)gk * g.A.cs]
+                         : A2[(int64_t)gi * g.A.rs2 + (int64_t)(gk - asplit) * g.A.cs2];
+      ra[q] = va;
+      const int kb = b_j ? e / 128 : e % F32_BK, jb = b_j ? e % 128 : e / F32_BK;
       const int gj = n0 + jb, gkb = k0 + kb;
-      rb[q] = (gj < g.n && gkb < g.k) ? (float)B[(int64_t)gkb * g.B.rs + (int64_t)gj * g.B.cs] : 0.f;
+      float vb = 0.f;
+      if (gj < g.n && gkb < kend)
+        vb = (float)(gkb < bsplit ? B[(int64_t)gkb * g.B.rs + (int64_t)gj * g.B.cs]
+                                  : B2[(int64_t)(gkb - bsplit) * g.B.rs2 + (int64_t)gj * g.B.cs2]);
+      rb[q] = vb;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = t + 256 * q;
-      sA[buf][e / 128][e % 128] = ra[q];
-      sB[buf][e % F32_BK][e / F32_BK] = rb[q];
+      if (a_k) sA[buf][e % F32_BK][e / F32_BK] = ra[q];
+      else sA[buf][e / 128][e % 128] = ra[q];
+      if (b_j) sB[buf][e / 128][e % 128] = rb[q];
+      else sB[buf][e % F32_BK][e / F32_BK] = rb[q];
     }
   };
   f32x4 acc[4][4];
@@ -755,13 +785,11 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restric
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // an upper-triangular B contributes nothing below the tile's last column
-  const int kend = g.b_upper ? min(g.k, n0 + 128) : g.k;
-  load(0);
+  load(kbeg);
   store(0);
   __syncthreads();
   int cur = 0;
-  for (int k0 = 0; k0 < kend; k0 += F32_BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += F32_BK) {
     const bool more = k0 + F32_BK < kend;
     if (more) load(k0 + F32_BK);
 #pragma unroll
@@ -783,6 +811,21 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restric
     if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
+  }
+  if (g.ksplit > 1) {  // partial sums, [kz][i + j m]
+    float* part = at<float>(rec, g.Part.slot, g.Part.off) + (int64_t)kz * g.m * g.n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int gi, gj;
+          if (SWP) { gi = m0 + wm + 16 * i + (l % 16); gj = n0 + wn + 16 * j + 4 * (l / 16) + v; }
+          else { gi = m0 + wm + 16 * i + 4 * (l / 16) + v; gj = n0 + wn + 16 * j + (l % 16); }
+          if (gi < g.m && gj < g.n) part[gi + (int64_t)gj * g.m] = acc[i][j][v];
+        }
+    return;
   }
   float* C = at<float>(rec, g.C.slot, g.C.off);
   const bool use_c0 = g.C0.slot >= 0 && (g.beta != 0.0 || g.beta_slot >= 0);
@@ -818,23 +861,46 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma_kernel(const Rec* __restric
         else { gi = m0 + wm + 16 * i + 4 * (l / 16) + v; gj = n0 + wn + 16 * j + (l % 16); }
         if (gi < g.m && gj < g.n) {
           float val = alpha * acc[i][j][v];
-          if (C0) val += beta * to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
-          C[gi * g.C.rs + gj * g.C.cs] = val;
+          if (C0) val += beta * to_f(C0[(int64_t)gi * g.C0.rs + (int64_t)gj * g.C0.cs]);
+          C[(int64_t)gi * g.C.rs + (int64_t)gj * g.C.cs] = val;
         }
       }
 }
 
 template <typename TB, typename TC0>
-hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
-  if (g.m <= 0 || g.n <= 0 || nrec <= 0) return hipSuccess;
-  if (g.A.slot2 >= 0 || g.B.slot2 >= 0 || g.ksplit > 1) return hipErrorInvalidValue;
-  dim3 grid((g.m + 127) / 128, (g.n + 127) / 128, nrec);
+hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t s) {
+  if (g0.m <= 0 || g0.n <= 0 || nrec <= 0) return hipSuccess;
+  GemmArgs g = g0;
+  if (g.k < 0) g.k = 0;
+  // a segmented operand: both segments run along the same dimension
+  auto seg_ok = [](const OpRef& o) {
+    if (o.slot2 < 0) return true;
+    const bool c1 = o.cs == 1 && o.rs != 1, c2 = o.cs2 == 1 && o.rs2 != 1;
+    return c1 == c2 && o.split > 0;
+  };
+  if (!seg_ok(g.A) || !seg_ok(g.B)) return hipErrorInvalidValue;
+  int ks = g.ksplit < 1 || g.k == 0 ? 1 : g.ksplit;
+  if (ks > 1) {  // chunks of whole k steps, the fixed-order reduction afterwards
+    if (g.Part.slot < 0) return hipErrorInvalidValue;
+    int chunk = (g.k + ks - 1) / ks;
+    chunk = ((chunk + F32_BK - 1) / F32_BK) * F32_BK;
+    ks = (g.k + chunk - 1) / chunk;
+    g.kchunk = chunk;
+  }
+  g.ksplit = ks;
+  dim3 grid(((g.m + 127) / 128) * ks, (g.n + 127) / 128, nrec);
   // column-major C with 16-byte columns (c_vec): the plain issue gives each lane
   // four consecutive rows, stored as one vector
-  GemmArgs gv = g;
-  gv.c_vec = g.c_vec && g.C.rs == 1 && g.C.cs % 4 == 0 && g.m % 4 == 0;
-  if (gv.c_vec || g.C.rs != 1) hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, false>), grid, dim3(256), 0, s, recs, gv);
-  else hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, true>), grid, dim3(256), 0, s, recs, gv);
+  g.c_vec = ks == 1 && g.c_vec && g.C.rs == 1 && g.C.cs % 4 == 0 && g.m % 4 == 0;
+  const bool plain = g.c_vec || (ks == 1 && g.C.rs != 1);
+  if (plain) hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, false>), grid, dim3(256), 0, s, recs, g);
+  else hipLaunchKernelGGL((gemm_f32_mfma_kernel<TB, TC0, true>), grid, dim3(256), 0, s, recs, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  const int64_t mn = (int64_t)g.m * g.n;
+  int blocks = (int)((mn + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL((mfma_splitk_reduce<float, TC0>), dim3(blocks, nrec), dim3(256), 0, s, recs, g);
   return hipGetLastError();
 }
 template hipError_t gemm_f32_mfma<double, float>(const Rec*, int, const GemmArgs&, hipStream_t);

@@ -102,8 +102,8 @@ hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, 
                         hipStream_t s);
 int jacobi_pick_block(int N, int elem_bytes, int* Np);
 // Eigensolver configuration: the block width (4, 8, 16, 32), for the kernel
-// that holds the panel in LDS, or JAC_STREAMED | width (16, 32; FP64 only) for
-// the kernels that read the panel from global memory.
+// that holds the panel in LDS, or JAC_STREAMED | width (32: FP64 or FP32;
+// 16: FP64 only) for the kernels that read the panel from global memory.
 constexpr int JAC_STREAMED = 0x100;
 // padded size for a configuration, or 0 if it is not admissible for N
 int jacobi_block_fits(int N, int elem_bytes, int cfg);

@@ -1090,7 +1090,28 @@ __global__ __launch_bounds__(JAC_NT) void jacobi_kernel(const Rec* __restrict__ 
 // ---------------------------------------------------------------------------
 constexpr int JG_NT = 512;
 constexpr int JG_P = 64, JG_BW = 32;
-constexpr int JG_LDS = (64 * 64 + 64 * 65) * 8;  // G and Z
+template <typename T> constexpr int JG_LDS = (64 * 64 + 64 * 65) * (int)sizeof(T);  // G and Z
+
+// MFMA 16x16x4 in the precision of the panel: FP64 (v_mfma_f64_16x16x4) or FP32
+// (v_mfma_f32_16x16x4).  Both take one A and one B element per lane (A: row
+// lane % 16, k lane / 16; B: k lane / 16, column lane % 16) and leave four
+// results per lane in column lane % 16; the rows differ: result v of a lane is
+// row lane / 16 + 4 v in FP64 and row 4 (lane / 16) + v in FP32 (row()).
+template <typename T> struct JgMma;
+template <> struct JgMma<double> {
+  typedef jac_d4 v4;
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct JgMma<float> {
+  typedef __attribute__((__vector_size__(4 * sizeof(float)))) float v4;
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
 
 __device__ __forceinline__ void jg_pair(bool full, int st, int ia, int* p, int* q) {
   // full: circle method over 64 columns (st < 63); otherwise cross pairs (st < 32)
@@ -1117,25 +1138,26 @@ __device__ __forceinline__ constexpr int jg_tile_b(int g, int u) {
 
 // Partial Gram tiles of group GRP over the 16-row steps q, q + 4, ... of the
 // panel (cp[i]: this lane's rows in column block i), the next step in flight.
-template <int GRP>
-__device__ __forceinline__ void jg_gram_part(const double* const* cp, int Ns, int q, jac_d4* acc) {
+template <typename T, int GRP>
+__device__ __forceinline__ void jg_gram_part(const T* const* cp, int Ns, int q, typename JgMma<T>::v4* acc) {
+  typedef typename JgMma<T>::v4 V4;
   constexpr int B0 = GRP;  // group 1 never reads column block 0
 #pragma unroll
-  for (int u = 0; u < 5; ++u) acc[u] = jac_d4{0.0, 0.0, 0.0, 0.0};
-  jac_d4 x[4], y[4];
+  for (int u = 0; u < 5; ++u) acc[u] = V4{T(0), T(0), T(0), T(0)};
+  V4 x[4], y[4];
   int st = q;
   if (st < Ns)
 #pragma unroll
-    for (int i = B0; i < 4; ++i) x[i] = *reinterpret_cast<const jac_d4*>(cp[i] + 16 * st);
+    for (int i = B0; i < 4; ++i) x[i] = *reinterpret_cast<const V4*>(cp[i] + 16 * st);
   for (; st < Ns; st += 4) {
     if (st + 4 < Ns)
 #pragma unroll
-      for (int i = B0; i < 4; ++i) y[i] = *reinterpret_cast<const jac_d4*>(cp[i] + 16 * (st + 4));
+      for (int i = B0; i < 4; ++i) y[i] = *reinterpret_cast<const V4*>(cp[i] + 16 * (st + 4));
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
       for (int u = 0; u < 5; ++u)
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[jg_tile_a(GRP, u)][e], x[jg_tile_b(GRP, u)][e], acc[u], 0, 0, 0);
+        acc[u] = JgMma<T>::mma(x[jg_tile_a(GRP, u)][e], x[jg_tile_b(GRP, u)][e], acc[u]);
 #pragma unroll
     for (int i = B0; i < 4; ++i) x[i] = y[i];
   }
@@ -1143,75 +1165,79 @@ __device__ __forceinline__ void jg_gram_part(const double* const* cp, int Ns, in
 
 // rotation (c, s) zeroing the (p, q) entry of a Gram, or false when the pair is
 // already orthogonal to tolerance (c = 1, s = 0)
-__device__ __forceinline__ bool jg_rot(double gpp, double gqq, double gpq, double tol, double* c, double* s) {
-  *c = 1.0;
-  *s = 0.0;
-  if (gpq != 0.0 && gpq * gpq > tol * tol * (gpp * gqq)) {
-    const double aa = gqq - gpp, bb = 2.0 * gpq;
-    const double ir = dev_rsqrt(aa * aa + bb * bb);
-    const double yy = 0.5 * (1.0 + fabs(aa) * ir);
-    const double ry = dev_rsqrt(yy);
+template <typename T>
+__device__ __forceinline__ bool jg_rot(T gpp, T gqq, T gpq, T tol, T* c, T* s) {
+  *c = T(1);
+  *s = T(0);
+  if (gpq != T(0) && gpq * gpq > tol * tol * (gpp * gqq)) {
+    const T aa = gqq - gpp, bb = T(2) * gpq;
+    const T ir = dev_rsqrt(aa * aa + bb * bb);
+    const T yy = T(0.5) * (T(1) + fabs(aa) * ir);
+    const T ry = dev_rsqrt(yy);
     *c = yy * ry;
-    *s = (aa >= 0.0 ? bb : -bb) * ir * 0.5 * ry;
+    *s = (aa >= T(0) ? bb : -bb) * ir * T(0.5) * ry;
     return true;
   }
   return false;
 }
 
 // J_A^T g J_B for the 2 x 2 block g = {(pa, pb), (pa, qb), (qa, pb), (qa, qb)}
-__device__ __forceinline__ void jg_rot_block(double ca, double sa, double cb, double sb, double* g) {
-  const double r00 = cb * g[0] - sb * g[1], r01 = sb * g[0] + cb * g[1];
-  const double r10 = cb * g[2] - sb * g[3], r11 = sb * g[2] + cb * g[3];
+template <typename T>
+__device__ __forceinline__ void jg_rot_block(T ca, T sa, T cb, T sb, T* g) {
+  const T r00 = cb * g[0] - sb * g[1], r01 = sb * g[0] + cb * g[1];
+  const T r10 = cb * g[2] - sb * g[3], r11 = sb * g[2] + cb * g[3];
   g[0] = ca * r00 - sa * r10;
   g[2] = sa * r00 + ca * r10;
   g[1] = ca * r01 - sa * r11;
   g[3] = sa * r01 + ca * r11;
 }
 
+template <typename T>
 __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restrict__ recs, JacArgs a, int sweep,
                                                             int round) {
   extern __shared__ __attribute__((aligned(16))) unsigned char jg_smem[];
   constexpr int P = JG_P, BW = JG_BW, NP2 = P / 2;
   constexpr int ZP = P + 1;  // row stride of Z
-  double* G = reinterpret_cast<double*>(jg_smem);  // G[i*P + j]
-  double* Z = G + P * P;                           // Z[i*ZP + j]
-  double* slot = G;                                // Gram partials (5 tiles x 256 per slot), before G is formed
-  __shared__ double rc[NP2], rsn[NP2];
-  __shared__ double hc[2][NP2], hs[2][NP2];  // cross rounds: rotations of the current and next step
+  typedef typename JgMma<T>::v4 V4;
+  T* G = reinterpret_cast<T*>(jg_smem);  // G[i*P + j]
+  T* Z = G + P * P;                      // Z[i*ZP + j]
+  T* slot = G;                           // Gram partials (5 tiles x 256 per slot), before G is formed
+  __shared__ T rc[NP2], rsn[NP2];
+  __shared__ T hc[2][NP2], hs[2][NP2];  // cross rounds: rotations of the current and next step
   __shared__ int pass_rot, any_off, step_any[2];
   const Rec& rec = recs[blockIdx.y];
   int32_t* cnt = at<int32_t>(rec, WS, a.off_cnt);
   const int Np = a.Np, Ns = Np / 16;
   const int nb = Np / BW;  // >= 4
   if (sweep > 0 && cnt[sweep - 1] == 0) return;
-  double* Bm = at<double>(rec, WS, a.off_B);
-  double* Vm = at<double>(rec, WS, a.off_V);
+  T* Bm = at<T>(rec, WS, a.off_B);
+  T* Vm = at<T>(rec, WS, a.off_V);
   int I, J;
   tour_pair(nb, round, blockIdx.x, &I, &J);
   auto gcol = [&](int c) { return c < BW ? I * BW + c : J * BW + (c - BW); };
   const int t = threadIdx.x, w = t / 64, l = t % 64;
-  const double tol = a.tol;
+  const T tol = T(a.tol);
   const bool full = round == 0;
 
   // ---- 1. Gram
   {
     const int q = w & 3, grp = w >> 2;
-    const double* cp[4];
+    const T* cp[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) cp[i] = Bm + (int64_t)gcol(16 * i + (l & 15)) * Np + 4 * (l >> 4);
-    jac_d4 acc[5];
-    if (grp == 0) jg_gram_part<0>(cp, Ns, q, acc);
-    else jg_gram_part<1>(cp, Ns, q, acc);
+    V4 acc[5];
+    if (grp == 0) jg_gram_part<T, 0>(cp, Ns, q, acc);
+    else jg_gram_part<T, 1>(cp, Ns, q, acc);
     // fixed-order sum over the row quarters: (q0 + q2) + (q1 + q3)
     auto put = [&](int sl) {
-      double* d = slot + sl * 1280;
+      T* d = slot + sl * 1280;
 #pragma unroll
       for (int u = 0; u < 5; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) d[u * 256 + v * 64 + l] = acc[u][v];
     };
     auto add = [&](int sl) {
-      const double* d = slot + sl * 1280;
+      const T* d = slot + sl * 1280;
 #pragma unroll
       for (int u = 0; u < 5; ++u)
 #pragma unroll
@@ -1231,7 +1257,7 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
         const int ta = jg_tile_a(grp, u), tb = jg_tile_b(grp, u);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = 16 * ta + (l >> 4) + 4 * v, j = 16 * tb + (l & 15);
+          const int i = 16 * ta + JgMma<T>::row(l, v), j = 16 * tb + (l & 15);
           G[i * P + j] = acc[u][v];
           if (ta != tb) G[j * P + i] = acc[u][v];
         }
@@ -1242,10 +1268,10 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
   __syncthreads();
   for (int e = t; e < P * P; e += JG_NT) {
     const int i = e / P, j = e % P;
-    Z[i * ZP + j] = (i == j) ? 1.0 : 0.0;
+    Z[i * ZP + j] = (i == j) ? T(1) : T(0);
     if (i < j && (full || (i < BW && j >= BW))) {
-      const double gij = G[e];
-      if (gij != 0.0 && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
+      const T gij = G[e];
+      if (gij != T(0) && gij * gij > tol * tol * (G[i * P + i] * G[j * P + j])) any_off = 1;
     }
   }
   __syncthreads();
@@ -1259,7 +1285,7 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
       if (t < NP2) {
         int p, q;
         jg_pair(true, st, t, &p, &q);
-        double c, sn;
+        T c, sn;
         if (jg_rot(G[p * P + p], G[q * P + q], G[p * P + q], tol, &c, &sn)) {
           ++nrot;
           step_any[st & 1] = 1;
@@ -1278,8 +1304,8 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
         const int ib = t & 31, r0 = t >> 5;
         int pb, qb, pa[2], qa[2];
         jg_pair(true, st, ib, &pb, &qb);
-        const double cb = rc[ib], sb = rsn[ib];
-        double ca[2], sa[2], g[2][4], zv[4][2];
+        const T cb = rc[ib], sb = rsn[ib];
+        T ca[2], sa[2], g[2][4], zv[4][2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int ia = r0 + 16 * k;
@@ -1332,12 +1358,12 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
     // the step's critical path.  Z: half-wave h = t/32 - 2 (0..13) owns rows
     // h + 14k (k < 5, rows < 64) in column t%32 and in its current partner.
     const int zib = t & 31, zh = (t >> 5) - 2;
-    double zp[5], zq[5];
+    T zp[5], zq[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const int iz = zh + 14 * k;
-      zp[k] = iz == zib ? 1.0 : 0.0;
-      zq[k] = iz == BW + zib ? 1.0 : 0.0;
+      zp[k] = iz == zib ? T(1) : T(0);
+      zq[k] = iz == BW + zib ? T(1) : T(0);
     }
     const int zsrc = (l & 32) | ((l + 1) & 31);  // lane holding the next step's column
     // storage of the block (a, b), a <= b: (a, b), (a, qb), (b, qa) [= (qa, b)], (min, max of qa, qb)
@@ -1370,7 +1396,7 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
     // block column of pair i + 1, so the new blocks consist of the lane's own
     // results, three results of lane i + 1, and one entry rotated by the owner
     // of the block (i, i + 2), read back from LDS.
-    double d0 = 0.0, d1 = 0.0, d3 = 0.0, e00 = 0.0, e01 = 0.0, e10 = 0.0, e11 = 0.0, ci = 1.0, si = 0.0;
+    T d0 = T(0), d1 = T(0), d3 = T(0), e00 = T(0), e01 = T(0), e10 = T(0), e11 = T(0), ci = T(1), si = T(0);
     if (t < NP2) {  // step 0 from the Gram (still complete)
       const int i = t, j = (i + 1) & (BW - 1), qi = BW + i, qj = BW + j;
       d0 = G[i * P + i];
@@ -1391,9 +1417,9 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
         const int i = t, j = (t + 1) & (BW - 1);
         const int qi = BW + ((i + st) & (BW - 1)), qj = BW + ((j + st) & (BW - 1));
         if (st > 0) e01 = G[i * P + qj];  // rotated last step by the owner of the block (i, i + 2)
-        const double cj = __shfl(ci, j), sj = __shfl(si, j);
-        double gd[4] = {d0, d1, d1, d3};
-        double ge[4] = {e00, e01, e10, e11};
+        const T cj = __shfl(ci, j), sj = __shfl(si, j);
+        T gd[4] = {d0, d1, d1, d3};
+        T ge[4] = {e00, e01, e10, e11};
         jg_rot_block(ci, si, ci, si, gd);
         jg_rot_block(ci, si, cj, sj, ge);
         G[i * P + i] = gd[0];
@@ -1423,17 +1449,17 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
           const int qa = BW + ((a + st) & (BW - 1)), qb = BW + ((b + st) & (BW - 1));
           int o[4];
           blk_off(a, b, qa, qb, o);
-          double g[4] = {G[o[0]], G[o[1]], G[o[2]], G[o[3]]};
+          T g[4] = {G[o[0]], G[o[1]], G[o[2]], G[o[3]]};
           jg_rot_block(hc[cur][a], hs[cur][a], hc[cur][b], hs[cur][b], g);
           G[o[0]] = g[0];
           G[o[1]] = g[1];
           G[o[2]] = g[2];
           G[o[3]] = g[3];
         }
-        const double cz = hc[cur][zib], sz = hs[cur][zib];
+        const T cz = hc[cur][zib], sz = hs[cur][zib];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-          const double x = zp[k], y = zq[k];
+          const T x = zp[k], y = zq[k];
           zp[k] = cz * x - sz * y;
           zq[k] = sz * x + cz * y;
         }
@@ -1471,13 +1497,13 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
   const int njobs = 2 * Ns;  // (matrix, 16-row block)
   for (int job = w; job < njobs; job += JG_NT / 64) {
     const int64_t rofs = (job < Ns ? job : job - Ns) * 16 + (l & 15);
-    double* X = (job < Ns ? Bm : Vm) + rofs;
-    jac_d4 acc[4];
+    T* X = (job < Ns ? Bm : Vm) + rofs;
+    V4 acc[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = jac_d4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 4; ++c) acc[c] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int half = 0; half < 2; ++half) {  // k in two halves of 32 panel columns
-      double xb[8];
+      T xb[8];
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) xb[kk] = X[co[8 * half + kk]];
 #pragma unroll
@@ -1485,15 +1511,15 @@ __global__ __launch_bounds__(JG_NT, 4) void jacobi_g_kernel(const Rec* __restric
         const int k = 4 * (8 * half + kk) + (l >> 4);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const double za = Z[k * ZP + 16 * c + (l & 15)];
-          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(za, xb[kk], acc[c], 0, 0, 0);
+          const T za = Z[k * ZP + 16 * c + (l & 15)];
+          acc[c] = JgMma<T>::mma(za, xb[kk], acc[c]);
         }
       }
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[(int64_t)gcol(16 * c + (l >> 4) + 4 * v) * Np] = acc[c][v];
+      for (int v = 0; v < 4; ++v) X[(int64_t)gcol(16 * c + JgMma<T>::row(l, v)) * Np] = acc[c][v];
   }
   if (t == 0) atomicAdd(&cnt[sweep], nrt);
 }
@@ -1723,8 +1749,10 @@ __global__ __launch_bounds__(JS_NT, 3) void jacobi_s_kernel(const Rec* __restric
 int jacobi_block_fits(int N, int elem_bytes, int cfg) {
   const int bw = cfg & 0xff;
   if (cfg & JAC_STREAMED) {
-    // streamed panels: FP64, 16- or 32-column blocks, at least four blocks
-    if ((cfg & ~(JAC_STREAMED | 0xff)) || elem_bytes != 8 || (bw != 16 && bw != 32)) return 0;
+    // streamed panels: 32-column blocks in FP64 or FP32, 16-column blocks in FP64;
+    // at least four blocks
+    if ((cfg & ~(JAC_STREAMED | 0xff)) || (bw != 16 && bw != 32)) return 0;
+    if (!(elem_bytes == 8 || (elem_bytes == 4 && bw == 32))) return 0;
     const int Np = ((N + 2 * bw - 1) / (2 * bw)) * (2 * bw);
     return Np / bw >= 4 ? Np : 0;
   }
@@ -1775,18 +1803,19 @@ static hipError_t jac_launch(const Rec* recs, int nrec, const JacArgs& a, int sw
 template <typename T>
 hipError_t jacobi_round(const Rec* recs, int nrec, const JacArgs& a, int sweep, int round, hipStream_t s) {
   if (a.b & JAC_STREAMED) {
-    if (sizeof(T) != 8) return hipErrorInvalidValue;
-    if ((a.b & 0xff) == JS_BW) {
+    if ((a.b & 0xff) == JS_BW) {  // 32-column panels: FP64 only
+      if (sizeof(T) != 8) return hipErrorInvalidValue;
       hipLaunchKernelGGL(jacobi_s_kernel, dim3(a.Np / JS_BW / 2, nrec), dim3(JS_NT), 0, s, recs, a, sweep, round);
       return hipGetLastError();
     }
     static bool attr = false;
-    const size_t lds = JG_LDS;
+    const size_t lds = JG_LDS<T>;
     if (!attr) {
-      (void)hipFuncSetAttribute((const void*)jacobi_g_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute((const void*)jacobi_g_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
       attr = true;
     }
-    hipLaunchKernelGGL(jacobi_g_kernel, dim3(a.Np / JG_BW / 2, nrec), dim3(JG_NT), lds, s, recs, a, sweep, round);
+    hipLaunchKernelGGL(jacobi_g_kernel<T>, dim3(a.Np / JG_BW / 2, nrec), dim3(JG_NT), lds, s, recs, a, sweep, round);
     return hipGetLastError();
   }
   switch (a.b) {

@@ -380,6 +380,39 @@ def test_fp64_streamed_panel_eigensolver(kfb, d, r, n, steps, bw):
         kfb.tune_set_jacobi(kfb.KFB_FP64, N, 0)
 
 
+@pytest.mark.parametrize("d,r,n,steps", [(400, 96, 96, 5), (1024, 256, 256, 4), (700, 200, 150, 4)])
+def test_fp32_streamed_panel_eigensolver(kfb, d, r, n, steps):
+    # the FP32 form's core through the 32-column streamed-panel eigensolver on FP32
+    # MFMA (main iteration, and the new-direction block's when n admits it), vs the
+    # dense definition on the same FP32-rounded batches
+    import torch
+    N = r + n
+    cfg = kfb.KFB_JAC_STREAMED | 32
+    kfb.tune_set_jacobi(kfb.KFB_FP32, N, cfg)
+    if n >= 128:
+        kfb.tune_set_jacobi(kfb.KFB_FP32, n, cfg)
+    try:
+        _announce(f"fp32 streamed-panel Jacobi d={d} r={r} n={n} N={N}")
+        rho = 0.95
+        f = kfb.Factor(d, r, n, rho, kfb.KFB_FP32)
+        o = oracle.DenseFactor(d, r, rho)
+        for k in range(steps):
+            M = _batch(12, k, "A" if k % 2 else "G", n, d)
+            Mf = M.astype(np.float32).astype(np.float64)
+            f.update(_to_dev(Mf, torch.float32))
+            o.update(Mf.T)
+            U, D = _front_np(f)
+            V, lamv = o.modes()
+            er, ed, eo = oracle.e_rec_dense(U, D, o.X), oracle.e_D(D, lamv), oracle.e_orth(U, D, rel_floor=1e-6)
+            _announce(f"  step {k} e_rec {er:.3e} e_D {ed:.3e} orth {eo:.2e}")
+            assert er <= TOL[1] and ed <= TOL[1] and eo <= 1e-4
+        assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
+    finally:
+        kfb.tune_set_jacobi(kfb.KFB_FP32, N, 0)
+        if n >= 128:
+            kfb.tune_set_jacobi(kfb.KFB_FP32, n, 0)
+
+
 @pytest.mark.parametrize("bw", [16, 32])
 def test_mixed_streamed_panel_headline_core(kfb, bw):
     # the headline shape's core (N = 512) through the streamed-panel eigensolvers, vs Oracle-B
