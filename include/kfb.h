@@ -352,14 +352,23 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream);
  *                            BF16-mixed forms) or FP32 MFMA (the FP32 form);
  *   KFB_JAC_STREAMED | 16     16-column blocks, panels read from global
  *                            memory (FP64 core only);
+ *   KFB_JAC_STREAMED | KFB_JAC_REFINE | 32
+ *                            BF16-mixed form only: the iteration on FP32
+ *                            copies of the core (FP32 MFMA), then one FP64
+ *                            refinement step of the eigenpairs of the FP64
+ *                            core (Ogita-Aishima iterative refinement on FP64
+ *                            MFMA), which leaves eigenvalues and vectors of
+ *                            FP64 accuracy outside clusters of near-equal
+ *                            eigenvalues;
  * streamed configurations need at least four blocks.
  * Inadmissible values give KFB_EINVAL.  bw = 0 removes the entry, restoring
- * the built-in choice: KFB_JAC_STREAMED | 32 for N >= 256 (and for the
- * new-direction block solve of an update), else the widest LDS block that
- * fits.  Affects calls made after it returns; results of a given table are
+ * the built-in choice: KFB_JAC_STREAMED | 32 for N >= 256 (with
+ * KFB_JAC_REFINE in the BF16-mixed form; also for the new-direction block
+ * solve of an update), else the widest LDS block that fits.  Affects calls made after it returns; results of a given table are
  * deterministic.  kfb_tune_get_jacobi reports the configuration and padded
  * size a core of size N would use. */
 #define KFB_JAC_STREAMED 0x100
+#define KFB_JAC_REFINE 0x200
 int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw);
 int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np);
 

@@ -114,12 +114,13 @@ int tuned_bw(int prec, int N) {
 // Eigensolver configuration for a core of size N (element size es): the tuning
 // table's entry, else, where streamed panels are preferred (cores of N >= 256;
 // the new-direction block solve always), 64-column panels streamed from global
-// memory (the autotuner's pick at the headline core in FP64 and FP32), else the
-// widest LDS panel.  Writes the padded size; returns 0 if nothing fits.
-int pick_jacobi(int prec, int N, int es, bool prefer_streamed, int* Np) {
+// memory (the autotuner's pick at the headline core; in the mixed form the
+// iteration in FP32 with the FP64 refinement, JAC_REFINE, where `refine`), else
+// the widest LDS panel.  Writes the padded size; returns 0 if nothing fits.
+int pick_jacobi(int prec, int N, int es, bool prefer_streamed, int* Np, bool refine = false) {
   int cfg = tuned_bw(prec, N);
-  if (!cfg && prefer_streamed) cfg = JAC_STREAMED | 32;
-  const int np = cfg ? jacobi_block_fits(N, es, cfg) : 0;
+  if (!cfg && prefer_streamed) cfg = JAC_STREAMED | 32 | (refine && prec == KFB_BF16_MIXED ? JAC_REFINE : 0);
+  const int np = cfg ? jacobi_block_fits(N, es, cfg & ~JAC_REFINE) : 0;
   if (np) {
     *Np = np;
     return cfg;
@@ -163,6 +164,10 @@ struct UpdPlan {
   int r, n, N, Np, bw;
   int ksP, ksG;
   int64_t oZ, oZb, oP, oP2, oGram, oR1, oX1, oR2, oX2, oR3, oRt, oPart, oB, oV, oW, oLam, oRank, oCnt;
+  // refine (mixed form, JAC_REFINE): FP32 copies of the core and its rotations,
+  // and the FP64 core K, S = X^T K X, G = X^T X (then E) of the refinement
+  bool refine = false;
+  int64_t oB32 = -1, oV32 = -1, oK = -1, oS = -1, oG = -1, oDelta = -1;
   // pre-rotation of the new-direction block: eigensolve of size n first (pre)
   bool pre = false;
   int preNp = 0, prebw = 0;
@@ -186,7 +191,11 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   // the CholeskyQR kernels and the eigensolver's finalize bound the widths
   if (n < 1 || r < 0 || n > MAX_QR_COLS || r + n > MAX_CORE) return false;
   p->d = d; p->ldu = ldu; p->ldm = ldm; p->r = r; p->n = n; p->N = r + n;
-  p->bw = pick_jacobi(PR, p->N, (int)sizeof(typename T::Core), p->N >= 256, &p->Np);
+  {
+    const int cfg = pick_jacobi(PR, p->N, (int)sizeof(typename T::Core), p->N >= 256, &p->Np, true);
+    p->refine = (cfg & JAC_REFINE) != 0;
+    p->bw = cfg & ~JAC_REFINE;
+  }
   if (p->bw == 0) return false;
   auto ks_for = [&](int m, int nn, int64_t k) {
     // split depends on the problem's own shape only, never on its batch-mates
@@ -220,8 +229,16 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   p->oCnt = take((size_t)MAX_SWEEPS * 4);
   p->pre = r > 0 && n >= PRE_MIN_N;
   if (p->pre) {
-    p->prebw = pick_jacobi(PR, n, (int)sizeof(typename T::Core), true, &p->preNp);
-    if (p->prebw == 0) p->pre = false;
+    p->prebw = pick_jacobi(PR, n, (int)sizeof(typename T::Core), true, &p->preNp) & ~JAC_REFINE;
+    // the FP32 iteration runs its block solve on the FP32 streamed kernel as well
+    if (p->refine) p->prebw = JAC_STREAMED | 32, p->preNp = jacobi_block_fits(n, 4, JAC_STREAMED | 32);
+    if (p->prebw == 0 || p->preNp == 0) p->pre = false;
+  }
+  if (p->refine) {
+    const size_t c32 = (size_t)p->Np * p->Np * 4, k64 = (size_t)p->N * p->N * 8;
+    p->oB32 = take(c32); p->oV32 = take(c32);
+    p->oK = take(k64); p->oS = take(k64); p->oG = take(k64);
+    p->oDelta = take(8);
   }
   if (p->pre) {
     const size_t pc = (size_t)p->preNp * p->preNp * sizeof(typename T::Core);
@@ -387,6 +404,97 @@ int core_evd(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s, bool f
   return KFB_OK;
 }
 
+// Core eigensolve of the mixed form with JAC_REFINE: the one-sided Jacobi
+// iteration (new-direction block, then the main one) runs on FP32 copies of the
+// core on FP32 MFMA; its rotations X then start one FP64 refinement step of the
+// eigenpairs of the FP64 core K = L L^T (Ogita-Aishima: K X, X^T K X and X^T X
+// on FP64 MFMA), so the eigenvalues and W carry FP64 accuracy outside clusters
+// of near-equal eigenvalues.  `co` describes the core (without pre-rotation).
+template <int PR>
+int core_evd_refined(const Rec* drecs, int nrec, const UpdPlan& p, const CoreArgs& co, hipStream_t s) {
+  if constexpr (PR != KFB_BF16_MIXED) {
+    return KFB_EINVAL;
+  } else {
+    typedef Ty<PR> T;
+    typedef typename T::P TP; typedef typename T::G TG; typedef typename T::D TD; typedef typename T::W TW;
+    const int N = p.N, n = p.n, Np = p.Np;
+    {
+      // K = L L^T in FP64: the Gram of the columns of B = L^T
+      StageTimer st("core", s, 2);
+      CoreArgs c64 = co;
+      KFB_TRY((assemble_core<double, TP, TG, TD>(drecs, nrec, c64, s)));
+      GemmArgs gk;
+      gk.A = op(WS, p.oB, Np, 1); gk.B = op(WS, p.oB, 1, Np); gk.C = op(WS, p.oK, 1, N);
+      gk.m = N; gk.n = N; gk.k = Np;
+      KFB_TRY(gemm_f64_mfma(drecs, nrec, gk, s));
+    }
+    const double eps32 = 1.1920929e-07;
+    auto iterate = [&](int Nc, int Npc, int bw, int64_t oB, int64_t oV, int64_t oCnt, int sweeps,
+                       const char* stage) -> int {
+      JacArgs ja;
+      ja.Np = Npc; ja.N = Nc; ja.b = bw; ja.max_sweeps = sweeps;
+      ja.off_B = oB; ja.off_V = oV; ja.off_cnt = oCnt;
+      ja.tol = eps32 * sqrt((double)Nc);
+      const int nb = Npc / (bw & 0xff);
+      StageTimer st(stage, s, sweeps * (nb - 1));
+      for (int sw = 0; sw < sweeps; ++sw)
+        for (int rd = 0; rd < nb - 1; ++rd) KFB_TRY(jacobi_round<float>(drecs, nrec, ja, sw, rd, s));
+      return KFB_OK;
+    };
+    CoreArgs c32 = co;
+    c32.off_B = p.oB32; c32.off_V = p.oV32;
+    if (p.pre) {
+      // block solve of sqrt(w) R^T in FP32 (the pre-rotation buffers hold FP32 here)
+      CoreArgs cr;
+      cr.r = 0; cr.n = n; cr.N = n; cr.Np = p.preNp; cr.off_P = p.oP; cr.off_P2 = -1;
+      cr.off_R = co.off_R; cr.off_B = p.oPB; cr.off_V = p.oPV;
+      {
+        StageTimer st("core", s, 2);
+        KFB_TRY((assemble_core<float, TP, TG, TD>(drecs, nrec, cr, s)));
+        KFB_TRY(zero_words(drecs, nrec, WS, p.oPCnt, MAX_SWEEPS, s));
+      }
+      const int rc = iterate(n, p.preNp, p.prebw, p.oPB, p.oPV, p.oPCnt, PRE_SWEEPS, "jacobi_pre");
+      if (rc != KFB_OK) return rc;
+      c32.off_preB = p.oPB; c32.off_preV = p.oPV; c32.preNp = p.preNp;
+    }
+    {
+      StageTimer st("core", s, 2);
+      KFB_TRY((assemble_core<float, TP, TG, TD>(drecs, nrec, c32, s)));
+      KFB_TRY(zero_words(drecs, nrec, WS, p.oCnt, MAX_SWEEPS, s));
+    }
+    {
+      const int rc = iterate(N, Np, p.bw, p.oB32, p.oV32, p.oCnt, MAX_SWEEPS, "jacobi");
+      if (rc != KFB_OK) return rc;
+    }
+    {
+      // X = V (FP64, N x N at oV); T = K X (over B); S = X^T T; G = X^T X; E; X' = X + X E (over B)
+      StageTimer st("refine", s, 8);
+      KFB_TRY((copy2d<double, float>(drecs, nrec, op(WS, p.oV, 1, N), op(WS, p.oV32, 1, Np), N, N, s)));
+      GemmArgs g;
+      g.m = N; g.n = N; g.k = N;
+      g.A = op(WS, p.oK, 1, N); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oB, 1, N);
+      KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
+      g.A = op(WS, p.oV, N, 1); g.B = op(WS, p.oB, 1, N); g.C = op(WS, p.oS, 1, N);
+      KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
+      g.A = op(WS, p.oV, N, 1); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oG, 1, N);
+      KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
+      OaArgs oa;
+      oa.N = N; oa.off_K = p.oK; oa.off_S = p.oS; oa.off_G = p.oG; oa.off_lam = p.oLam; oa.off_delta = p.oDelta;
+      KFB_TRY(oa_prepare(drecs, nrec, oa, s));
+      KFB_TRY(oa_correct(drecs, nrec, oa, s));
+      g.A = op(WS, p.oV, 1, N); g.B = op(WS, p.oG, 1, N); g.C = op(WS, p.oB, 1, N);
+      g.C0 = op(WS, p.oV, 1, N); g.beta = 1.0;
+      KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
+    }
+    FinArgs fa;
+    fa.N = N; fa.Np = N; fa.max_sweeps = MAX_SWEEPS; fa.off_B = p.oB; fa.off_V = p.oB;
+    fa.off_cnt = p.oCnt; fa.off_lam = p.oLam; fa.off_rank = p.oRank; fa.off_W = p.oW;
+    StageTimer st_fin("finalize", s, 2);
+    KFB_TRY((finalize_sorted<TW, TD>(drecs, nrec, fa, s)));
+    return KFB_OK;
+  }
+}
+
 template <int PR>
 int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   typedef Ty<PR> T;
@@ -434,6 +542,10 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   CoreArgs co;
   co.r = r; co.n = n; co.N = N; co.Np = p.Np; co.off_P = p.oP; co.off_P2 = r > 0 ? p.oP2 : -1;
   co.off_R = oRfin; co.off_B = p.oB; co.off_V = p.oV;
+  if (p.refine) {
+    const int rc = core_evd_refined<PR>(drecs, nrec, p, co, s);
+    if (rc != KFB_OK) return rc;
+  } else {
   if (p.pre) {
     // eigensolve of the new-direction block sqrt(w) R^T (same arithmetic, size n)
     UpdPlan pp = p;
@@ -458,6 +570,7 @@ int run_update(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s) {
   {
     const int rc = core_evd<PR>(drecs, nrec, p, s);
     if (rc != KFB_OK) return rc;
+  }
   }
   // rotation: U' = [U_r Q] W  (Algorithm 3), into the back buffer
   GemmArgs ro;
@@ -1681,7 +1794,10 @@ int kfb_state_status(kfb_state_t st, uint32_t* events, kfb_stream_t stream) {
 int kfb_tune_set_jacobi(int32_t prec, int32_t N, int32_t bw) {
   if (prec < KFB_FP64 || prec > KFB_BF16_MIXED || N <= 0) return KFB_EINVAL;
   const int eb = prec == KFB_FP32 ? 4 : 8;
-  if (bw != 0 && jacobi_block_fits(N, eb, bw) == 0) return KFB_EINVAL;
+  if (bw & JAC_REFINE) {  // mixed form, 32-column streamed panels only
+    if (prec != KFB_BF16_MIXED || (bw & ~JAC_REFINE) != (JAC_STREAMED | 32)) return KFB_EINVAL;
+  }
+  if (bw != 0 && jacobi_block_fits(N, eb, bw & ~JAC_REFINE) == 0) return KFB_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (size_t i = 0; i < g_tune.size(); ++i)
     if (g_tune[i].prec == prec && g_tune[i].N == N) {
@@ -1697,7 +1813,7 @@ int kfb_tune_get_jacobi(int32_t prec, int32_t N, int32_t* bw, int32_t* Np) {
   if (prec < KFB_FP64 || prec > KFB_BF16_MIXED || N <= 0) return KFB_EINVAL;
   const int eb = prec == KFB_FP32 ? 4 : 8;
   int np = 0;
-  const int b = pick_jacobi(prec, N, eb, N >= 256, &np);
+  const int b = pick_jacobi(prec, N, eb, N >= 256, &np, true);  // as a Brand update's main solve
   if (bw) *bw = b;
   if (Np) *Np = np;
   return b ? KFB_OK : KFB_EINVAL;

@@ -906,6 +906,121 @@ hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g0, hipStrea
 template hipError_t gemm_f32_mfma<double, float>(const Rec*, int, const GemmArgs&, hipStream_t);
 template hipError_t gemm_f32_mfma<float, float>(const Rec*, int, const GemmArgs&, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// FP64 products on FP64 MFMA (v_mfma_f64_16x16x4f64): the small square
+// products of the eigenpair refinement (Ogita-Aishima step) that follows the
+// mixed form's FP32 core eigensolve.  C = alpha A B + beta C0, all FP64, plain
+// operands.  64 x 64 tiles of four waves (32 x 32 each), k in steps of 16
+// staged in LDS (k-major rows), the next step's operands loaded while the
+// current one is multiplied; each operand read along its contiguous dimension;
+// XCD-aware tile order.  Result v of a lane of the FP64 instruction is row
+// lane / 16 + 4 v, column lane % 16: a column-major C takes the transposed issue
+// (B^T A^T) so that 16 consecutive lanes store 16 consecutive rows.
+// ---------------------------------------------------------------------------
+constexpr int D64_BM = 64, D64_BK = 16, D64_LD = 64 + 2;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+
+template <bool SWP>
+__global__ __launch_bounds__(256) void gemm_f64_mfma_kernel(const Rec* __restrict__ recs, GemmArgs g) {
+  __shared__ double sA[2][D64_BK][D64_LD];
+  __shared__ double sB[2][D64_BK][D64_LD];
+  int tm, tn, tz;
+  xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
+  const Rec& rec = recs[tz];
+  const double* A = at<const double>(rec, g.A.slot, g.A.off);
+  const double* B = at<const double>(rec, g.B.slot, g.B.off);
+  const bool a_k = g.A.cs == 1 && g.A.rs != 1, b_j = g.B.cs == 1 && g.B.rs != 1;
+  const int t = threadIdx.x, w = t / 64, l = t % 64;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int m0 = tm * D64_BM, n0 = tn * D64_BM;
+  // staging: element e = t + 256 q (q < 4) of the 64 x 16 A tile is (i, k) =
+  // (e % 64, e / 64), or (e / 16, e % 16) along k; of the 16 x 64 B tile (k, j) =
+  // (e % 16, e / 16), or (e / 64, e % 64) along j
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      const int ia = a_k ? e / D64_BK : e % D64_BM, ka = a_k ? e % D64_BK : e / D64_BM;
+      const int gi = m0 + ia, gk = k0 + ka;
+      ra[q] = (gi < g.m && gk < g.k) ? A[(int64_t)gi * g.A.rs + (int64_t)gk * g.A.cs] : 0.0;
+      const int kb = b_j ? e / D64_BM : e % D64_BK, jb = b_j ? e % D64_BM : e / D64_BK;
+      const int gj = n0 + jb, gkb = k0 + kb;
+      rb[q] = (gj < g.n && gkb < g.k) ? B[(int64_t)gkb * g.B.rs + (int64_t)gj * g.B.cs] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      if (a_k) sA[buf][e % D64_BK][e / D64_BK] = ra[q];
+      else sA[buf][e / D64_BM][e % D64_BM] = ra[q];
+      if (b_j) sB[buf][e / D64_BM][e % D64_BM] = rb[q];
+      else sB[buf][e % D64_BK][e / D64_BK] = rb[q];
+    }
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = 0; k0 < g.k; k0 += D64_BK) {
+    const bool more = k0 + D64_BK < g.k;
+    if (more) load(k0 + D64_BK);
+#pragma unroll
+    for (int ks = 0; ks < D64_BK / 4; ++ks) {
+      const int kr = 4 * ks + l / 16;
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        af[i] = sA[cur][kr][wm + 16 * i + (l % 16)];
+        bf[i] = sB[cur][kr][wn + 16 * i + (l % 16)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = SWP ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0)
+                          : __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  double* C = at<double>(rec, g.C.slot, g.C.off);
+  const bool use_c0 = g.C0.slot >= 0 && g.beta != 0.0;
+  const double* C0 = use_c0 ? at<const double>(rec, g.C0.slot, g.C0.off) : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi, gj;
+        if (SWP) { gi = m0 + wm + 16 * i + (l % 16); gj = n0 + wn + 16 * j + (l / 16) + 4 * v; }
+        else { gi = m0 + wm + 16 * i + (l / 16) + 4 * v; gj = n0 + wn + 16 * j + (l % 16); }
+        if (gi < g.m && gj < g.n) {
+          double val = g.alpha * acc[i][j][v];
+          if (C0) val += g.beta * C0[(int64_t)gi * g.C0.rs + (int64_t)gj * g.C0.cs];
+          C[(int64_t)gi * g.C.rs + (int64_t)gj * g.C.cs] = val;
+        }
+      }
+}
+
+hipError_t gemm_f64_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0 || nrec <= 0) return hipSuccess;
+  if (g.A.slot2 >= 0 || g.B.slot2 >= 0 || g.ksplit > 1 || g.beta_slot >= 0 || g.k < 0)
+    return hipErrorInvalidValue;
+  dim3 grid((g.m + D64_BM - 1) / D64_BM, (g.n + D64_BM - 1) / D64_BM, nrec);
+  if (g.C.rs == 1) hipLaunchKernelGGL((gemm_f64_mfma_kernel<true>), grid, dim3(256), 0, s, recs, g);
+  else hipLaunchKernelGGL((gemm_f64_mfma_kernel<false>), grid, dim3(256), 0, s, recs, g);
+  return hipGetLastError();
+}
+
 #define KFB_GEMM_BF16(TA, TB, TC, TC0, SP) \
   template hipError_t gemm_bf16<TA, TB, TC, TC0, SP>(const Rec*, int, const GemmArgs&, hipStream_t);
 // mixed-form update: projections (U FP32 split, M BF16 exact), residuals, rotation

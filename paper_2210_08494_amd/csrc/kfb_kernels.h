@@ -29,9 +29,11 @@ int gemm_tile_lookup(int m, int n, int k);
 int gemm_tile_set(int m, int n, int k, int tile);
 
 // FP32 MFMA variant for FP32 products (A FP32, B FP32 or FP64 rounded to FP32,
-// C FP32; plain operands, no split-K).
+// C FP32; two-segment operands and split-K as the FMA engine).
 template <typename TB, typename TC0>
 hipError_t gemm_f32_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
+// FP64 products on FP64 MFMA (plain operands, no split-K): C = alpha A B + beta C0
+hipError_t gemm_f64_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s);
 
 // ---- small helpers ---------------------------------------------------------
 hipError_t upload_recs(const Rec* host, int nrec, Rec* dev, hipStream_t s);
@@ -105,6 +107,9 @@ int jacobi_pick_block(int N, int elem_bytes, int* Np);
 // that holds the panel in LDS, or JAC_STREAMED | width (32: FP64 or FP32;
 // 16: FP64 only) for the kernels that read the panel from global memory.
 constexpr int JAC_STREAMED = 0x100;
+// mixed form with JAC_STREAMED | 32: the iteration runs in FP32 on FP32 MFMA and
+// the eigenpairs are refined in FP64 (one Ogita-Aishima step on FP64 MFMA)
+constexpr int JAC_REFINE = 0x200;
 // padded size for a configuration, or 0 if it is not admissible for N
 int jacobi_block_fits(int N, int elem_bytes, int cfg);
 
@@ -115,6 +120,22 @@ struct FinArgs {
 };
 template <typename TCore, typename TW, typename TD>
 hipError_t finalize_core(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s);
+// finalize from eigenvalues in lam[0, N) and eigenvector columns at off_V (N x N,
+// scales lam[N + j]); requires Np == N
+template <typename TW, typename TD>
+hipError_t finalize_sorted(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s);
+
+// Eigenpair refinement (one Ogita-Aishima step) of the FP64 core K (N x N) from
+// approximate eigenvectors X: with S = X^T K X and G = X^T X already formed,
+// oa_prepare writes the eigenvalue estimates into lam[0, N) (scales lam[N + j]
+// = 1) and the cluster threshold delta; oa_correct overwrites G with the
+// correction E, after which X' = X + X E.
+struct OaArgs {
+  int N;
+  int64_t off_K, off_S, off_G, off_lam, off_delta;
+};
+hipError_t oa_prepare(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s);
+hipError_t oa_correct(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s);
 
 // ---- preconditioner helpers -------------------------------------------------
 // Per side: c_i = 1/(D_i + lam) - 1/lam for the modes used, stored as

@@ -1873,7 +1873,8 @@ __global__ __launch_bounds__(256) void fin_sort_kernel(const Rec* __restrict__ r
   int32_t* rank = at<int32_t>(rec, WS, a.off_rank);
   TD* Dout = at<TD>(rec, D_BACK, 0);
   __shared__ TCore sl[FIN_MAXN];
-  for (int j = threadIdx.x; j < N; j += 256) sl[j] = lam[j];
+  // the core is PSD: an estimate a rounding error below zero is taken as zero
+  for (int j = threadIdx.x; j < N; j += 256) sl[j] = lam[j] > TCore(0) ? lam[j] : TCore(0);
   __syncthreads();  // every estimate is read before the sorted ones overwrite them
   for (int j = threadIdx.x; j < N; j += 256) {
     const TCore v = sl[j];
@@ -2218,6 +2219,107 @@ template hipError_t sqrt_prefix<double>(const Rec*, int, int, int64_t, int, hipS
 template hipError_t sqrt_prefix<float>(const Rec*, int, int, int64_t, int, hipStream_t);
 template hipError_t chol_inv<double>(const Rec*, int, const CholArgs&, hipStream_t);
 template hipError_t chol_inv<float>(const Rec*, int, const CholArgs&, hipStream_t);
+// ---------------------------------------------------------------------------
+// Eigenpair refinement of the FP64 core K from approximate eigenvectors X (the
+// FP32 eigensolve's), one step of Ogita and Aishima's iterative refinement for
+// the symmetric eigenvalue problem.  With S = X^T K X and G = X^T X (R = I - G),
+// to first order X' = X (I + E) is orthonormal and diagonalises K when
+//   E + E^T = R  and  S + E^T diag(lam) + diag(lam) E = diag(lam),
+// giving lam_i = S_ii / G_ii and, for pairs whose estimates are separated by
+// more than delta = 2 (||S - diag(lam)|| + ||K|| ||R||) (Frobenius norms, bounds
+// of the spectral ones), E_ij = (S_ij + lam_j R_ij) / (lam_j - lam_i); closer
+// pairs (and the diagonal) take E_ij = R_ij / 2, which restores orthonormality
+// only.  The error of X drops from e to O(e^2) outside such clusters.
+// ---------------------------------------------------------------------------
+// one workgroup per problem: lam (into the finalize step's eigenvalue slots, the
+// eigenvector scales at lam + N set to 1) and delta, by fixed-order reductions
+__global__ __launch_bounds__(256) void oa_prepare_kernel(const Rec* __restrict__ recs, OaArgs a) {
+  const Rec& rec = recs[blockIdx.x];
+  const int N = a.N;
+  const double* K = at<const double>(rec, WS, a.off_K);
+  const double* S = at<const double>(rec, WS, a.off_S);
+  const double* G = at<const double>(rec, WS, a.off_G);
+  double* lam = at<double>(rec, WS, a.off_lam);
+  __shared__ double red[3][256];
+  const int t = threadIdx.x;
+  for (int i = t; i < N; i += 256) {
+    const int64_t dii = i + (int64_t)i * N;
+    lam[i] = G[dii] > 0.0 ? S[dii] / G[dii] : 0.0;
+    lam[N + i] = 1.0;
+  }
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const int64_t nn = (int64_t)N * N;
+  for (int64_t e = t; e < nn; e += 256) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    const double sij = S[e], kij = K[e], gij = G[e];
+    const double off = i == j ? sij - (gij > 0.0 ? sij / gij : 0.0) : sij;
+    const double rij = (i == j ? 1.0 : 0.0) - gij;
+    s0 += off * off;
+    s1 += kij * kij;
+    s2 += rij * rij;
+  }
+  red[0][t] = s0;
+  red[1][t] = s1;
+  red[2][t] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + h];
+    __syncthreads();
+  }
+  if (t == 0) *at<double>(rec, WS, a.off_delta) = 2.0 * (sqrt(red[0][0]) + sqrt(red[1][0]) * sqrt(red[2][0]));
+}
+
+// E over G, element by element (each thread reads and writes its own entries)
+__global__ __launch_bounds__(256) void oa_correct_kernel(const Rec* __restrict__ recs, OaArgs a) {
+  const Rec& rec = recs[blockIdx.y];
+  const int N = a.N;
+  const double* S = at<const double>(rec, WS, a.off_S);
+  double* G = at<double>(rec, WS, a.off_G);
+  const double* lam = at<const double>(rec, WS, a.off_lam);
+  const double dl = *at<const double>(rec, WS, a.off_delta);
+  const int64_t nn = (int64_t)N * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    const double rij = (i == j ? 1.0 : 0.0) - G[e];
+    const double gap = lam[j] - lam[i];
+    G[e] = fabs(gap) > dl ? (S[e] + lam[j] * rij) / gap : 0.5 * rij;
+  }
+}
+
+hipError_t oa_prepare(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s) {
+  if (a.N > FIN_MAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(oa_prepare_kernel, dim3(nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+hipError_t oa_correct(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s) {
+  const int64_t nn = (int64_t)a.N * a.N;
+  int blocks = (int)((nn + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(oa_correct_kernel, dim3(blocks, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+
+// finalize from eigenvalue estimates already in lam[0, N) and eigenvectors in
+// the columns of the N x N matrix at off_V (column scales lam[N + j]): ranks,
+// D descending, W permuted
+template <typename TW, typename TD>
+hipError_t finalize_sorted(const Rec* recs, int nrec, const FinArgs& a, hipStream_t s) {
+  if (a.N > FIN_MAXN || a.Np != a.N) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fin_sort_kernel<double, TD>), dim3(nrec), dim3(256), 0, s, recs, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = (int64_t)a.N * a.N;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((fin_gather_kernel<double, TW>), dim3(blocks, nrec), dim3(256), 0, s, recs, a);
+  return hipGetLastError();
+}
+template hipError_t finalize_sorted<float, double>(const Rec*, int, const FinArgs&, hipStream_t);
+template hipError_t finalize_sorted<double, double>(const Rec*, int, const FinArgs&, hipStream_t);
+template hipError_t assemble_core<float, float, double, double>(const Rec*, int, const CoreArgs&, hipStream_t);
+
 template hipError_t assemble_core<double, double, double, double>(const Rec*, int, const CoreArgs&, hipStream_t);
 template hipError_t assemble_core<float, float, float, float>(const Rec*, int, const CoreArgs&, hipStream_t);
 template hipError_t assemble_core<double, float, double, double>(const Rec*, int, const CoreArgs&, hipStream_t);

@@ -17,6 +17,7 @@ KFB_FP64, KFB_FP32, KFB_BF16_MIXED = 0, 1, 2
 KFB_SPECTRUM_CONTINUATION, KFB_TRUNCATE_AFTER, KFB_RELATIVE_DAMPING = 1, 2, 4
 KFB_EV_NONFINITE, KFB_EV_CHOL_DEFICIENT, KFB_EV_JACOBI_MAXSWEEPS, KFB_EV_ORTHO_DRIFT = 1, 2, 4, 8
 KFB_JAC_STREAMED = 0x100
+KFB_JAC_REFINE = 0x200
 ERRORS = {0: "KFB_OK", 1: "KFB_EINVAL", 2: "KFB_EWORKSPACE", 3: "KFB_EHIP", 4: "KFB_ESTATE",
           5: "KFB_EEMPTY"}
 

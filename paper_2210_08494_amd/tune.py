@@ -16,11 +16,14 @@ import time
 from . import kfb
 
 
-DEFAULT_CANDIDATES = (4, 8, 16, 32, kfb.KFB_JAC_STREAMED | 16, kfb.KFB_JAC_STREAMED | 32)
+DEFAULT_CANDIDATES = (4, 8, 16, 32, kfb.KFB_JAC_STREAMED | 16, kfb.KFB_JAC_STREAMED | 32,
+                      kfb.KFB_JAC_STREAMED | kfb.KFB_JAC_REFINE | 32)
 
 
 def config_name(cfg: int) -> str:
-    return f"s{cfg & 0xff}" if cfg & kfb.KFB_JAC_STREAMED else str(cfg)
+    if cfg & kfb.KFB_JAC_STREAMED:
+        return f"s{cfg & 0xff}" + ("r" if cfg & kfb.KFB_JAC_REFINE else "")
+    return str(cfg)
 
 
 def tune_jacobi(prec: int, d: int, r: int, n: int, count: int = 8, reps: int = 3, device="cuda",

@@ -149,3 +149,22 @@ def test_gemm_tile_table(lib):
     assert lib.kfb_tune_get_gemm(512, 4096, 4096, ctypes.byref(t)) == 0 and t.value == 128
     for bad in ((0, 1, 1, 128), (1, 1, 1, 64), (1, -1, 1, 256)):
         assert lib.kfb_tune_set_gemm(*bad) == 1
+
+
+def test_jacobi_table_and_built_in_choice(lib):
+    # host-side eigensolver table: built-in choices per form and size, the streamed
+    # and refined configurations' admissibility, and removal
+    S, REF = 0x100, 0x200
+    bw, Np = ctypes.c_int32(), ctypes.c_int32()
+
+    def get(prec, N):
+        assert lib.kfb_tune_get_jacobi(prec, N, ctypes.byref(bw), ctypes.byref(Np)) == 0
+        return bw.value, Np.value
+    assert get(0, 512) == (S | 32, 512)          # FP64: streamed 32-column panels at N >= 256
+    assert get(1, 512) == (S | 32, 512)          # FP32: the same kernel on FP32 MFMA
+    assert get(2, 512) == (S | REF | 32, 512)    # mixed: FP32 iteration + FP64 refinement
+    assert get(2, 150)[0] & S == 0               # below 256: a panel held in LDS
+    assert lib.kfb_tune_set_jacobi(2, 512, S | 32) == 0 and get(2, 512) == (S | 32, 512)
+    assert lib.kfb_tune_set_jacobi(2, 512, 0) == 0 and get(2, 512) == (S | REF | 32, 512)
+    for prec, cfg in ((0, S | REF | 32), (1, S | REF | 32), (2, S | REF | 16), (2, REF | 32), (1, S | 16)):
+        assert lib.kfb_tune_set_jacobi(prec, 512, cfg) == 1, (prec, hex(cfg))

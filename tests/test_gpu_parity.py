@@ -413,9 +413,10 @@ def test_fp32_streamed_panel_eigensolver(kfb, d, r, n, steps):
             kfb.tune_set_jacobi(kfb.KFB_FP32, n, 0)
 
 
-@pytest.mark.parametrize("bw", [16, 32])
+@pytest.mark.parametrize("bw", [16, 32, 32 | 0x200])
 def test_mixed_streamed_panel_headline_core(kfb, bw):
-    # the headline shape's core (N = 512) through the streamed-panel eigensolvers, vs Oracle-B
+    # the headline shape's core (N = 512) through the streamed-panel eigensolvers (FP64
+    # iteration; or, with KFB_JAC_REFINE, the FP32 iteration and the FP64 refinement), vs Oracle-B
     import torch
     d, r, n, rho, steps = 4096, 256, 256, 0.95, 3
     kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, r + n, kfb.KFB_JAC_STREAMED | bw)
@@ -434,6 +435,45 @@ def test_mixed_streamed_panel_headline_core(kfb, bw):
         assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
     finally:
         kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, r + n, 0)
+
+
+@pytest.mark.parametrize("dup", [False, True])
+def test_mixed_refined_core_ragged_and_clustered(kfb, dup):
+    # the mixed form's FP32 iteration + FP64 refinement at a core whose size is no
+    # multiple of the panel (N = 350, new-direction block n = 150), and with every
+    # batch column duplicated (a cluster of 75 zero eigenvalues that the refinement
+    # only re-orthonormalises): vs Oracle-B, and vs the FP64 iteration on the same inputs
+    import torch
+    d, r, n, rho, steps = 700, 200, 150, 0.95, 4
+    N = r + n
+    res = {}
+    for cfg in (kfb.KFB_JAC_STREAMED | kfb.KFB_JAC_REFINE | 32, kfb.KFB_JAC_STREAMED | 32):
+        kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, N, cfg)
+        try:
+            _announce(f"mixed core cfg={cfg:#x} d={d} r={r} n={n} dup={dup}")
+            f = kfb.Factor(d, r, n, rho, kfb.KFB_BF16_MIXED)
+            o = oracle.BrandFactor(d, r, rho)
+            out = []
+            for k in range(steps):
+                M = _batch(14, k, "G", n, d, prec=2)
+                if dup:
+                    M = np.concatenate([M[: n // 2], M[: n // 2]], axis=0)
+                f.update(_to_dev(M, torch.bfloat16))
+                o.update(M.T)
+                U, D = _front_np(f)
+                e, eo = oracle.e_rec_lowrank(U, D, o.U, o.D), oracle.e_orth(U, D, rel_floor=1e-6)
+                _announce(f"  step {k} e_rec {e:.3e} orth {eo:.2e}")
+                assert e <= TOL[2] and eo <= 1e-3
+                out.append((U, D))
+            assert f.status() & kfb.KFB_EV_JACOBI_MAXSWEEPS == 0
+            res[cfg] = out
+        finally:
+            kfb.tune_set_jacobi(kfb.KFB_BF16_MIXED, N, 0)
+    a_, b_ = res.values()
+    for k, ((Ua, Da), (Ub, Db)) in enumerate(zip(a_, b_)):
+        e = oracle.e_rec_lowrank(Ua, Da, Ub, Db)
+        _announce(f"  step {k}: refined vs FP64 iteration {e:.3e}")
+        assert e <= 1e-4
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
