@@ -165,7 +165,7 @@ struct UpdPlan {
   int ksP, ksG;
   int64_t oZ, oZb, oP, oP2, oGram, oR1, oX1, oR2, oX2, oR3, oRt, oPart, oB, oV, oW, oLam, oRank, oCnt;
   // refine (mixed form, JAC_REFINE): FP32 copies of the core and its rotations,
-  // and the FP64 core K, S = X^T K X, G = X^T X (then E) of the refinement
+  // and Y = L^T X, S = X^T K X, G = X^T X (then E) of the FP64 refinement
   bool refine = false;
   int64_t oB32 = -1, oV32 = -1, oK = -1, oS = -1, oG = -1, oDelta = -1;
   // pre-rotation of the new-direction block: eigensolve of size n first (pre)
@@ -238,7 +238,7 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
     const size_t c32 = (size_t)p->Np * p->Np * 4, k64 = (size_t)p->N * p->N * 8;
     p->oB32 = take(c32); p->oV32 = take(c32);
     p->oK = take(k64); p->oS = take(k64); p->oG = take(k64);
-    p->oDelta = take(8);
+    p->oDelta = take(8 * (1 + 3 * 32));  // the refinement threshold's partial sums
   }
   if (p->pre) {
     const size_t pc = (size_t)p->preNp * p->preNp * sizeof(typename T::Core);
@@ -407,9 +407,10 @@ int core_evd(const Rec* drecs, int nrec, const UpdPlan& p, hipStream_t s, bool f
 // Core eigensolve of the mixed form with JAC_REFINE: the one-sided Jacobi
 // iteration (new-direction block, then the main one) runs on FP32 copies of the
 // core on FP32 MFMA; its rotations X then start one FP64 refinement step of the
-// eigenpairs of the FP64 core K = L L^T (Ogita-Aishima: K X, X^T K X and X^T X
-// on FP64 MFMA), so the eigenvalues and W carry FP64 accuracy outside clusters
-// of near-equal eigenvalues.  `co` describes the core (without pre-rotation).
+// eigenpairs of the FP64 core K = L L^T (Ogita-Aishima) on FP64 MFMA, with
+// X^T K X formed as Y^T Y from Y = L^T X, so the eigenvalues and W carry FP64
+// accuracy outside clusters of near-equal eigenvalues.  `co` describes the core
+// (without pre-rotation).
 template <int PR>
 int core_evd_refined(const Rec* drecs, int nrec, const UpdPlan& p, const CoreArgs& co, hipStream_t s) {
   if constexpr (PR != KFB_BF16_MIXED) {
@@ -419,14 +420,10 @@ int core_evd_refined(const Rec* drecs, int nrec, const UpdPlan& p, const CoreArg
     typedef typename T::P TP; typedef typename T::G TG; typedef typename T::D TD; typedef typename T::W TW;
     const int N = p.N, n = p.n, Np = p.Np;
     {
-      // K = L L^T in FP64: the Gram of the columns of B = L^T
-      StageTimer st("core", s, 2);
+      // B = L^T in FP64 (kept for the refinement)
+      StageTimer st("core", s, 1);
       CoreArgs c64 = co;
       KFB_TRY((assemble_core<double, TP, TG, TD>(drecs, nrec, c64, s)));
-      GemmArgs gk;
-      gk.A = op(WS, p.oB, Np, 1); gk.B = op(WS, p.oB, 1, Np); gk.C = op(WS, p.oK, 1, N);
-      gk.m = N; gk.n = N; gk.k = Np;
-      KFB_TRY(gemm_f64_mfma(drecs, nrec, gk, s));
     }
     const double eps32 = 1.1920929e-07;
     auto iterate = [&](int Nc, int Npc, int bw, int64_t oB, int64_t oV, int64_t oCnt, int sweeps,
@@ -467,19 +464,21 @@ int core_evd_refined(const Rec* drecs, int nrec, const UpdPlan& p, const CoreArg
       if (rc != KFB_OK) return rc;
     }
     {
-      // X = V (FP64, N x N at oV); T = K X (over B); S = X^T T; G = X^T X; E; X' = X + X E (over B)
-      StageTimer st("refine", s, 8);
+      // X = V (FP64, N x N at oV); Y = L^T X (the first N rows of B times X, at oK);
+      // S = Y^T Y = X^T K X; G = X^T X; E over G; X' = X + X E (over B).  ||K|| in
+      // the cluster threshold is taken as ||S|| (X is orthonormal to the FP32 level).
+      StageTimer st("refine", s, 7);
       KFB_TRY((copy2d<double, float>(drecs, nrec, op(WS, p.oV, 1, N), op(WS, p.oV32, 1, Np), N, N, s)));
       GemmArgs g;
       g.m = N; g.n = N; g.k = N;
-      g.A = op(WS, p.oK, 1, N); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oB, 1, N);
+      g.A = op(WS, p.oB, 1, Np); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oK, 1, N);
       KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
-      g.A = op(WS, p.oV, N, 1); g.B = op(WS, p.oB, 1, N); g.C = op(WS, p.oS, 1, N);
+      g.A = op(WS, p.oK, N, 1); g.B = op(WS, p.oK, 1, N); g.C = op(WS, p.oS, 1, N);
       KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
       g.A = op(WS, p.oV, N, 1); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oG, 1, N);
       KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
       OaArgs oa;
-      oa.N = N; oa.off_K = p.oK; oa.off_S = p.oS; oa.off_G = p.oG; oa.off_lam = p.oLam; oa.off_delta = p.oDelta;
+      oa.N = N; oa.off_K = p.oS; oa.off_S = p.oS; oa.off_G = p.oG; oa.off_lam = p.oLam; oa.off_delta = p.oDelta;
       KFB_TRY(oa_prepare(drecs, nrec, oa, s));
       KFB_TRY(oa_correct(drecs, nrec, oa, s));
       g.A = op(WS, p.oV, 1, N); g.B = op(WS, p.oG, 1, N); g.C = op(WS, p.oB, 1, N);

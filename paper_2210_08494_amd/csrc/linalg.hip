@@ -2231,25 +2231,34 @@ template hipError_t chol_inv<float>(const Rec*, int, const CholArgs&, hipStream_
 // pairs (and the diagonal) take E_ij = R_ij / 2, which restores orthonormality
 // only.  The error of X drops from e to O(e^2) outside such clusters.
 // ---------------------------------------------------------------------------
-// one workgroup per problem: lam (into the finalize step's eigenvalue slots, the
-// eigenvector scales at lam + N set to 1) and delta, by fixed-order reductions
+// OA_BLOCKS workgroups per problem, each over a contiguous range of the N^2
+// entries: the eigenvalue estimates of its diagonal entries (into the finalize
+// step's eigenvalue slots, the eigenvector scales at lam + N set to 1) and its
+// partial sums of ||S - diag(lam)||^2, ||K||^2 and ||R||^2 (fixed order within
+// the block); oa_correct sums the blocks' partials in block order, so delta is
+// the same for every workgroup and every run.
+constexpr int OA_BLOCKS = 32;
+
 __global__ __launch_bounds__(256) void oa_prepare_kernel(const Rec* __restrict__ recs, OaArgs a) {
-  const Rec& rec = recs[blockIdx.x];
+  const Rec& rec = recs[blockIdx.y];
   const int N = a.N;
   const double* K = at<const double>(rec, WS, a.off_K);
   const double* S = at<const double>(rec, WS, a.off_S);
   const double* G = at<const double>(rec, WS, a.off_G);
   double* lam = at<double>(rec, WS, a.off_lam);
+  double* part = at<double>(rec, WS, a.off_delta) + 1 + 3 * blockIdx.x;
   __shared__ double red[3][256];
   const int t = threadIdx.x;
-  for (int i = t; i < N; i += 256) {
+  const int ic = (N + OA_BLOCKS - 1) / OA_BLOCKS;
+  for (int i = blockIdx.x * ic + t; i < min(N, (int)(blockIdx.x + 1) * ic); i += 256) {
     const int64_t dii = i + (int64_t)i * N;
     lam[i] = G[dii] > 0.0 ? S[dii] / G[dii] : 0.0;
     lam[N + i] = 1.0;
   }
+  const int64_t nn = (int64_t)N * N, ec = (nn + OA_BLOCKS - 1) / OA_BLOCKS;
+  const int64_t e0 = blockIdx.x * ec, e1 = min(nn, e0 + ec);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  const int64_t nn = (int64_t)N * N;
-  for (int64_t e = t; e < nn; e += 256) {
+  for (int64_t e = e0 + t; e < e1; e += 256) {
     const int i = (int)(e % N), j = (int)(e / N);
     const double sij = S[e], kij = K[e], gij = G[e];
     const double off = i == j ? sij - (gij > 0.0 ? sij / gij : 0.0) : sij;
@@ -2267,7 +2276,7 @@ __global__ __launch_bounds__(256) void oa_prepare_kernel(const Rec* __restrict__
       for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + h];
     __syncthreads();
   }
-  if (t == 0) *at<double>(rec, WS, a.off_delta) = 2.0 * (sqrt(red[0][0]) + sqrt(red[1][0]) * sqrt(red[2][0]));
+  if (t < 3) part[t] = red[t][0];
 }
 
 // E over G, element by element (each thread reads and writes its own entries)
@@ -2277,7 +2286,19 @@ __global__ __launch_bounds__(256) void oa_correct_kernel(const Rec* __restrict__
   const double* S = at<const double>(rec, WS, a.off_S);
   double* G = at<double>(rec, WS, a.off_G);
   const double* lam = at<const double>(rec, WS, a.off_lam);
-  const double dl = *at<const double>(rec, WS, a.off_delta);
+  __shared__ double dl_s;
+  if (threadIdx.x == 0) {
+    const double* part = at<const double>(rec, WS, a.off_delta) + 1;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < OA_BLOCKS; ++b) {
+      s0 += part[3 * b];
+      s1 += part[3 * b + 1];
+      s2 += part[3 * b + 2];
+    }
+    dl_s = 2.0 * (sqrt(s0) + sqrt(s1) * sqrt(s2));
+  }
+  __syncthreads();
+  const double dl = dl_s;
   const int64_t nn = (int64_t)N * N;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % N), j = (int)(e / N);
@@ -2289,7 +2310,7 @@ __global__ __launch_bounds__(256) void oa_correct_kernel(const Rec* __restrict__
 
 hipError_t oa_prepare(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s) {
   if (a.N > FIN_MAXN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(oa_prepare_kernel, dim3(nrec), dim3(256), 0, s, recs, a);
+  hipLaunchKernelGGL(oa_prepare_kernel, dim3(OA_BLOCKS, nrec), dim3(256), 0, s, recs, a);
   return hipGetLastError();
 }
 
