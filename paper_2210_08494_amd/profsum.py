@@ -2,8 +2,8 @@
 
     python -m paper_2210_08494_amd.profsum <dir-with-csv> <prefix> [--kernel SUBSTR] [--grid X,Y]
         [--top N] [--cmd "the command that produced the CSV"]
-    python -m paper_2210_08494_amd.profsum --pmc <dir> <prefix> [--trace-dir D --trace-prefix P]
-        [--cmd ...]
+    python -m paper_2210_08494_amd.profsum --pmc --fetch F.csv --write W.csv [--trace T.csv] [--cmd ...]
+    python -m paper_2210_08494_amd.profsum --pmc --fetch F.csv --write W.csv --mops M.csv --trace T.csv
 
 Prints the top kernels by total time, and, for --kernel, the dispatch count,
 average and total duration of that kernel restricted to dispatches whose grid
@@ -61,7 +61,12 @@ def pmc_main(argv):
     ap.add_argument("--calib-mib", type=float, default=256.0)
     ap.add_argument("--cmd", action="append", default=[])
     ap.add_argument("--top", type=int, default=24)
+    ap.add_argument("--mops", default="",
+                    help="counter_collection.csv of a run with SQ_INSTS_VALU_MFMA_MOPS_{BF16,F64,F32} "
+                         "(same command as --trace): executed MFMA flops per dispatch and rate")
     a = ap.parse_args(argv)
+    if a.mops:
+        return mops_table(a)
     fe, wr = _counters(a.fetch), _counters(a.write)
     last = max(fe)
     kib = a.calib_mib * 1024.0
@@ -103,6 +108,52 @@ def pmc_main(argv):
         t = g["t"] / g["nt"] if g["nt"] else float("nan")
         gbs = (f + w) / t / 1e9 if g["nt"] else float("nan")
         print(f"{g['n']:6d} {f / 1e6:14.2f} {w / 1e6:14.2f} {t * 1e6:9.1f} {gbs:8.0f}  {name[:95]}  ({grid})")
+
+
+def _trace_by_ordinal(path):
+    """{(kernel, total grid, k): duration s} of a kernel trace, k-th dispatch of each kernel and grid."""
+    dur, seen = {}, {}
+    for r in sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"])):
+        key = (re.sub(r"\(.*", "", r["Kernel_Name"]),
+               str(int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])))
+        k = seen.get(key, 0)
+        seen[key] = k + 1
+        dur[key + (k,)] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    return dur
+
+
+PEAK_TF = {"BF16": 2500.0, "F64": 78.6, "F32": 157.3}
+
+
+def mops_table(a):
+    """Executed MFMA flops per (kernel, grid): 512 flops per MOPS count (the counters
+    count 512-flop units), over the traced duration of the same dispatches, and the
+    fraction of the dense peak of the dtype that dominates the kernel's count."""
+    mo = _counters(a.mops)
+    dur = _trace_by_ordinal(a.trace) if a.trace else {}
+    for c in a.cmd:
+        print(f"command: {c}")
+    agg = {}
+    for did, (name, grid, c) in sorted(mo.items()):
+        g = agg.setdefault((name, grid), {"n": 0, "t": 0.0, "nt": 0, "BF16": 0.0, "F64": 0.0, "F32": 0.0})
+        key = (name, grid, g["n"])
+        g["n"] += 1
+        for dt in ("BF16", "F64", "F32"):
+            g[dt] += 512.0 * c.get(f"SQ_INSTS_VALU_MFMA_MOPS_{dt}", 0.0)
+        if key in dur:
+            g["t"] += dur[key]
+            g["nt"] += 1
+    items = sorted(agg.items(), key=lambda kv: -kv[1]["t"])
+    print(f"{'n':>6} {'avg_us':>9} {'GFLOP/disp':>11} {'TFLOP/s':>8} {'dtype':>5} {'of_peak':>7}  kernel  (grid threads)")
+    for (name, grid), g in items[:a.top]:
+        fl = {dt: g[dt] / g["n"] for dt in ("BF16", "F64", "F32")}
+        dt = max(fl, key=fl.get)
+        tot = sum(fl.values())
+        if tot == 0 or not g["nt"]:
+            continue
+        t = g["t"] / g["nt"]
+        tf = tot / t / 1e12
+        print(f"{g['n']:6d} {t * 1e6:9.1f} {tot / 1e9:11.3f} {tf:8.1f} {dt:>5} {tf / PEAK_TF[dt]:7.1%}  {name[:90]}  ({grid})")
 
 
 def main():
