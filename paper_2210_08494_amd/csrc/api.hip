@@ -473,10 +473,12 @@ int core_evd_refined(const Rec* drecs, int nrec, const UpdPlan& p, const CoreArg
       g.m = N; g.n = N; g.k = N;
       g.A = op(WS, p.oB, 1, Np); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oK, 1, N);
       KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
+      g.sym = 1;  // S and G: the tiles on and above the diagonal, mirrored
       g.A = op(WS, p.oK, N, 1); g.B = op(WS, p.oK, 1, N); g.C = op(WS, p.oS, 1, N);
       KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
       g.A = op(WS, p.oV, N, 1); g.B = op(WS, p.oV, 1, N); g.C = op(WS, p.oG, 1, N);
       KFB_TRY(gemm_f64_mfma(drecs, nrec, g, s));
+      g.sym = 0;
       OaArgs oa;
       oa.N = N; oa.off_K = p.oS; oa.off_S = p.oS; oa.off_G = p.oG; oa.off_lam = p.oLam; oa.off_delta = p.oDelta;
       KFB_TRY(oa_prepare(drecs, nrec, oa, s));

@@ -915,7 +915,9 @@ template hipError_t gemm_f32_mfma<float, float>(const Rec*, int, const GemmArgs&
 // current one is multiplied; each operand read along its contiguous dimension;
 // XCD-aware tile order.  Result v of a lane of the FP64 instruction is row
 // lane / 16 + 4 v, column lane % 16: a column-major C takes the transposed issue
-// (B^T A^T) so that 16 consecutive lanes store 16 consecutive rows.
+// (B^T A^T) so that 16 consecutive lanes store 16 consecutive rows.  A
+// symmetric product (sym: X^T X, Y^T Y) computes the tiles on and above the
+// diagonal and writes each result at both of its positions.
 // ---------------------------------------------------------------------------
 constexpr int D64_BM = 64, D64_BK = 16, D64_LD = 64 + 2;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
@@ -926,6 +928,7 @@ __global__ __launch_bounds__(256) void gemm_f64_mfma_kernel(const Rec* __restric
   __shared__ double sB[2][D64_BK][D64_LD];
   int tm, tn, tz;
   xcd_tile(gridDim.x, gridDim.y, gridDim.z, &tm, &tn, &tz);
+  if (g.sym && tm > tn) return;  // the mirror of a tile above the diagonal
   const Rec& rec = recs[tz];
   const double* A = at<const double>(rec, g.A.slot, g.A.off);
   const double* B = at<const double>(rec, g.B.slot, g.B.off);
@@ -1007,13 +1010,15 @@ __global__ __launch_bounds__(256) void gemm_f64_mfma_kernel(const Rec* __restric
           double val = g.alpha * acc[i][j][v];
           if (C0) val += g.beta * C0[(int64_t)gi * g.C0.rs + (int64_t)gj * g.C0.cs];
           C[(int64_t)gi * g.C.rs + (int64_t)gj * g.C.cs] = val;
+          if (g.sym && tm < tn) C[(int64_t)gj * g.C.rs + (int64_t)gi * g.C.cs] = val;
         }
       }
 }
 
 hipError_t gemm_f64_mfma(const Rec* recs, int nrec, const GemmArgs& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || nrec <= 0) return hipSuccess;
-  if (g.A.slot2 >= 0 || g.B.slot2 >= 0 || g.ksplit > 1 || g.beta_slot >= 0 || g.k < 0)
+  if (g.A.slot2 >= 0 || g.B.slot2 >= 0 || g.ksplit > 1 || g.beta_slot >= 0 || g.k < 0 ||
+      (g.sym && (g.m != g.n || g.C0.slot >= 0)))
     return hipErrorInvalidValue;
   dim3 grid((g.m + D64_BM - 1) / D64_BM, (g.n + D64_BM - 1) / D64_BM, nrec);
   if (g.C.rs == 1) hipLaunchKernelGGL((gemm_f64_mfma_kernel<true>), grid, dim3(256), 0, s, recs, g);

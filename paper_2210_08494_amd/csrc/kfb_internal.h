@@ -69,6 +69,9 @@ struct GemmArgs {
   // caller's promise: B is upper triangular (B(k, j) = 0 for k > j), so a tile
   // of columns [n0, n0 + 128) only needs k < n0 + 128 (FP32 MFMA kernel)
   int32_t b_upper = 0;
+  // caller's promise: C = A B is symmetric (A = B^T) and square: the FP64 MFMA
+  // kernel computes the tiles on and above the diagonal and mirrors them
+  int32_t sym = 0;
 };
 
 template <typename T>
