@@ -425,13 +425,16 @@ int core_evd_refined(const Rec* drecs, int nrec, const UpdPlan& p, const CoreArg
       CoreArgs c64 = co;
       KFB_TRY((assemble_core<double, TP, TG, TD>(drecs, nrec, c64, s)));
     }
-    const double eps32 = 1.1920929e-07;
+    // the FP32 iteration stops at 1e-5 rather than at FP32 round-off (eps_32 sqrt(N),
+    // 2.7e-6 at N = 512): the refinement's error is quadratic in its input's, and
+    // the last partial sweep it saves (~1 ms per 48-core call at the headline
+    // shape) moved the tests' errors by less than 1e-7
     auto iterate = [&](int Nc, int Npc, int bw, int64_t oB, int64_t oV, int64_t oCnt, int sweeps,
                        const char* stage) -> int {
       JacArgs ja;
       ja.Np = Npc; ja.N = Nc; ja.b = bw; ja.max_sweeps = sweeps;
       ja.off_B = oB; ja.off_V = oV; ja.off_cnt = oCnt;
-      ja.tol = eps32 * sqrt((double)Nc);
+      ja.tol = 1e-5;
       const int nb = Npc / (bw & 0xff);
       StageTimer st(stage, s, sweeps * (nb - 1));
       for (int sw = 0; sw < sweeps; ++sw)
