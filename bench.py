@@ -109,6 +109,28 @@ def cpu_baseline(budget_s: float = 8.0):
             "legs": res}
 
 
+def _cu_masked_streams(torch, dev, n_pre):
+    """Two streams on disjoint sets of CUs (hipExtStreamCreateWithCUMask, default
+    priority): the first ncu - n_pre CUs for the update, the last n_pre for the
+    preconditioning.  None when the runtime refuses the masks."""
+    import ctypes
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    if not 0 < n_pre < ncu:
+        return None
+    hip = ctypes.CDLL("libamdhip64.so")
+    words = (ncu + 31) // 32
+    out = []
+    for cus in (range(0, ncu - n_pre), range(ncu - n_pre, ncu)):
+        mask = (ctypes.c_uint32 * words)()
+        for c in cus:
+            mask[c // 32] |= 1 << (c % 32)
+        h = ctypes.c_void_p()
+        if hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), ctypes.c_uint32(words), mask) != 0:
+            return None
+        out.append(torch.cuda.ExternalStream(h.value, device=dev))
+    return out[0], out[1], ncu - n_pre, n_pre
+
+
 def _measured_traffic(kfb, kname):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, only when it was taken on this exact library build."""
@@ -311,6 +333,9 @@ def main():
     ap.add_argument("--serve-requests-fp32", type=int, default=2000)
     ap.add_argument("--serve-requests-uneven", type=int, default=2000)
     ap.add_argument("--uneven-inflight", type=int, default=8, help="groups in flight in the uneven serving leg")
+    ap.add_argument("--cu-split", default="auto",
+                    help="CUs of the preconditioning's stream in the two-stream step ('auto': what the "
+                         "update's eigensolver rounds leave at two workgroups per CU; 'off': unmasked streams)")
     ap.add_argument("--jacobi-config", default="",
                     help="install this eigensolver configuration instead of autotuning (e.g. 0x320: "
                          "FP32 iteration + FP64 refinement, 0x120: FP64 iteration)")
@@ -364,13 +389,26 @@ def main():
     # The timed step runs its two calls on two streams at once: the
     # preconditioning reads the factors the previous update left in the front
     # buffers while this step's update writes the back buffers (the states are
-    # double-buffered for this), so the apply's products fill the CUs the
-    # Cholesky and the eigensolver rounds leave idle.  The preconditioning is
-    # enqueued first (the library takes the front buffers at enqueue) and waits
-    # for the previous update; the update waits for the previous
-    # preconditioning, which read the buffers it is about to write.
-    s_upd = torch.cuda.current_stream()
-    s_pre = torch.cuda.Stream(device=dev)
+    # double-buffered for this).  The preconditioning is enqueued first (the
+    # library takes the front buffers at enqueue) and waits for the previous
+    # update; the update waits for the previous preconditioning, which read the
+    # buffers it is about to write.  The two streams run on disjoint CUs
+    # (--cu-split): the update keeps as many as its eigensolver rounds fill at
+    # two workgroups per CU (48 cores x 8 block pairs = 384 workgroups -> 192
+    # CUs), the preconditioning's products take the rest, so they never hold CUs
+    # that a round's workgroups wait for (each round lasts as long as its
+    # slowest workgroup).
+    streams = None
+    if args.cu_split != "off" and not args.one_stream:
+        pairs = (R + N_BATCH + 63) // 64   # block pairs of 32-column blocks per round
+        n_pre = (torch.cuda.get_device_properties(dev).multi_processor_count - S * pairs // 2
+                 if args.cu_split == "auto" else int(args.cu_split))
+        streams = _cu_masked_streams(torch, dev, n_pre)
+        _progress(f"CU-masked streams: {streams[2:] if streams else None}")
+    if streams:
+        s_upd, s_pre, cus_upd, cus_pre = streams
+    else:
+        s_upd, s_pre, cus_upd, cus_pre = torch.cuda.current_stream(), torch.cuda.Stream(device=dev), None, None
     pipe = {"u": None, "p": None}
 
     def step(j):
@@ -383,11 +421,12 @@ def main():
             kfb.precondition_batched(fg, fa, Gsets[j], Ss, lam, lam, 0, ws_p)
             ep = torch.cuda.Event()
             ep.record(s_pre)
-        if pipe["p"] is not None:
-            s_upd.wait_event(pipe["p"])
-        kfb.update_batched(states, batches[j], ws_u)
-        eu = torch.cuda.Event()
-        eu.record(s_upd)
+        with torch.cuda.stream(s_upd):
+            if pipe["p"] is not None:
+                s_upd.wait_event(pipe["p"])
+            kfb.update_batched(states, batches[j], ws_u)
+            eu = torch.cuda.Event()
+            eu.record(s_upd)
         pipe["u"], pipe["p"] = eu, ep
 
     # first update takes every state from empty to n modes; warmup reaches r + n
@@ -413,10 +452,11 @@ def main():
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record()
+    s_rec = torch.cuda.current_stream() if args.one_stream else s_upd
+    ev[0].record(s_rec)
     for j in range(args.steps):
         step(1 + args.warmup + j)
-        ev[j + 1].record()
+        ev[j + 1].record(s_rec)
     s_upd.wait_stream(s_pre)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -713,9 +753,12 @@ def main():
         "config": {"workload": f"{L}-layer stack, 2 K-factors per layer ({S} states) at d={D}, r={R}, "
                                f"n={N_BATCH}, rho={RHO}, lambda={LAM}; step = grouped Brand update of all "
                                f"states + grouped two-sided preconditioning of all {L} layers (on two streams: "
-                               f"the preconditioning reads the factors of the previous update)",
+                               f"the preconditioning reads the factors of the previous update"
+                               + (f"; the update's stream on {cus_upd} CUs, the preconditioning's on {cus_pre})"
+                                  if cus_upd else ")"),
                    "layers": L, "states": S, "d": D, "r": R, "n": N_BATCH, "precision": "bf16-mixed",
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu",
+                   "streams": ({"update_cus": cus_upd, "precond_cus": cus_pre} if cus_upd else None)},
         "latency_ms": {"step_p50": round(_percentile(step_ms, 50), 3),
                        "step_p99": round(_percentile(step_ms, 99), 3),
                        "single_update_p50": round(_percentile(lat1, 50), 3),
