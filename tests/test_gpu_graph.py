@@ -63,12 +63,32 @@ def test_graph_replay_equals_eager(kfb):
     assert all(f.status() == 0 for f in A + B)
 
 
-def test_two_stream_pipeline_equals_one_stream(kfb):
+def _cu_masked_pair(torch, dev, n_second):
+    """Two streams on disjoint CU sets (the benchmark's split), or None if refused."""
+    import ctypes
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    hip = ctypes.CDLL("libamdhip64.so")
+    words = (ncu + 31) // 32
+    out = []
+    for cus in (range(0, ncu - n_second), range(ncu - n_second, ncu)):
+        mask = (ctypes.c_uint32 * words)()
+        for c in cus:
+            mask[c // 32] |= 1 << (c % 32)
+        h = ctypes.c_void_p()
+        if hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), ctypes.c_uint32(words), mask) != 0:
+            return None
+        out.append(torch.cuda.ExternalStream(h.value, device=dev))
+    return out
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_two_stream_pipeline_equals_one_stream(kfb, masked):
     # the benchmark's step on two streams: each step's preconditioning (reading the
     # factors the previous update left in the front buffers) runs beside that step's
     # update (writing the back buffers); ordered by events on the buffer they share.
     # Every step's S and every state equal the same calls issued in that order on one
-    # stream, bit for bit, with extra work on a third stream to shift the timing.
+    # stream, bit for bit, with extra work on a third stream to shift the timing; with
+    # `masked` the two streams run on disjoint CU sets, as in the benchmark's step.
     import torch
     dev = torch.device("cuda:0")
     d, r, n, L, steps = 768, 96, 64, 3, 5
@@ -96,9 +116,13 @@ def test_two_stream_pipeline_equals_one_stream(kfb):
     for j in range(steps):
         kfb.precondition_batched(A[1::2], A[0::2], Gs[j], SA[j], lam, lam, 0, wsA)
         kfb.update_batched(A, batches[j + 1], wsA)
-    # pipeline: two streams, plus unrelated work on a third
-    s_upd = torch.cuda.current_stream()
-    s_pre = torch.cuda.Stream(device=dev)
+    # pipeline: two streams (unmasked, or on disjoint CU sets as in the benchmark),
+    # plus unrelated work on a third
+    s_upd, s_pre = torch.cuda.current_stream(), torch.cuda.Stream(device=dev)
+    if masked:
+        pair = _cu_masked_pair(torch, dev, 64)
+        assert pair is not None, "the runtime refused the CU-masked streams"
+        s_upd, s_pre = pair
     s_noise = torch.cuda.Stream(device=dev)
     big = torch.randn(2048, 2048, device=dev)
     eu = ep = None
@@ -113,14 +137,16 @@ def test_two_stream_pipeline_equals_one_stream(kfb):
             kfb.precondition_batched(B[1::2], B[0::2], Gs[j], SB[j], lam, lam, 0, wsP)
             ep = torch.cuda.Event()
             ep.record(s_pre)
-        if j > 0:
-            s_upd.wait_event(prev_ep)
-        kfb.update_batched(B, batches[j + 1], wsB)
-        eu = torch.cuda.Event()
-        eu.record(s_upd)
+        with torch.cuda.stream(s_upd):
+            if j > 0:
+                s_upd.wait_event(prev_ep)
+            kfb.update_batched(B, batches[j + 1], wsB)
+            eu = torch.cuda.Event()
+            eu.record(s_upd)
         prev_ep = ep
     s_upd.wait_stream(s_pre)
     torch.cuda.synchronize()
+    print(f"  two-stream pipeline (masked={masked}) done", flush=True)
     for j in range(steps):
         for x, y in zip(SA[j], SB[j]):
             assert torch.equal(x, y), f"step {j}: preconditioned gradient differs"
