@@ -231,14 +231,17 @@ bool make_upd_plan(int64_t d, int64_t ldu, int64_t ldm, int r, int n, int nrec, 
   if (p->pre) {
     p->prebw = pick_jacobi(PR, n, (int)sizeof(typename T::Core), true, &p->preNp) & ~JAC_REFINE;
     // the FP32 iteration runs its block solve on the FP32 streamed kernel as well
-    if (p->refine) p->prebw = JAC_STREAMED | 32, p->preNp = jacobi_block_fits(n, 4, JAC_STREAMED | 32);
+    if (p->refine) {
+      p->prebw = JAC_STREAMED | 32;
+      p->preNp = jacobi_block_fits(n, 4, JAC_STREAMED | 32);
+    }
     if (p->prebw == 0 || p->preNp == 0) p->pre = false;
   }
   if (p->refine) {
     const size_t c32 = (size_t)p->Np * p->Np * 4, k64 = (size_t)p->N * p->N * 8;
     p->oB32 = take(c32); p->oV32 = take(c32);
     p->oK = take(k64); p->oS = take(k64); p->oG = take(k64);
-    p->oDelta = take(8 * (1 + 3 * 32));  // the refinement threshold's partial sums
+    p->oDelta = take(8 * (1 + 3 * OA_BLOCKS));  // the refinement threshold's partial sums
   }
   if (p->pre) {
     const size_t pc = (size_t)p->preNp * p->preNp * sizeof(typename T::Core);

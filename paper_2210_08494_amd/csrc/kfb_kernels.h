@@ -130,11 +130,12 @@ hipError_t finalize_sorted(const Rec* recs, int nrec, const FinArgs& a, hipStrea
 // oa_prepare writes the eigenvalue estimates into lam[0, N) (scales lam[N + j]
 // = 1) and the partial sums of the cluster threshold; oa_correct forms the
 // threshold and overwrites G with the correction E, after which X' = X + X E.
+constexpr int OA_BLOCKS = 32;  // workgroups per problem of oa_prepare
 struct OaArgs {
   int N;
   int64_t off_K;  // a matrix whose Frobenius norm stands for ||K|| (K itself, or S)
   int64_t off_S, off_G, off_lam;
-  int64_t off_delta;  // 1 + 3 * 32 doubles: scratch of the threshold's partial sums
+  int64_t off_delta;  // 1 + 3 OA_BLOCKS doubles: scratch of the threshold's partial sums
 };
 hipError_t oa_prepare(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s);
 hipError_t oa_correct(const Rec* recs, int nrec, const OaArgs& a, hipStream_t s);

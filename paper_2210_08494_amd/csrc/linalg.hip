@@ -2237,7 +2237,6 @@ template hipError_t chol_inv<float>(const Rec*, int, const CholArgs&, hipStream_
 // partial sums of ||S - diag(lam)||^2, ||K||^2 and ||R||^2 (fixed order within
 // the block); oa_correct sums the blocks' partials in block order, so delta is
 // the same for every workgroup and every run.
-constexpr int OA_BLOCKS = 32;
 
 __global__ __launch_bounds__(256) void oa_prepare_kernel(const Rec* __restrict__ recs, OaArgs a) {
   const Rec& rec = recs[blockIdx.y];
