@@ -441,9 +441,11 @@ def main():
         for (m, n, k) in tune.precond_product_shapes(D, D, Ncore, Ncore):
             kfb.tune_set_gemm(m, n, k, tile_best)
     else:
-        tile_best, tile_ms = tune.tune_gemm_tiles(
-            lambda: kfb.precondition_batched(fg, fa, Gsets[0], Ss, lam, lam, 0, ws_p),
-            tune.precond_product_shapes(D, D, Ncore, Ncore), reps=3)
+        # timed where the step runs it: on the preconditioning's stream (its CU share)
+        with torch.cuda.stream(s_pre):
+            tile_best, tile_ms = tune.tune_gemm_tiles(
+                lambda: kfb.precondition_batched(fg, fa, Gsets[0], Ss, lam, lam, 0, ws_p),
+                tune.precond_product_shapes(D, D, Ncore, Ncore), reps=3)
     _progress(f"gemm tile autotune done: {tile_best} {tile_ms}")
 
     # ---- timed region (stage events recorded live on the same stream)
