@@ -466,6 +466,14 @@ def main():
     kfb.profile_enable(False)
     step_ms = [ev[j].elapsed_time(ev[j + 1]) for j in range(args.steps)]
     status = [f.status() for f in states]
+    if streams:
+        # a CU-masked stream holds a hardware queue of its own; give both back before
+        # the serving legs, whose streams share the process's few queues
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        for st in (s_upd, s_pre):
+            hip.hipStreamDestroy(ctypes.c_void_p(st.cuda_stream))
+        s_upd = s_pre = None
 
     bups = S * args.steps / wall
     ms_per_step = 1e3 * wall / args.steps
