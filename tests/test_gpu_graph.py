@@ -146,6 +146,11 @@ def test_two_stream_pipeline_equals_one_stream(kfb, masked):
         prev_ep = ep
     s_upd.wait_stream(s_pre)
     torch.cuda.synchronize()
+    if masked:  # each masked stream holds a hardware queue: give them back
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        for st in (s_upd, s_pre):
+            hip.hipStreamDestroy(ctypes.c_void_p(st.cuda_stream))
     print(f"  two-stream pipeline (masked={masked}) done", flush=True)
     for j in range(steps):
         for x, y in zip(SA[j], SB[j]):
