@@ -23,6 +23,7 @@ random vectors.  Tolerances: 1e-5 (FP32) and 2e-2 (BF16-mixed) on
 reconstruction and on the preconditioned gradient, both in Frobenius norm and
 projected on the modes' span (e_S_proj).
 """
+import sys
 import numpy as np
 import pytest
 
@@ -58,7 +59,10 @@ def _D_np(f):
 
 
 def _say(msg):
-    print(msg, flush=True)
+    # progress of the long runs goes to the process's own stderr, past pytest's
+    # capture, so a multi-minute test keeps reporting while it runs
+    sys.__stderr__.write(msg + "\n")
+    sys.__stderr__.flush()
 
 
 def _batch(cfg, k, side, n, d, prec, bias=False):
