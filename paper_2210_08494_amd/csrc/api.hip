@@ -614,7 +614,9 @@ void make_pre_plan(int64_t dG, int64_t dA, int64_t lduG, int64_t lduA, int NG, i
   p->ldg = ldg; p->lds = lds;
   const int tiles = ((NG + 63) / 64) * ((NA + 63) / 64);  // own shape only
   int ks = 1;
-  while (tiles * ks < 512 && (dA / (ks * 2)) >= 256) ks *= 2;
+  // T3's inner dimension: dA (T1 U_A), or dG in the mixed form (U_G^T T2)
+  const int64_t k3 = PR == KFB_BF16_MIXED ? dG : dA;
+  while (tiles * ks < 512 && (k3 / (ks * 2)) >= 256) ks *= 2;
   p->ks3 = ks;
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at_ = o; o = align256(o + bytes); return (int64_t)at_; };
@@ -639,32 +641,45 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   CoefArgs ca;
   ca.kG = NG; ca.kA = NA; ca.off_cG = p.ocG; ca.off_cA = p.ocA; ca.flags = flags;
   KFB_TRY((precond_coefs<TD, TA>(drecs, nrec, ca, s)));
-  // T1 = U_G^T G   (NG x dA, row-major)
+  // Mixed form: the coefficient scalings of X1 and of T2 are folded into the
+  // epilogues of the BF16 products (T1's rows, X2's C0 columns), so T3 is formed
+  // from the unscaled T2 (U_G^T G U_A either way) and no separate pass rereads
+  // T1 or T2.
+  constexpr bool FOLD = PR == KFB_BF16_MIXED;
+  // T1 = U_G^T G   (NG x dA, row-major; mixed form: X1 = diag(c_G / lam_A) T1)
   GemmArgs g1;
   g1.A = op(PU_G, 0, p.lduG, 1); g1.B = op(P_G, 0, p.ldg, 1); g1.C = op(PWS, p.oT1, dA, 1);
   g1.m = NG; g1.n = (int)dA; g1.k = (int)dG; g1.aligned16 = p.aligned16; g1.c_vec = 1;  // workspace
+  if (FOLD) { g1.rsc_slot = PWS; g1.rsc_off = p.ocG; }
   KFB_TRY((mm<PR, 0, TU, TGrad, TA, TA, TA>(drecs, nrec, g1, s)));
   // T2 = G U_A     (dG x NA, column-major)
   GemmArgs g2;
   g2.A = op(P_G, 0, p.ldg, 1); g2.B = op(PU_A, 0, 1, p.lduA); g2.C = op(PWS, p.oT2, 1, dG);
   g2.m = (int)dG; g2.n = NA; g2.k = (int)dA; g2.aligned16 = p.aligned16; g2.c_vec = 1;  // workspace
   KFB_TRY((mm<PR, 0, TGrad, TU, TA, TA, TA>(drecs, nrec, g2, s)));
-  // T3 = T1 U_A    (NG x NA)
+  // T3 = T1 U_A    (NG x NA); mixed form: U_G^T T2 (T1 already holds X1)
   GemmArgs g3;
-  g3.A = op(PWS, p.oT1, dA, 1); g3.B = op(PU_A, 0, 1, p.lduA); g3.C = op(PWS, p.oT3, 1, NG);
-  g3.m = NG; g3.n = NA; g3.k = (int)dA; g3.ksplit = p.ks3; g3.Part = op(PWS, p.oPart, 1, NG);
+  if (FOLD) {
+    g3.A = op(PU_G, 0, p.lduG, 1); g3.B = op(PWS, p.oT2, 1, dG); g3.k = (int)dG;
+  } else {
+    g3.A = op(PWS, p.oT1, dA, 1); g3.B = op(PU_A, 0, 1, p.lduA); g3.k = (int)dA;
+  }
+  g3.C = op(PWS, p.oT3, 1, NG);
+  g3.m = NG; g3.n = NA; g3.ksplit = p.ks3; g3.Part = op(PWS, p.oPart, 1, NG);
   g3.aligned16 = p.aligned16;  // T1 rows need dA % 4 == 0 as well (checked with the strides)
   KFB_TRY((mm<PR, 0, TA, TU, TA, TA, TA>(drecs, nrec, g3, s)));
-  st_pre.reset(new StageTimer("pre_scale_X2", s, 4));
+  st_pre.reset(new StageTimer("pre_scale_X2", s, FOLD ? 2 : 4));
   // X1 = diag(c_G / lam_A) T1;  T2 <- T2 diag(c_A / lam_G);  T3 <- diag(c_G) T3 diag(c_A)
-  ScaleArgs s1;
-  s1.m = NG; s1.n = (int)dA; s1.X = op(PWS, p.oT1, dA, 1); s1.row_slot = PWS; s1.row_off = p.ocG;
-  s1.col_slot = -1; s1.col_off = 0; s1.extra_mode = 0;
-  KFB_TRY((scale2d<TA, TA>(drecs, nrec, s1, s)));
-  ScaleArgs s2;
-  s2.m = (int)dG; s2.n = NA; s2.X = op(PWS, p.oT2, 1, dG); s2.row_slot = -1; s2.row_off = 0;
-  s2.col_slot = PWS; s2.col_off = p.ocA; s2.extra_mode = 0;
-  KFB_TRY((scale2d<TA, TA>(drecs, nrec, s2, s)));
+  if (!FOLD) {
+    ScaleArgs s1;
+    s1.m = NG; s1.n = (int)dA; s1.X = op(PWS, p.oT1, dA, 1); s1.row_slot = PWS; s1.row_off = p.ocG;
+    s1.col_slot = -1; s1.col_off = 0; s1.extra_mode = 0;
+    KFB_TRY((scale2d<TA, TA>(drecs, nrec, s1, s)));
+    ScaleArgs s2;
+    s2.m = (int)dG; s2.n = NA; s2.X = op(PWS, p.oT2, 1, dG); s2.row_slot = -1; s2.row_off = 0;
+    s2.col_slot = PWS; s2.col_off = p.ocA; s2.extra_mode = 0;
+    KFB_TRY((scale2d<TA, TA>(drecs, nrec, s2, s)));
+  }
   ScaleArgs s3;
   s3.m = NG; s3.n = NA; s3.X = op(PWS, p.oT3, 1, NG); s3.row_slot = PWS;
   s3.row_off = p.ocG + (int64_t)NG * sizeof(TA); s3.col_slot = PWS;
@@ -676,6 +691,7 @@ int run_precond(const Rec* drecs, int nrec, const PrePlan& p, uint32_t flags, hi
   g4.C = op(PWS, p.oT2, 1, dG); g4.m = (int)dG; g4.n = NA; g4.k = NG; g4.beta = 1.0;
   g4.aligned16 = p.aligned16;  // U_G columns (256-byte multiples) and the workspace blocks
   g4.c_vec = 1;                // T2 (C0 and C) in the workspace
+  if (FOLD) { g4.c0cs_slot = PWS; g4.c0cs_off = p.ocA; }  // X2 = T2 diag(c_A / lam_G) + U_G T3
   KFB_TRY((mm<PR, 0, TU, TA, TA, TA, TA>(drecs, nrec, g4, s)));
   st_pre.reset();
   StageTimer st_s("pre_S", s, 1);

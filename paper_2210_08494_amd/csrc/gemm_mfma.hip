@@ -268,6 +268,13 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_kernel(const Rec* __restrict__ 
   const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
   const float alpha = (float)g.alpha;
   const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+  // optional scalings C = alpha diag(r) (A B) + beta C0 diag(c) (single-term products)
+  const float* rsc = nullptr;
+  const float* ccs = nullptr;
+  if constexpr (SPLIT == 0) {
+    rsc = g.rsc_slot >= 0 ? at<const float>(rec, g.rsc_slot, g.rsc_off) : nullptr;
+    ccs = g.c0cs_slot >= 0 ? at<const float>(rec, g.c0cs_slot, g.c0cs_off) : nullptr;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -279,7 +286,12 @@ __global__ __launch_bounds__(MNT) void gemm_bf16_kernel(const Rec* __restrict__ 
         else { gi = gm0 + 16 * i + 4 * (l / 16) + v; gj = gn0 + 16 * j + (l % 16); }
         if (gi < g.m && gj < g.n) {
           float val = alpha * acc[i][j][v];
-          if (C0) val += beta * to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+          if (rsc) val *= rsc[gi];
+          if (C0) {
+            float c0 = to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+            if (ccs) c0 *= ccs[gj];
+            val += beta * c0;
+          }
           C[gi * g.C.rs + gj * g.C.cs] = TC(val);
         }
       }
@@ -393,9 +405,13 @@ __device__ __forceinline__ void xcd_tile(int nx, int ny, int nz, int* tm, int* t
 
 // TT: square output tile (128: four waves of 64 x 64; 256: eight waves of
 // 128 x 64, single-term products only, twice the flops per staged byte).
-template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP, bool SPL = false, int TT = 128>
+// ESC: the epilogue applies the optional scalings C = alpha diag(r) (A B) +
+// beta C0 diag(c) (single term, no split-K); a template switch, so the other
+// products keep their register budget.
+template <typename TC, typename TC0, bool AKC, bool BKC, bool SWP, bool SPL = false, int TT = 128, bool ESC = false>
 __global__ __launch_bounds__(2 * TT) void gemm_bf16_fast_kernel(const Rec* __restrict__ recs, GemmArgs g) {
   static_assert(TT == 128 || (TT == 256 && !SPL), "tile");
+  static_assert(!(ESC && SPL), "scaled epilogue");
   constexpr int FM = TT / 32, FN = 4;  // 16 x 16 fragments per wave along rows / columns
   __shared__ __attribute__((aligned(16))) __bf16 sA[2][TT * MLD];
   __shared__ __attribute__((aligned(16))) __bf16 sB[2][TT * MLD];
@@ -502,6 +518,12 @@ __global__ __launch_bounds__(2 * TT) void gemm_bf16_fast_kernel(const Rec* __res
   const TC0* C0 = use_c0 ? at<const TC0>(rec, g.C0.slot, g.C0.off) : nullptr;
   const float alpha = (float)g.alpha;
   const float beta = g.beta_slot >= 0 ? (float)*at<const double>(rec, g.beta_slot, g.beta_off) : (float)g.beta;
+  const float* rsc = nullptr;
+  const float* ccs = nullptr;
+  if constexpr (ESC) {
+    rsc = g.rsc_slot >= 0 ? at<const float>(rec, g.rsc_slot, g.rsc_off) : nullptr;
+    ccs = g.c0cs_slot >= 0 ? at<const float>(rec, g.c0cs_slot, g.c0cs_off) : nullptr;
+  }
   if constexpr (sizeof(TC) == 4 && sizeof(TC0) == 4) {
     // vector epilogue: each lane's four results are four consecutive columns of
     // a row-major C (transposed issue) or four consecutive rows of a
@@ -522,7 +544,18 @@ __global__ __launch_bounds__(2 * TT) void gemm_bf16_fast_kernel(const Rec* __res
           }
           if (gi < g.m && gj < g.n) {
             f32x4 val = alpha * acc[i][j];
-            if (C0) val += beta * *reinterpret_cast<const f32x4*>(&C0[oc0]);
+            if constexpr (ESC) {  // the lane's four results: one row (SWP) or four rows
+              if (rsc) val *= SWP ? f32x4{rsc[gi], rsc[gi], rsc[gi], rsc[gi]}
+                                  : *reinterpret_cast<const f32x4*>(&rsc[gi]);
+            }
+            if (C0) {
+              f32x4 c0 = *reinterpret_cast<const f32x4*>(&C0[oc0]);
+              if constexpr (ESC) {  // four columns (SWP) or one column
+                if (ccs) c0 *= SWP ? *reinterpret_cast<const f32x4*>(&ccs[gj])
+                                   : f32x4{ccs[gj], ccs[gj], ccs[gj], ccs[gj]};
+              }
+              val += beta * c0;
+            }
             *reinterpret_cast<f32x4*>(&C[oc]) = val;
           }
         }
@@ -540,7 +573,16 @@ __global__ __launch_bounds__(2 * TT) void gemm_bf16_fast_kernel(const Rec* __res
         else { gi = gm0 + 16 * i + 4 * (l / 16) + v; gj = gn0 + 16 * j + (l % 16); }
         if (gi < g.m && gj < g.n) {
           float val = alpha * acc[i][j][v];
-          if (C0) val += beta * to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+          if constexpr (ESC) {
+            if (rsc) val *= rsc[gi];
+          }
+          if (C0) {
+            float c0 = to_f(C0[gi * g.C0.rs + gj * g.C0.cs]);
+            if constexpr (ESC) {
+              if (ccs) c0 *= ccs[gj];
+            }
+            val += beta * c0;
+          }
           C[gi * g.C.rs + gj * g.C.cs] = TC(val);
         }
       }
@@ -609,6 +651,11 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStr
     g.kchunk = chunk;
   }
   g.ksplit = ks;
+  const bool esc = g.rsc_slot >= 0 || g.c0cs_slot >= 0;
+  if (esc && (SPL || ks > 1)) {  // the scaled epilogue takes whole single-term sums
+    *err = hipErrorInvalidValue;
+    return true;
+  }
   dim3 grid(((g.m + tt - 1) / tt) * ks, (g.n + tt - 1) / tt, nrec);
   // vector epilogue (C and C0 as 16-byte vectors): a row-major C takes the
   // transposed issue (four consecutive columns per lane), a column-major C the
@@ -624,6 +671,11 @@ static bool gemm_bf16_fast(const Rec* recs, int nrec, const GemmArgs& g0, hipStr
   do {                                                                                                \
     if constexpr (SPL) {                                                                              \
       hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, SPL, 128>), grid, dim3(MNT), 0, s, recs, g); \
+    } else if (esc) {                                                                                 \
+      if (tt == 256)                                                                                  \
+        hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, false, 256, true>), grid, dim3(512), 0, s, recs, g); \
+      else                                                                                            \
+        hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, false, 128, true>), grid, dim3(MNT), 0, s, recs, g); \
     } else if (tt == 256) {                                                                           \
       hipLaunchKernelGGL((gemm_bf16_fast_kernel<TC, TC0, AK, BK, SW, false, 256>), grid, dim3(512), 0, s, recs, g); \
     } else {                                                                                          \
@@ -693,6 +745,7 @@ hipError_t gemm_bf16(const Rec* recs, int nrec, const GemmArgs& g0, hipStream_t 
     g.kchunk = g.k > 0 ? g.k : 1;
   }
   g.ksplit = ks;
+  if ((g.rsc_slot >= 0 || g.c0cs_slot >= 0) && (SPLIT != 0 || ks > 1)) return hipErrorInvalidValue;
   dim3 grid(tiles_m * ks, tiles_n, nrec);
   hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, TC, TC0, SPLIT>), grid, dim3(MNT), 0, s, recs, g);
   hipError_t e = hipGetLastError();

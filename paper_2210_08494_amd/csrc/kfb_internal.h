@@ -72,6 +72,13 @@ struct GemmArgs {
   // caller's promise: C = A B is symmetric (A = B^T) and square: the FP64 MFMA
   // kernel computes the tiles on and above the diagonal and mirrors them
   int32_t sym = 0;
+  // optional scalings of a single-term BF16 product without split-K:
+  // C = alpha diag(r) (A B) + beta C0 diag(c), r and c FP32 vectors at
+  // rec.p[rsc_slot] + rsc_off and rec.p[c0cs_slot] + c0cs_off (-1: none)
+  int32_t rsc_slot = -1;
+  int64_t rsc_off = 0;
+  int32_t c0cs_slot = -1;
+  int64_t c0cs_off = 0;
 };
 
 template <typename T>
