@@ -206,6 +206,7 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
   __shared__ T Dg[CB][CB + 1];
   __shared__ T red[CHB_NT / 64], redt[CHB_NT / 64];
   __shared__ T invrow[CB];
+  __shared__ T rowb[CB];  // row j of R during the diagonal block's step j
   __shared__ int okrow[CB];
   __shared__ int deficient, nonfinite;
   const T* Wg = at<const T>(rec, WS, a.off_gram);
@@ -273,57 +274,41 @@ __global__ __launch_bounds__(CHB_NT) void chol_blocked_kernel(const Rec* __restr
       Pn[i * LDW + c] = (i < nbk && c < m) ? R[(kb + i) + (int64_t)(c0 + c) * n] : T(0);
     }
     __syncthreads();
-    if (t < 64) {
-      // diagonal block, right-looking on its upper triangle: lane (ti, tk) holds
-      // the 4 x 4 tile of rows 4 ti.., columns 4 tk..; at step j the pivot comes
-      // from its lane and the pieces of row j from the lanes of tile row j / 4
-      // by cross-lane reads (a rolled loop: the unrolled form overflows the
-      // instruction cache)
-      const int ti = t & 7, tk = t >> 3;
-      T a4[4][4];
+    if (t < CB) {
+      // diagonal block, right-looking: lane c holds column c of the block in
+      // registers (rows 0..c); step j takes the pivot from lane j, each lane
+      // forms its entry of row j of R, the row goes through LDS, and each lane
+      // updates its column with it (the rank-1 update of the rows below j)
+      const int c = t;
+      T a[CB];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int i = 0; i < CB; ++i) a[i] = Dg[i][c];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a4[r][c] = Dg[4 * ti + r][4 * tk + c];
-      for (int j = 0; j < nbk; ++j) {
-        const int jt = j >> 2, jr = j & 3;
-        T v[4];  // row jr of this lane's tile
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = jr == 0 ? a4[0][c] : jr == 1 ? a4[1][c] : jr == 2 ? a4[2][c] : a4[3][c];
-        T vi[4], vk[4];  // row j at this lane's rows (tile (jt, ti)) and columns (tile (jt, tk))
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          vi[q] = __shfl(v[q], jt + 8 * ti, 64);
-          vk[q] = __shfl(v[q], jt + 8 * tk, 64);
-        }
-        const T p = lane_value(jr == 0 ? v[0] : jr == 1 ? v[1] : jr == 2 ? v[2] : v[3], 9 * jt);
-        const bool ok = p > tau && dmax > T(0);
-        const T inv = ok ? dev_rsqrt(p) : T(0);
-        const T sp = ok ? p * inv : T(0);
-        T ri[4], rk[4];  // R[j][i] for this lane's rows below j, R[j][k] for its columns
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = 4 * ti + q, k = 4 * tk + q;
-          ri[q] = i > j ? vi[q] * inv : T(0);
-          rk[q] = k > j ? vk[q] * inv : (k == j ? sp : T(0));
-        }
-        if (t == 0) {
-          okrow[j] = ok;
-          invrow[j] = inv;
-          if (!ok && kb + j < nreal) deficient = 1;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            a4[r][c] = fma(-ri[r], rk[c], a4[r][c]);
-            if (ti == jt && r == jr) a4[r][c] = rk[c];  // row j of R
+      for (int j = 0; j < CB; ++j) {
+        if (j < nbk) {
+          const T p = lane_value(a[j], j);
+          const bool ok = p > tau && dmax > T(0);
+          const T inv = ok ? dev_rsqrt(p) : T(0);
+          const T sp = ok ? p * inv : T(0);
+          const T rj = c > j ? a[j] * inv : (c == j ? sp : T(0));  // R[j][c]
+          if (c >= j) a[j] = rj;
+          if (t == 0) {
+            okrow[j] = ok;
+            invrow[j] = inv;
+            if (!ok && kb + j < nreal) deficient = 1;
           }
+          rowb[c] = rj;
+          wave_sync();
+#pragma unroll
+          for (int i = j + 1; i < CB; ++i) {
+            const T ri = rowb[i];  // R[j][i]
+            if (i <= c) a[i] = fma(-ri, rj, a[i]);
+          }
+          wave_sync();  // every lane has read the row before the next step writes it
+        }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) Dg[4 * ti + r][4 * tk + c] = 4 * ti + r <= 4 * tk + c ? a4[r][c] : T(0);
+      for (int i = 0; i < CB; ++i) Dg[i][c] = i <= c ? a[i] : T(0);
     }
     __syncthreads();
     for (int e = t; e < nbk * nbk; e += CHB_NT) {
