@@ -318,12 +318,16 @@ def test_batched_equals_single(kfb):
             assert torch.equal(Ua, Ub) and torch.equal(Da, Db)
 
 
+@pytest.mark.parametrize("dG,dA", [(768, 1024), (770, 1001)])
 @pytest.mark.parametrize("flags", [0, 1])
-def test_mixed_precondition_on_loaded_state(kfb, flags):
-    # BF16-MFMA apply on an oracle-built state (U in FP32, D in FP64), G FP32
+def test_mixed_precondition_on_loaded_state(kfb, flags, dG, dA):
+    # BF16-MFMA apply on an oracle-built state (U in FP32, D in FP64), G FP32;
+    # widths that are not multiples of 4 / 32 take the general BF16 kernel
+    # (unaligned G rows, k not a whole number of tiles) with the coefficient
+    # scalings in its epilogue
     import torch
-    dG, dA, r, n, rho = 768, 1024, 64, 64, 0.95
-    _announce(f"mixed precondition flags={flags}")
+    r, n, rho = 64, 64, 0.95
+    _announce(f"mixed precondition flags={flags} dG={dG} dA={dA}")
     bg = _oracle_state(dG, r, n, rho, 4, 31, "G")
     ba = _oracle_state(dA, r, n, rho, 4, 31, "A")
     fg = kfb.Factor(dG, r, n, rho, kfb.KFB_BF16_MIXED)
