@@ -318,20 +318,22 @@ def test_batched_equals_single(kfb):
             assert torch.equal(Ua, Ub) and torch.equal(Da, Db)
 
 
-@pytest.mark.parametrize("dG,dA", [(768, 1024), (770, 1001)])
+@pytest.mark.parametrize("dG,dA,rG,nG,rA,nA", [(768, 1024, 64, 64, 64, 64), (770, 1001, 64, 64, 64, 64),
+                                                (768, 1024, 64, 64, 48, 32)])
 @pytest.mark.parametrize("flags", [0, 1])
-def test_mixed_precondition_on_loaded_state(kfb, flags, dG, dA):
+def test_mixed_precondition_on_loaded_state(kfb, flags, dG, dA, rG, nG, rA, nA):
     # BF16-MFMA apply on an oracle-built state (U in FP32, D in FP64), G FP32;
     # widths that are not multiples of 4 / 32 take the general BF16 kernel
     # (unaligned G rows, k not a whole number of tiles) with the coefficient
-    # scalings in its epilogue
+    # scalings in its epilogue; the last case has a different number of modes
+    # on the two sides (the row and column coefficient vectors differ in length)
     import torch
-    r, n, rho = 64, 64, 0.95
-    _announce(f"mixed precondition flags={flags} dG={dG} dA={dA}")
-    bg = _oracle_state(dG, r, n, rho, 4, 31, "G")
-    ba = _oracle_state(dA, r, n, rho, 4, 31, "A")
-    fg = kfb.Factor(dG, r, n, rho, kfb.KFB_BF16_MIXED)
-    fa = kfb.Factor(dA, r, n, rho, kfb.KFB_BF16_MIXED)
+    rho = 0.95
+    _announce(f"mixed precondition flags={flags} dG={dG} dA={dA} ranks G {rG}+{nG} A {rA}+{nA}")
+    bg = _oracle_state(dG, rG, nG, rho, 4, 31, "G")
+    ba = _oracle_state(dA, rA, nA, rho, 4, 31, "A")
+    fg = kfb.Factor(dG, rG, nG, rho, kfb.KFB_BF16_MIXED)
+    fa = kfb.Factor(dA, rA, nA, rho, kfb.KFB_BF16_MIXED)
     UG32, UA32 = bg.U.astype(np.float32), ba.U.astype(np.float32)
     fg.load_state(_to_dev(UG32, torch.float32), _to_dev(bg.D, torch.float64), step=4)
     fa.load_state(_to_dev(UA32, torch.float32), _to_dev(ba.D, torch.float64), step=4)
